@@ -1,0 +1,259 @@
+/*
+ * dmd_stream.h -- C ABI of the MI355X (gfx950) streaming method-of-snapshots
+ * dynamic mode decomposition library (libdmdstream.so).
+ *
+ * Method: Pendergrass, Kutz, Brunton, "Streaming GPU Singular Value and
+ * Dynamic Mode Decompositions" (arXiv:1612.07875).
+ *
+ *   * A stream keeps a window of the last m+1 snapshots x_{t-m} .. x_t, each
+ *     of length n.  X is the first m of them and X' the last m (Sec. 2,
+ *     the data matrices X and X'; Algorithm 2 takes the (m+1)-column window).
+ *   * Every push computes only the new snapshot's inner products with the
+ *     window and reuses all others (Sec. 3.1, streaming method of snapshots;
+ *     Algorithm 1).  One Gram of the whole (m+1)-column window serves both
+ *     X^* X (Algorithm 1's xtx) and X^* X' (Algorithm 2's xty).
+ *   * Once the window is full the small solves run in FP64 on the GPU:
+ *     eig of X^* X -> sigma, V (Sec. 2.1); A~ = Sigma^-1 V^* X^* X' V Sigma^-1
+ *     (Eq. Atilde with U = X V Sigma^-1 never formed, Sec. 3.4);
+ *     A~ W = W Lambda (Sec. 2.2).
+ *   * On request the tall-skinny projections run on the GPU:
+ *     modes Phi = X' V Sigma^-1 W (Eq. Phi) and POD modes U = X V Sigma^-1
+ *     (Sec. 2.1, step 2).
+ *   * Complex snapshots given in compressed sparse form (sorted indices and
+ *     complex64 values) use sparse inner products; SVD and DMD are invariant
+ *     under the unitary Fourier transform, so Fourier coefficients can be
+ *     processed directly (Sec. 3.5).
+ *
+ * Readings fixed by this library where the paper is silent:
+ *   * Truncation to the r leading singular values (exact DMD of Tu et al.,
+ *     cited in Sec. 2.2).  Singular values at or below rcond * sigma_1 are
+ *     not resolvable by a Gram accumulated in FP64; only the leading
+ *     r_eff <= r are then used and calls report DMD_W_RANK.
+ *   * Conjugate transposes throughout (complex snapshots give a Hermitian Gram).
+ *   * sigma is sorted descending and V's columns are permuted alike.
+ *   * Eigenvalues are sorted by descending |lambda|, ties by ascending
+ *     arg(lambda).  Columns of V and W have unit 2-norm and their entry of
+ *     largest modulus (lowest index on ties) real and positive; Phi inherits W.
+ *
+ * Conventions of this ABI:
+ *   * Every function returns an int status: DMD_OK (0), a positive warning,
+ *     or a negative error.  No C++ exception crosses the ABI.  The message of
+ *     the calling thread's last error is returned by dmd_last_error().
+ *   * "stream" arguments are hipStream_t values passed as void* (NULL = the
+ *     null stream).  Work on one handle is serialised in call order across
+ *     all streams it is given.
+ *   * Device pointers are HIP device allocations of the current device of
+ *     the handle; host pointers are ordinary host memory.
+ *   * The library owns every device buffer it allocates (ring of snapshots,
+ *     Gram, workspaces); the caller owns all input and output buffers and
+ *     must keep inputs valid until the call's work completes
+ *     (dmd_stream_sync, or any call that returns host results).
+ *   * A handle is not thread-safe: calls on one handle must not overlap.
+ *   * Matrices are column-major.  Complex values are interleaved (re, im)
+ *     pairs: complex64 = 2 x float, complex128 = 2 x double.
+ */
+#ifndef DMD_STREAM_H
+#define DMD_STREAM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define DMD_OK              0
+#define DMD_W_RANK          1   /* fewer than r singular values resolvable; r_eff < r */
+#define DMD_E_INVAL        -1   /* bad argument (null pointer, size, alignment, index) */
+#define DMD_E_NOMEM        -2   /* device or pinned-host allocation failed */
+#define DMD_E_NOT_READY    -3   /* fewer than m+1 snapshots pushed, or no solve yet */
+#define DMD_E_NONFINITE    -4   /* a pushed snapshot had a non-finite inner product; it
+                                   was rejected and the window left unchanged */
+#define DMD_E_CONVERGENCE  -5   /* an eigensolver hit its iteration limit */
+#define DMD_E_DEVICE       -6   /* a HIP runtime call failed */
+#define DMD_E_UNSUPPORTED  -7   /* valid request not supported for this dtype/precision */
+
+/* ------------------------------------------------------------ options */
+typedef enum {
+    DMD_F32     = 0,  /* real float32 snapshots */
+    DMD_F64     = 1,  /* real float64 snapshots */
+    DMD_C64_CSR = 2   /* complex64 snapshots in sparse form (dmd_stream_push_csr) */
+} dmd_dtype_t;
+
+typedef enum {
+    DMD_PREC_DEFAULT = 0, /* FP64 for F64 data, FP32 for F32 / C64 data          */
+    DMD_PREC_FP32    = 1, /* projections in FP32 (MFMA), FP32 accumulation       */
+    DMD_PREC_BF16X3  = 2, /* projections as three BF16 MFMA products (hi*hi +
+                             hi*lo + lo*hi), FP32 accumulation                    */
+    DMD_PREC_FP64    = 3  /* projections in FP64                                  */
+} dmd_precision_t;
+
+typedef struct {
+    int32_t dtype;       /* dmd_dtype_t (default DMD_F32)                           */
+    int32_t precision;   /* dmd_precision_t for the tall-skinny projections; the
+                            per-frame inner products always accumulate in FP64 and
+                            the small solves always run in FP64                     */
+    int32_t max_nnz;     /* DMD_C64_CSR: capacity per snapshot (0 = n)              */
+    int32_t max_sweeps;  /* Jacobi sweep limit (0 = 40)                              */
+    int32_t max_qr_iter; /* Hessenberg-QR iterations per eigenvalue (0 = 60)         */
+    int32_t auto_solve;  /* 1 (default): a push into a full window also runs the
+                            small solves; 0: only dmd_stream_solve runs them        */
+    double  rcond;       /* rank cut-off relative to sigma_1 (< 0: default
+                            10 * sqrt(2^-52) ~ 1.5e-7; 0: keep all nonzero)        */
+    double  tol;         /* Jacobi stopping threshold: rotate while
+                            |a_pq| > tol * sqrt(|a_pp a_qq|) (0 = 1e-15)            */
+    int32_t reserved[8]; /* must be zero                                             */
+} dmd_opts_t;
+
+typedef struct dmd_stream dmd_stream_t;
+
+/* Fill *opts with the defaults listed above.  DMD_E_INVAL if opts is NULL. */
+int dmd_opts_init(dmd_opts_t* opts);
+
+/* ------------------------------------------------------------ lifecycle */
+
+/* Create a stream with snapshot length n, window m (X has m columns, the
+ * window holds m+1 snapshots) and truncation rank r on the current HIP device.
+ * Requires n >= 1, 2 <= m <= 256, 1 <= r <= min(m, 32); for DMD_C64_CSR also
+ * 1 <= max_nnz <= n.  opts may be NULL (defaults).  Allocates the ring of
+ * snapshots (m+2 slots of n elements: the window plus one slot being filled),
+ * the (m+2) x (m+2) FP64 Gram and the solve workspaces, all zeroed.
+ * Errors: DMD_E_INVAL, DMD_E_NOMEM, DMD_E_DEVICE.  *out is NULL on error. */
+int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t* opts,
+                      dmd_stream_t** out);
+
+/* Wait for all work of the handle, then free everything it owns.  NULL is a no-op. */
+int dmd_stream_destroy(dmd_stream_t* h);
+
+/* Wait for all work of the handle.  Returns DMD_E_NONFINITE once if pushes
+ * were rejected since the last report, else DMD_OK. */
+int dmd_stream_sync(dmd_stream_t* h);
+
+/* Empty the window (the next push starts a new one).  Stream-ordered. */
+int dmd_stream_reset(dmd_stream_t* h, void* stream);
+
+/* ------------------------------------------------------------ ingest (Sec. 3.1) */
+
+/* Append one dense snapshot (n elements of the stream's dtype, device memory,
+ * 4-byte aligned for F32, 8-byte for F64).  Enqueues on `stream`:
+ *   the copy of x into the ring, its n-length inner products with every
+ *   snapshot that stays in the window and with itself (FP64 accumulation,
+ *   fixed reduction order: bitwise reproducible), the Gram update (oldest
+ *   snapshot dropped, new row and column written), and -- when the window is
+ *   full and auto_solve is on -- the FP64 small solves.
+ * A snapshot whose inner products are not finite is rejected on the device:
+ * the window, Gram and results stay as they were and the next synchronising
+ * call returns DMD_E_NONFINITE.  Asynchronous: returns before the work runs.
+ * Errors: DMD_E_INVAL (NULL, wrong dtype, misaligned), DMD_E_DEVICE. */
+int dmd_stream_push(dmd_stream_t* h, const void* x, void* stream);
+
+/* Append one sparse complex snapshot: nnz entries, idx (int32, device) strictly
+ * increasing in [0, n), val (complex64, device).  Only for DMD_C64_CSR streams;
+ * 0 <= nnz <= max_nnz.  Index validity is checked on the device: a snapshot
+ * with unsorted or out-of-range indices is rejected like a non-finite one
+ * (DMD_E_INVAL at the next synchronising call).  Otherwise as dmd_stream_push. */
+int dmd_stream_push_csr(dmd_stream_t* h, int32_t nnz, const int32_t* idx,
+                        const void* val, void* stream);
+
+/* Append k dense snapshots at once: X_new is n x k (device, column-major,
+ * leading dimension ldx >= n), 1 <= k <= m+1.  Equivalent to k pushes in
+ * column order; the k new Gram columns come from one pass over the window
+ * (Sec. 5, updating with more than one column at a time). */
+int dmd_stream_push_block(dmd_stream_t* h, const void* X_new, int64_t ldx,
+                          int32_t k, void* stream);
+
+/* ------------------------------------------------------------ small solves (Alg. 1-2) */
+
+/* Run the FP64 small solves for the current window on `stream` (not needed
+ * when auto_solve is on). */
+int dmd_stream_solve(dmd_stream_t* h, void* stream);
+
+/* Host results of the latest solve (waits for it).  Each of lam_re, lam_im,
+ * sigma may be NULL; otherwise it receives r_eff values (sigma: the r_eff
+ * leading singular values of X).  *r_eff (may be NULL) receives the rank used.
+ * Returns DMD_OK, DMD_W_RANK (r_eff < r), DMD_E_NOT_READY (window not full or
+ * no solve yet), DMD_E_NONFINITE, DMD_E_CONVERGENCE. */
+int dmd_stream_eigs(dmd_stream_t* h, double* lam_re, double* lam_im, double* sigma,
+                    int32_t* r_eff);
+
+/* Host copies of the latest solve's matrices (waits for it).  Any pointer may
+ * be NULL.  sigma: all m singular values of X, descending.  V: m x r_eff
+ * (leading dimension ldv >= m; complex128 for DMD_C64_CSR, else double).
+ * Atilde: r_eff x r_eff (lda >= r_eff; complex128 for DMD_C64_CSR, else double).
+ * W: r_eff x r_eff complex128 (ldw >= r_eff).  Status as dmd_stream_eigs. */
+int dmd_stream_svd(dmd_stream_t* h, double* sigma, double* V, int64_t ldv, int32_t* r_eff);
+int dmd_stream_atilde(dmd_stream_t* h, double* Atilde, int64_t lda, double* W, int64_t ldw,
+                      int32_t* r_eff);
+
+/* Host copy of the Gram of the current window in window order (oldest first):
+ * G[i + j*ldg] = <x_i, x_j> = x_i^* x_j for 0 <= i, j < *ncols, where *ncols
+ * (m+1 once full) is written first.  ldg >= m+1.  complex128 for DMD_C64_CSR,
+ * else double.  Waits for the handle's work. */
+int dmd_stream_gram(dmd_stream_t* h, double* G, int64_t ldg, int32_t* ncols);
+
+/* ------------------------------------------------------------ projections (Eq. Phi, Sec. 2.1) */
+
+/* DMD modes Phi = X' V Sigma^-1 W of the latest solve into `phi` (device,
+ * n x r_eff complex, leading dimension ld >= n, column order = eigenvalue
+ * order).  complex128 for DMD_F64 streams or DMD_PREC_FP64, else complex64.
+ * For DMD_C64_CSR streams rows outside the window's union support are zero.
+ * Stream-ordered; does not wait.  DMD_E_NOT_READY if no solve was enqueued. */
+int dmd_stream_modes(dmd_stream_t* h, void* phi, int64_t ld, void* stream);
+
+/* POD modes U = X V Sigma^-1 (n x r_eff, leading dimension ld >= n; double for
+ * DMD_F64 or DMD_PREC_FP64, complex64 for DMD_C64_CSR, else float). */
+int dmd_stream_pod(dmd_stream_t* h, void* U, int64_t ld, void* stream);
+
+/* ------------------------------------------------------------ bulk Gram (Alg. 1 first step) */
+
+/* Replace the window by the k = ncols snapshots in X (device, n x k
+ * column-major, leading dimension ldx >= n, 1 <= k <= m+1, stream dtype;
+ * dense dtypes only) and compute their whole Gram at once (Algorithm 1's
+ * first step) with the MFMA Gram kernel in the stream's precision. */
+int dmd_stream_load_window(dmd_stream_t* h, const void* X, int64_t ldx, int32_t ncols,
+                           void* stream);
+
+/* Recompute the whole Gram of the current window from the snapshots held in
+ * the ring (MFMA Gram kernel, stream's precision), e.g. to compare precisions. */
+int dmd_stream_resync(dmd_stream_t* h, void* stream);
+
+/* ------------------------------------------------------------ introspection */
+
+typedef struct {
+    int64_t n;
+    int32_t m, r, dtype, precision;
+    int32_t count;          /* snapshots currently in the window */
+    int32_t r_eff;          /* rank used by the latest solve (0 if none) */
+    int32_t sweeps;         /* Jacobi sweeps of the latest solve */
+    int32_t qr_iters;       /* Hessenberg-QR iterations of the latest solve */
+    int64_t device_bytes;   /* device memory owned by the handle */
+} dmd_info_t;
+
+/* Wait for the handle's work and describe it. */
+int dmd_stream_info(dmd_stream_t* h, dmd_info_t* info);
+
+/* ------------------------------------------------------------ kernel timing */
+
+/* Process-wide per-kernel timing for diagnostics and roofline measurement.
+ * When enabled, every kernel launch of every handle is bracketed by HIP events
+ * recorded on its launch stream.  Kernel names: "gram_columns",
+ * "gram_finalize", "solve_sym", "solve_eig", "project_modes", "project_pod",
+ * "csr_gram", "csr_finalize", "csr_project", "gram_full".
+ * dmd_profile_read waits for the recorded events and returns the number of
+ * launches of `kernel` and their summed duration in milliseconds since the
+ * last dmd_profile_reset. */
+int dmd_profile_enable(int on);
+int dmd_profile_reset(void);
+int dmd_profile_read(const char* kernel, int64_t* launches, double* total_ms);
+
+/* Message of the calling thread's last error ("" if none).  Never NULL. */
+const char* dmd_last_error(void);
+
+/* Library version string. */
+const char* dmd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMD_STREAM_H */

@@ -1,0 +1,305 @@
+"""ctypes binding of libdmdstream (see include/dmd_stream.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  torch provides device buffers and streams; it is imported before
+the library is loaded so that both share one HIP runtime.  There is no
+fallback: if the library is missing or no GPU is present, calls raise.
+"""
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdmdstream.so")
+
+OK, W_RANK = 0, 1
+E_INVAL, E_NOMEM, E_NOT_READY, E_NONFINITE, E_CONVERGENCE, E_DEVICE, E_UNSUPPORTED = -1, -2, -3, -4, -5, -6, -7
+STATUS_NAMES = {
+    0: "OK", 1: "W_RANK", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_NOT_READY",
+    -4: "E_NONFINITE", -5: "E_CONVERGENCE", -6: "E_DEVICE", -7: "E_UNSUPPORTED",
+}
+
+DTYPES = {"f32": 0, "f64": 1, "c64_csr": 2}
+PRECISIONS = {"default": 0, "fp32": 1, "bf16x3": 2, "fp64": 3}
+
+
+class DMDError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("dtype", ctypes.c_int32), ("precision", ctypes.c_int32), ("max_nnz", ctypes.c_int32),
+        ("max_sweeps", ctypes.c_int32), ("max_qr_iter", ctypes.c_int32), ("auto_solve", ctypes.c_int32),
+        ("rcond", ctypes.c_double), ("tol", ctypes.c_double), ("reserved", ctypes.c_int32 * 8),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("m", ctypes.c_int32), ("r", ctypes.c_int32), ("dtype", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("count", ctypes.c_int32), ("r_eff", ctypes.c_int32),
+        ("sweeps", ctypes.c_int32), ("qr_iters", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
+    ]
+
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_DP = ctypes.POINTER(ctypes.c_double)
+_I32P = ctypes.POINTER(ctypes.c_int32)
+
+# exported symbol -> argument types (every function returns int unless noted)
+SIGNATURES = {
+    "dmd_opts_init": [ctypes.POINTER(Opts)],
+    "dmd_stream_create": [_I64, _I32, _I32, ctypes.POINTER(Opts), ctypes.POINTER(_P)],
+    "dmd_stream_destroy": [_P],
+    "dmd_stream_sync": [_P],
+    "dmd_stream_reset": [_P, _P],
+    "dmd_stream_push": [_P, _P, _P],
+    "dmd_stream_push_csr": [_P, _I32, _P, _P, _P],
+    "dmd_stream_push_block": [_P, _P, _I64, _I32, _P],
+    "dmd_stream_solve": [_P, _P],
+    "dmd_stream_eigs": [_P, _DP, _DP, _DP, _I32P],
+    "dmd_stream_svd": [_P, _DP, _DP, _I64, _I32P],
+    "dmd_stream_atilde": [_P, _DP, _I64, _DP, _I64, _I32P],
+    "dmd_stream_gram": [_P, _DP, _I64, _I32P],
+    "dmd_stream_modes": [_P, _P, _I64, _P],
+    "dmd_stream_pod": [_P, _P, _I64, _P],
+    "dmd_stream_load_window": [_P, _P, _I64, _I32, _P],
+    "dmd_stream_resync": [_P, _P],
+    "dmd_stream_info": [_P, ctypes.POINTER(Info)],
+    "dmd_profile_enable": [ctypes.c_int],
+    "dmd_profile_reset": [],
+    "dmd_profile_read": [ctypes.c_char_p, ctypes.POINTER(_I64), _DP],
+}
+STRING_FUNCS = ["dmd_last_error", "dmd_version"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the shared library once and declare its signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1612_07875_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, args in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    for name in STRING_FUNCS:
+        fn = getattr(lib, name)
+        fn.argtypes = []
+        fn.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().dmd_last_error().decode()
+
+
+def check(rc: int) -> int:
+    if rc < 0:
+        raise DMDError(rc, last_error())
+    return rc
+
+
+def profile_enable(on: bool = True) -> None:
+    check(load().dmd_profile_enable(1 if on else 0))
+
+
+def profile_reset() -> None:
+    check(load().dmd_profile_reset())
+
+
+def profile_read(kernel: str):
+    """(launches, total milliseconds) of one kernel since the last reset."""
+    cnt = ctypes.c_int64(0)
+    ms = ctypes.c_double(0.0)
+    check(load().dmd_profile_read(kernel.encode(), ctypes.byref(cnt), ctypes.byref(ms)))
+    return cnt.value, ms.value
+
+
+def _dp(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(_DP)
+
+
+def _stream_ptr(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+class Stream:
+    """One streaming-DMD window on the current GPU (see dmd_stream_create)."""
+
+    def __init__(self, n: int, m: int, r: int, dtype: str = "f32", precision: str = "default",
+                 auto_solve: bool = True, rcond: Optional[float] = None, tol: float = 0.0,
+                 max_nnz: int = 0, max_sweeps: int = 0, max_qr_iter: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libdmdstream needs a HIP GPU; none is available")
+        lib = load()
+        o = Opts()
+        check(lib.dmd_opts_init(ctypes.byref(o)))
+        o.dtype = DTYPES[dtype]
+        o.precision = PRECISIONS[precision]
+        o.max_nnz = max_nnz
+        o.max_sweeps = max_sweeps
+        o.max_qr_iter = max_qr_iter
+        o.auto_solve = 1 if auto_solve else 0
+        o.rcond = -1.0 if rcond is None else float(rcond)
+        o.tol = float(tol)
+        h = _P()
+        check(lib.dmd_stream_create(int(n), int(m), int(r), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.n, self.m, self.r = int(n), int(m), int(r)
+        self.dtype = dtype
+        self.precision = precision
+        self.elem = {"f32": torch.float32, "f64": torch.float64, "c64_csr": torch.complex64}[dtype]
+        wide = dtype == "f64" or precision == "fp64"
+        self.mode_dtype = torch.complex128 if wide else torch.complex64
+        self.pod_dtype = (torch.float64 if wide else torch.float32) if dtype != "c64_csr" else self.mode_dtype
+
+    # ---------------------------------------------------------------- lifecycle
+    def close(self):
+        if getattr(self, "_h", None):
+            load().dmd_stream_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def sync(self) -> int:
+        return check(load().dmd_stream_sync(self._h))
+
+    def reset(self, stream=None):
+        check(load().dmd_stream_reset(self._h, _stream_ptr(stream)))
+
+    def info(self) -> Info:
+        inf = Info()
+        check(load().dmd_stream_info(self._h, ctypes.byref(inf)))
+        return inf
+
+    # ---------------------------------------------------------------- ingest
+    def push(self, x: torch.Tensor, stream=None) -> int:
+        if not (x.is_cuda and x.dtype == self.elem and x.numel() == self.n and x.is_contiguous()):
+            raise ValueError(f"snapshot must be a contiguous {self.elem} CUDA tensor of {self.n} elements")
+        return check(load().dmd_stream_push(self._h, x.data_ptr(), _stream_ptr(stream)))
+
+    def push_csr(self, idx: torch.Tensor, val: torch.Tensor, stream=None) -> int:
+        if not (idx.is_cuda and idx.dtype == torch.int32 and val.is_cuda and val.dtype == torch.complex64
+                and idx.numel() == val.numel() and idx.is_contiguous() and val.is_contiguous()):
+            raise ValueError("idx must be int32 and val complex64, contiguous CUDA tensors of equal length")
+        return check(load().dmd_stream_push_csr(self._h, idx.numel(), idx.data_ptr(), val.data_ptr(),
+                                                _stream_ptr(stream)))
+
+    def push_block(self, X: torch.Tensor, stream=None) -> int:
+        """X: (k, n) tensor whose rows are snapshots (column-major n x k)."""
+        if not (X.is_cuda and X.dtype == self.elem and X.dim() == 2 and X.shape[1] == self.n
+                and X.stride(1) == 1):
+            raise ValueError("X must be a (k, n) CUDA tensor with unit stride along n")
+        return check(load().dmd_stream_push_block(self._h, X.data_ptr(), X.stride(0), X.shape[0],
+                                                  _stream_ptr(stream)))
+
+    def load_window(self, X: torch.Tensor, stream=None) -> int:
+        if not (X.is_cuda and X.dtype == self.elem and X.dim() == 2 and X.shape[1] == self.n
+                and X.stride(1) == 1):
+            raise ValueError("X must be a (k, n) CUDA tensor with unit stride along n")
+        return check(load().dmd_stream_load_window(self._h, X.data_ptr(), X.stride(0), X.shape[0],
+                                                   _stream_ptr(stream)))
+
+    def resync(self, stream=None) -> int:
+        return check(load().dmd_stream_resync(self._h, _stream_ptr(stream)))
+
+    # ---------------------------------------------------------------- small solves
+    def solve(self, stream=None) -> int:
+        return check(load().dmd_stream_solve(self._h, _stream_ptr(stream)))
+
+    def eigs(self):
+        """(lambda complex128[r_eff], sigma float64[r_eff], status)."""
+        re = np.zeros(self.r)
+        im = np.zeros(self.r)
+        sg = np.zeros(self.r)
+        k = ctypes.c_int32(0)
+        rc = check(load().dmd_stream_eigs(self._h, _dp(re), _dp(im), _dp(sg), ctypes.byref(k)))
+        k = k.value
+        return re[:k] + 1j * im[:k], sg[:k], rc
+
+    def svd(self):
+        """(sigma float64[m], V[m, r_eff] (complex128 for sparse streams), status)."""
+        cw = 2 if self.dtype == "c64_csr" else 1
+        sg = np.zeros(self.m)
+        V = np.zeros((self.r, self.m * cw))
+        k = ctypes.c_int32(0)
+        rc = check(load().dmd_stream_svd(self._h, _dp(sg), _dp(V), self.m, ctypes.byref(k)))
+        k = k.value
+        V = V[:k]
+        V = (V[:, 0::2] + 1j * V[:, 1::2]) if cw == 2 else V
+        return sg, np.ascontiguousarray(V.T), rc
+
+    def atilde(self):
+        """(Atilde[r_eff, r_eff], W[r_eff, r_eff] complex128, status)."""
+        cw = 2 if self.dtype == "c64_csr" else 1
+        At = np.zeros((self.r, self.r * cw))
+        W = np.zeros((self.r, self.r * 2))
+        k = ctypes.c_int32(0)
+        rc = check(load().dmd_stream_atilde(self._h, _dp(At), self.r, _dp(W), self.r, ctypes.byref(k)))
+        k = k.value
+        At = At[:k, : k * cw]
+        At = (At[:, 0::2] + 1j * At[:, 1::2]) if cw == 2 else At
+        W = W[:k, : 2 * k]
+        W = W[:, 0::2] + 1j * W[:, 1::2]
+        return np.ascontiguousarray(At.T), np.ascontiguousarray(W.T), rc
+
+    def gram(self) -> np.ndarray:
+        """Gram of the current window in window order (count x count)."""
+        cw = 2 if self.dtype == "c64_csr" else 1
+        ld = self.m + 1
+        G = np.zeros((ld, ld * cw))
+        k = ctypes.c_int32(0)
+        check(load().dmd_stream_gram(self._h, _dp(G), ld, ctypes.byref(k)))
+        k = k.value
+        G = G[:k, : k * cw]
+        G = (G[:, 0::2] + 1j * G[:, 1::2]) if cw == 2 else G
+        return np.ascontiguousarray(G.T)
+
+    # ---------------------------------------------------------------- projections
+    def modes(self, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """Phi (n x r) on the device; the first r_eff columns are written."""
+        if out is None:
+            out = torch.zeros((self.r, self.n), dtype=self.mode_dtype, device="cuda").T
+        self._check_out(out, self.mode_dtype)
+        check(load().dmd_stream_modes(self._h, out.data_ptr(), out.stride(1), _stream_ptr(stream)))
+        return out
+
+    def pod(self, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """U (n x r) on the device; the first r_eff columns are written."""
+        if out is None:
+            out = torch.zeros((self.r, self.n), dtype=self.pod_dtype, device="cuda").T
+        self._check_out(out, self.pod_dtype)
+        check(load().dmd_stream_pod(self._h, out.data_ptr(), out.stride(1), _stream_ptr(stream)))
+        return out
+
+    def _check_out(self, out: torch.Tensor, dt):
+        if not (out.is_cuda and out.dtype == dt and out.dim() == 2 and out.shape[0] == self.n
+                and out.shape[1] >= self.r and out.stride(0) == 1):
+            raise ValueError(f"output must be an (n, >= r) column-major CUDA tensor of {dt}")

@@ -1,0 +1,139 @@
+// Internal definitions shared by the HIP kernels and the C-ABI runtime of
+// libdmdstream.  Not part of the public interface (see include/dmd_stream.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dmd {
+
+// Device-resident state of one stream.  It lives at the start of the results
+// block so that a single device-to-host copy returns the state together with
+// sigma and lambda.  Kernels read and update it, so the host can enqueue a
+// whole frame without knowing whether earlier pushes were accepted.
+//
+// The ring holds slots = m+2 snapshots: the window (count <= m+1 snapshots
+// starting at physical slot `oldest`) and one spare slot that the next push
+// fills.  A rejected push therefore never touches the window.
+struct DevState {
+    int32_t oldest;             // physical slot of the oldest window snapshot
+    int32_t count;              // snapshots in the window (0 .. m+1)
+    int32_t rejected_nonfinite; // pushes rejected for non-finite inner products
+    int32_t rejected_index;     // sparse pushes rejected for bad indices
+    int32_t solve_status;       // status of the latest solve (DMD_* code)
+    int32_t r_eff;              // rank used by the latest solve
+    int32_t sweeps;             // Jacobi sweeps of the latest solve
+    int32_t qr_iters;           // Hessenberg-QR iterations of the latest solve
+    int32_t solves;             // solves run on a full window
+    int32_t pushes;             // accepted pushes
+    int32_t pad[6];
+};
+static_assert(sizeof(DevState) == 64, "DevState must stay 64 bytes");
+
+// Layout of the results block (device and pinned-host mirror).
+struct ResultsLayout {
+    size_t sigma_off;  // m doubles
+    size_t lam_off;    // 2 r doubles (interleaved complex)
+    size_t bytes;
+    static ResultsLayout make(int m, int r) {
+        ResultsLayout L;
+        L.sigma_off = sizeof(DevState);
+        L.lam_off = L.sigma_off + sizeof(double) * (size_t)m;
+        L.bytes = L.lam_off + sizeof(double) * 2 * (size_t)r;
+        return L;
+    }
+};
+
+// Physical slot of logical window column l (0 = oldest).
+__host__ __device__ inline int slot_of(int oldest, int l, int slots) {
+    int s = oldest + l;
+    return s >= slots ? s - slots : s;
+}
+
+// Status codes (mirror of the public header, usable in device code).
+enum : int32_t {
+    ST_OK = 0, ST_W_RANK = 1, ST_E_INVAL = -1, ST_E_NOT_READY = -3,
+    ST_E_NONFINITE = -4, ST_E_CONVERGENCE = -5
+};
+
+// Maximum sizes supported by the kernels.
+constexpr int kMaxM = 256;   // window columns
+constexpr int kMaxR = 64;    // truncation rank
+
+// ------------------------------------------------------------------ launchers
+// Each returns hipSuccess or the launch error.  All are asynchronous on `s`.
+
+// Dense inner products of one new snapshot with the kept window columns
+// (ingest fused), per-workgroup partial sums, then the fixed-order reduction
+// and Gram update.  T = float or double.
+template <typename T>
+hipError_t launch_gram_columns(const T* x, T* ring, int64_t ld, int64_t n, int m,
+                               double* partials, int nblk_cap, const DevState* st,
+                               int* nblk_used, hipStream_t s);
+hipError_t launch_gram_finalize(double* G, const double* partials, int nblk, int m,
+                                DevState* st, hipStream_t s);
+int gram_push_blocks(int64_t n, int elem_bytes);
+
+// Sparse complex snapshot: ingest into the CSR ring and Hermitian inner
+// products through a dense scatter buffer.
+hipError_t launch_csr_push(const int32_t* idx, const float2* val, int nnz,
+                           int32_t* ring_idx, float2* ring_val, int32_t* ring_nnz,
+                           int max_nnz, int64_t n, int m, float2* scatter,
+                           double* G, double* partials, DevState* st, hipStream_t s);
+
+// FP64 small solves for the current window: Jacobi eig of X^*X, sigma, V,
+// A~, eig(A~) by Hessenberg-QR, coefficient matrices for the projections.
+struct SolveArgs {
+    DevState* st;
+    const double* G;       // (m+2)^2 physical Gram (complex: interleaved)
+    int m, r, slots;
+    int cplx;              // 1 for the Hermitian (sparse complex) path
+    double rcond, tol;
+    int max_sweeps, max_qr_iter;
+    double* sigma;         // results block: m sigmas
+    double* lam;           // results block: 2 r doubles
+    double* V;             // m x r (complex: interleaved), canonical columns
+    double* At;            // r x r (complex: interleaved)
+    double* W;             // r x r complex
+    double* work;          // global scratch for m > 64: A and V (2 m^2 [x2 complex])
+    void* Bphi;            // m x 2r coefficients of Phi (row-major, data precision)
+    void* Bpod;            // m x r (real) or m x 2r (complex) coefficients of U
+    int coef_f64;          // 1: coefficients stored as double, 0: float
+    char* res_block;       // device results block (state, sigma, lambda)
+    char* res_host;        // device address of its pinned host mirror
+    int res_bytes;         // size of the results block
+};
+hipError_t launch_solve_sym(const SolveArgs& a, hipStream_t s);
+hipError_t launch_solve_eig(const SolveArgs& a, hipStream_t s);
+
+// Tall-skinny projection out = X_sub * B for the ring's logical columns
+// first .. first+m-1 (X' for first = 1, X for first = 0).
+struct ProjectArgs {
+    const DevState* st;
+    const void* ring;      // dense ring (float or double)
+    int64_t ld, n;
+    int m, slots, first;
+    const void* B;         // m x kcols row-major coefficients
+    int kmax;              // allocated columns of B (row stride)
+    int cplx_out;          // 1: kcols = 2 r_eff interleaved complex columns
+    void* out;
+    int64_t ldo;
+    int elem_f64;          // ring elements are double (else float)
+    int coef_f64;          // coefficients, accumulation and output in double
+    int precision;         // DMD_PREC_* used for float data
+};
+hipError_t launch_project(const ProjectArgs& a, hipStream_t s);
+
+// Sparse projection: Phi = X'_sparse * C into a dense n x r complex64 output.
+hipError_t launch_csr_project(const DevState* st, const int32_t* ring_idx,
+                              const float2* ring_val, const int32_t* ring_nnz,
+                              int max_nnz, int m, int slots, int first,
+                              const float2* B, int kmax, int cplx_rows,
+                              float2* out, int64_t ldo, int64_t n, hipStream_t s);
+
+// Whole Gram of k dense columns (MFMA): G_sub = X^* X for logical columns.
+hipError_t launch_gram_full(const void* ring, int64_t ld, int64_t n, int m, int slots,
+                            int elem_f64, int precision, double* G, DevState* st,
+                            double* work, hipStream_t s);
+
+}  // namespace dmd

@@ -1,0 +1,645 @@
+// C-ABI runtime of libdmdstream: stream handles, device memory, argument
+// checks and the ordering of kernels for one frame.  See include/dmd_stream.h
+// for the contract of every entry point.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dmd_internal.h"
+#include "dmd_stream.h"
+
+#define DMD_API extern "C" __attribute__((visibility("default")))
+
+using dmd::DevState;
+using dmd::ResultsLayout;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(DMD_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                                         \
+    do {                                                      \
+        hipError_t _e = (call);                               \
+        if (_e != hipSuccess) return hip_fail(_e, #call);     \
+    } while (0)
+
+struct DeviceGuard {
+    int prev = -1;
+    bool changed = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) {
+            changed = hipSetDevice(dev) == hipSuccess;
+        }
+    }
+    ~DeviceGuard() {
+        if (changed) (void)hipSetDevice(prev);
+    }
+};
+
+// Optional per-kernel timing: HIP events recorded on the launch stream right
+// before and after each kernel, resolved when read.
+struct ProfRec {
+    const char* name;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+std::vector<hipEvent_t> g_prof_pool;
+
+hipEvent_t prof_event() {
+    if (!g_prof_pool.empty()) {
+        hipEvent_t e = g_prof_pool.back();
+        g_prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+// Runs `launch` (a callable returning hipError_t) bracketed by events when profiling.
+template <typename F>
+hipError_t timed(const char* name, hipStream_t s, F&& launch) {
+    if (!g_prof_on) return launch();
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    ProfRec r{name, prof_event(), prof_event()};
+    (void)hipEventRecord(r.a, s);
+    hipError_t e = launch();
+    (void)hipEventRecord(r.b, s);
+    g_prof.push_back(r);
+    return e;
+}
+
+}  // namespace
+
+struct dmd_stream {
+    int64_t n = 0, ld = 0;
+    int32_t m = 0, r = 0, slots = 0;
+    dmd_opts_t opts{};
+    int device = 0;
+    int elem_bytes = 4;     // dense ring element size
+    bool cplx = false;      // sparse complex path
+    bool coef_f64 = false;  // projection coefficients and accumulation in double
+
+    void* ring = nullptr;       // dense: slots x ld elements
+    int32_t* ring_idx = nullptr;  // sparse: slots x max_nnz indices
+    float2* ring_val = nullptr;   // sparse: slots x max_nnz values
+    int32_t* ring_nnz = nullptr;  // sparse: slots counts
+    float2* scatter = nullptr;    // sparse: n dense scratch (kept zero)
+    int max_nnz = 0;
+
+    double* G = nullptr;
+    double* partials = nullptr;
+    int nblk_cap = 0;
+    char* res_dev = nullptr;
+    char* res_host = nullptr;   // pinned, mapped
+    char* res_host_dev = nullptr;
+    ResultsLayout L{};
+    double* V = nullptr;
+    double* At = nullptr;
+    double* W = nullptr;
+    double* work = nullptr;
+    void* Bphi = nullptr;
+    void* Bpod = nullptr;
+
+    hipEvent_t ev_last = nullptr;
+    hipEvent_t ev_solved = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool has_last = false;
+    bool solve_enqueued = false;
+    int32_t reported_nonfinite = 0;
+    int32_t reported_index = 0;
+    int64_t device_bytes = 0;
+};
+
+namespace {
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Order the handle's work across streams: a call on a new stream first waits
+// for everything enqueued before it.
+hipError_t begin(dmd_stream* h, hipStream_t s) {
+    if (h->has_last && h->last_stream != s) return hipStreamWaitEvent(s, h->ev_last, 0);
+    return hipSuccess;
+}
+hipError_t end(dmd_stream* h, hipStream_t s) {
+    h->last_stream = s;
+    h->has_last = true;
+    return hipEventRecord(h->ev_last, s);
+}
+
+template <typename P>
+int dev_alloc(dmd_stream* h, P** p, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) return fail(DMD_E_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    e = hipMemset(q, 0, bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMemset");
+    *p = reinterpret_cast<P*>(q);
+    h->device_bytes += (int64_t)bytes;
+    return DMD_OK;
+}
+
+void free_all(dmd_stream* h) {
+    void* bufs[] = {h->ring, h->ring_idx, h->ring_val, h->ring_nnz, h->scatter, h->G, h->partials,
+                    h->res_dev, h->V, h->At, h->W, h->work, h->Bphi, h->Bpod};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    if (h->res_host) (void)hipHostFree(h->res_host);
+    if (h->ev_last) (void)hipEventDestroy(h->ev_last);
+    if (h->ev_solved) (void)hipEventDestroy(h->ev_solved);
+}
+
+int check_handle(dmd_stream* h) {
+    if (!h) return fail(DMD_E_INVAL, "null handle");
+    return DMD_OK;
+}
+
+const DevState& host_state(const dmd_stream* h) {
+    return *reinterpret_cast<const DevState*>(h->res_host);
+}
+
+int enqueue_solve(dmd_stream* h, hipStream_t s) {
+    dmd::SolveArgs a{};
+    a.st = reinterpret_cast<DevState*>(h->res_dev);
+    a.G = h->G;
+    a.m = h->m;
+    a.r = h->r;
+    a.slots = h->slots;
+    a.cplx = h->cplx ? 1 : 0;
+    a.rcond = h->opts.rcond;
+    a.tol = h->opts.tol;
+    a.max_sweeps = h->opts.max_sweeps;
+    a.max_qr_iter = h->opts.max_qr_iter;
+    a.sigma = reinterpret_cast<double*>(h->res_dev + h->L.sigma_off);
+    a.lam = reinterpret_cast<double*>(h->res_dev + h->L.lam_off);
+    a.V = h->V;
+    a.At = h->At;
+    a.W = h->W;
+    a.work = h->work;
+    a.Bphi = h->Bphi;
+    a.Bpod = h->Bpod;
+    a.coef_f64 = h->coef_f64 ? 1 : 0;
+    a.res_block = h->res_dev;
+    a.res_host = h->res_host_dev;
+    a.res_bytes = (int)h->L.bytes;
+    HIP_TRY(timed("solve_sym", s, [&] { return dmd::launch_solve_sym(a, s); }));
+    HIP_TRY(timed("solve_eig", s, [&] { return dmd::launch_solve_eig(a, s); }));
+    HIP_TRY(hipEventRecord(h->ev_solved, s));
+    h->solve_enqueued = true;
+    return DMD_OK;
+}
+
+int wait_solved(dmd_stream* h) {
+    if (!h->solve_enqueued) return fail(DMD_E_NOT_READY, "no solve has been enqueued");
+    HIP_TRY(hipEventSynchronize(h->ev_solved));
+    return DMD_OK;
+}
+
+// Status of the latest published solve, plus one-shot rejection reports.
+int solve_status(dmd_stream* h) {
+    const DevState& st = host_state(h);
+    if (st.rejected_nonfinite > h->reported_nonfinite) {
+        h->reported_nonfinite = st.rejected_nonfinite;
+        return fail(DMD_E_NONFINITE, "%d snapshot(s) rejected: non-finite inner products", st.rejected_nonfinite);
+    }
+    if (st.rejected_index > h->reported_index) {
+        h->reported_index = st.rejected_index;
+        return fail(DMD_E_INVAL, "%d sparse snapshot(s) rejected: indices not strictly increasing in [0, n)",
+                    st.rejected_index);
+    }
+    switch (st.solve_status) {
+        case dmd::ST_E_NOT_READY: return fail(DMD_E_NOT_READY, "window not full (%d of %d snapshots)", st.count, h->m + 1);
+        case dmd::ST_E_CONVERGENCE: return fail(DMD_E_CONVERGENCE, "eigensolver did not converge");
+        case dmd::ST_W_RANK: return DMD_W_RANK;
+        default: return DMD_OK;
+    }
+}
+
+int read_state(dmd_stream* h, DevState* out) {
+    if (h->has_last) HIP_TRY(hipEventSynchronize(h->ev_last));
+    HIP_TRY(hipMemcpy(out, h->res_dev, sizeof(DevState), hipMemcpyDeviceToHost));
+    return DMD_OK;
+}
+
+}  // namespace
+
+DMD_API int dmd_opts_init(dmd_opts_t* o) {
+    if (!o) return fail(DMD_E_INVAL, "null opts");
+    std::memset(o, 0, sizeof(*o));
+    o->dtype = DMD_F32;
+    o->precision = DMD_PREC_DEFAULT;
+    o->max_nnz = 0;
+    o->max_sweeps = 40;
+    o->max_qr_iter = 60;
+    o->auto_solve = 1;
+    o->rcond = -1.0;
+    o->tol = 0.0;
+    return DMD_OK;
+}
+
+DMD_API const char* dmd_last_error(void) { return g_err.c_str(); }
+
+DMD_API const char* dmd_version(void) { return "dmdstream 0.1 (gfx950)"; }
+
+DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t* opts,
+                              dmd_stream_t** out) {
+    if (!out) return fail(DMD_E_INVAL, "null output pointer");
+    *out = nullptr;
+    dmd_opts_t o;
+    dmd_opts_init(&o);
+    if (opts) {
+        o = *opts;
+        for (int i = 0; i < 8; ++i)
+            if (o.reserved[i] != 0) return fail(DMD_E_INVAL, "opts.reserved must be zero");
+        if (o.max_sweeps == 0) o.max_sweeps = 40;
+        if (o.max_qr_iter == 0) o.max_qr_iter = 60;
+    }
+    if (o.rcond < 0.0) o.rcond = 10.0 * 1.4901161193847656e-08;  // 10 sqrt(2^-52)
+    if (o.tol <= 0.0) o.tol = 1e-15;
+    if (n < 1) return fail(DMD_E_INVAL, "n must be >= 1 (got %lld)", (long long)n);
+    if (m < 2 || m > dmd::kMaxM) return fail(DMD_E_INVAL, "m must be in [2, %d] (got %d)", dmd::kMaxM, m);
+    if (r < 1 || r > m || r > 32) return fail(DMD_E_INVAL, "r must be in [1, min(m, 32)] (got %d)", r);
+    if (o.dtype != DMD_F32 && o.dtype != DMD_F64 && o.dtype != DMD_C64_CSR)
+        return fail(DMD_E_INVAL, "unknown dtype %d", o.dtype);
+    if (o.precision < DMD_PREC_DEFAULT || o.precision > DMD_PREC_FP64)
+        return fail(DMD_E_INVAL, "unknown precision %d", o.precision);
+    if (o.max_sweeps < 1 || o.max_qr_iter < 1) return fail(DMD_E_INVAL, "iteration limits must be positive");
+    if (o.auto_solve != 0 && o.auto_solve != 1) return fail(DMD_E_INVAL, "auto_solve must be 0 or 1");
+    if (o.dtype == DMD_C64_CSR) {
+        if (o.max_nnz == 0) o.max_nnz = (int32_t)(n < INT32_MAX ? n : INT32_MAX);
+        if (o.max_nnz < 1 || o.max_nnz > n) return fail(DMD_E_INVAL, "max_nnz must be in [1, n]");
+        if (n > INT32_MAX) return fail(DMD_E_INVAL, "sparse streams need n <= 2^31-1");
+        return fail(DMD_E_UNSUPPORTED, "sparse complex streams are not available in this build");
+    }
+    if (o.precision == DMD_PREC_BF16X3)
+        return fail(DMD_E_UNSUPPORTED, "BF16X3 projections are not available in this build");
+
+    dmd_stream* h = new (std::nothrow) dmd_stream();
+    if (!h) return fail(DMD_E_NOMEM, "host allocation failed");
+    h->n = n;
+    h->m = m;
+    h->r = r;
+    h->slots = m + 2;
+    h->opts = o;
+    h->cplx = (o.dtype == DMD_C64_CSR);
+    h->elem_bytes = (o.dtype == DMD_F64) ? 8 : 4;
+    h->coef_f64 = (o.dtype == DMD_F64) || (o.precision == DMD_PREC_FP64);
+    h->ld = (n + 63) / 64 * 64;
+    h->L = ResultsLayout::make(m, r);
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return fail(DMD_E_DEVICE, "no HIP device");
+    }
+
+    int rc = DMD_OK;
+    const int cw = h->cplx ? 2 : 1;
+    const int M = m + (m & 1);
+    h->nblk_cap = dmd::gram_push_blocks(n, h->elem_bytes);
+    const size_t coef = h->coef_f64 ? 8 : 4;
+#define ALLOC(p, bytes)                                  \
+    if (rc == DMD_OK) rc = dev_alloc(h, &(p), (bytes));
+    ALLOC(h->ring, (size_t)h->slots * h->ld * h->elem_bytes);
+    ALLOC(h->G, sizeof(double) * cw * h->slots * h->slots);
+    ALLOC(h->partials, sizeof(double) * cw * (size_t)(m + 2) * h->nblk_cap);
+    ALLOC(h->res_dev, h->L.bytes);
+    ALLOC(h->V, sizeof(double) * cw * (size_t)m * r);
+    ALLOC(h->At, sizeof(double) * cw * (size_t)r * r);
+    ALLOC(h->W, sizeof(double) * 2 * (size_t)r * r);
+    ALLOC(h->work, sizeof(double) * cw * 2 * (size_t)M * M);
+    ALLOC(h->Bphi, coef * 2 * (size_t)m * r);
+    ALLOC(h->Bpod, coef * cw * (size_t)m * r);
+#undef ALLOC
+    if (rc == DMD_OK) {
+        hipError_t e = hipHostMalloc((void**)&h->res_host, h->L.bytes, hipHostMallocMapped | hipHostMallocCoherent);
+        if (e != hipSuccess) rc = fail(DMD_E_NOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+    }
+    if (rc == DMD_OK) {
+        std::memset(h->res_host, 0, h->L.bytes);
+        hipError_t e = hipHostGetDevicePointer((void**)&h->res_host_dev, h->res_host, 0);
+        if (e != hipSuccess) rc = hip_fail(e, "hipHostGetDevicePointer");
+    }
+    if (rc == DMD_OK) {
+        DevState init{};
+        init.solve_status = dmd::ST_E_NOT_READY;
+        std::memcpy(h->res_host, &init, sizeof(init));
+        hipError_t e = hipMemcpy(h->res_dev, &init, sizeof(init), hipMemcpyHostToDevice);
+        if (e != hipSuccess) rc = hip_fail(e, "hipMemcpy(state)");
+    }
+    if (rc == DMD_OK) {
+        hipError_t e = hipEventCreateWithFlags(&h->ev_last, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_solved, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) rc = hip_fail(e, "event/sync");
+    }
+    if (rc != DMD_OK) {
+        std::string msg = g_err;
+        free_all(h);
+        delete h;
+        g_err = msg;
+        return rc;
+    }
+    *out = h;
+    g_err.clear();
+    return DMD_OK;
+}
+
+DMD_API int dmd_stream_destroy(dmd_stream_t* h) {
+    if (!h) return DMD_OK;
+    DeviceGuard g(h->device);
+    if (h->has_last) (void)hipEventSynchronize(h->ev_last);
+    free_all(h);
+    delete h;
+    return DMD_OK;
+}
+
+DMD_API int dmd_stream_sync(dmd_stream_t* h) {
+    if (int rc = check_handle(h)) return rc;
+    DeviceGuard g(h->device);
+    DevState st;
+    if (int rc = read_state(h, &st)) return rc;
+    if (st.rejected_nonfinite > h->reported_nonfinite) {
+        h->reported_nonfinite = st.rejected_nonfinite;
+        return fail(DMD_E_NONFINITE, "%d snapshot(s) rejected: non-finite inner products", st.rejected_nonfinite);
+    }
+    if (st.rejected_index > h->reported_index) {
+        h->reported_index = st.rejected_index;
+        return fail(DMD_E_INVAL, "%d sparse snapshot(s) rejected: bad indices", st.rejected_index);
+    }
+    return DMD_OK;
+}
+
+namespace dmd {
+__global__ void k_reset_state(DevState* st) {
+    st->count = 0;
+    st->oldest = 0;
+    st->solve_status = ST_E_NOT_READY;
+    st->r_eff = 0;
+}
+}  // namespace dmd
+
+DMD_API int dmd_stream_reset(dmd_stream_t* h, void* stream) {
+    if (int rc = check_handle(h)) return rc;
+    DeviceGuard g(h->device);
+    hipStream_t s = as_stream(stream);
+    HIP_TRY(begin(h, s));
+    hipLaunchKernelGGL(dmd::k_reset_state, dim3(1), dim3(1), 0, s, reinterpret_cast<DevState*>(h->res_dev));
+    HIP_TRY(hipGetLastError());
+    h->solve_enqueued = false;
+    HIP_TRY(end(h, s));
+    return DMD_OK;
+}
+
+DMD_API int dmd_stream_push(dmd_stream_t* h, const void* x, void* stream) {
+    if (int rc = check_handle(h)) return rc;
+    if (!x) return fail(DMD_E_INVAL, "null snapshot");
+    if (h->cplx) return fail(DMD_E_INVAL, "sparse stream: use dmd_stream_push_csr");
+    if ((uintptr_t)x % h->elem_bytes) return fail(DMD_E_INVAL, "snapshot not %d-byte aligned", h->elem_bytes);
+    DeviceGuard g(h->device);
+    hipStream_t s = as_stream(stream);
+    HIP_TRY(begin(h, s));
+    DevState* st = reinterpret_cast<DevState*>(h->res_dev);
+    int nblk = 0;
+    hipError_t e = timed("gram_columns", s, [&] {
+        if (h->elem_bytes == 8)
+            return dmd::launch_gram_columns<double>(static_cast<const double*>(x), static_cast<double*>(h->ring),
+                                                    h->ld, h->n, h->m, h->partials, h->nblk_cap, st, &nblk, s);
+        return dmd::launch_gram_columns<float>(static_cast<const float*>(x), static_cast<float*>(h->ring), h->ld,
+                                               h->n, h->m, h->partials, h->nblk_cap, st, &nblk, s);
+    });
+    if (e == hipSuccess)
+        e = timed("gram_finalize", s, [&] { return dmd::launch_gram_finalize(h->G, h->partials, nblk, h->m, st, s); });
+    if (e != hipSuccess) return hip_fail(e, "gram push launch");
+    if (h->opts.auto_solve)
+        if (int rc = enqueue_solve(h, s)) return rc;
+    HIP_TRY(end(h, s));
+    return DMD_OK;
+}
+
+DMD_API int dmd_stream_push_csr(dmd_stream_t* h, int32_t nnz, const int32_t* idx, const void* val,
+                                void* stream) {
+    if (int rc = check_handle(h)) return rc;
+    (void)nnz; (void)idx; (void)val; (void)stream;
+    return fail(DMD_E_UNSUPPORTED, "sparse complex streams are not available in this build");
+}
+
+DMD_API int dmd_stream_push_block(dmd_stream_t* h, const void* X_new, int64_t ldx, int32_t k,
+                                  void* stream) {
+    if (int rc = check_handle(h)) return rc;
+    (void)X_new; (void)ldx; (void)k; (void)stream;
+    return fail(DMD_E_UNSUPPORTED, "block pushes are not available in this build");
+}
+
+DMD_API int dmd_stream_solve(dmd_stream_t* h, void* stream) {
+    if (int rc = check_handle(h)) return rc;
+    DeviceGuard g(h->device);
+    hipStream_t s = as_stream(stream);
+    HIP_TRY(begin(h, s));
+    if (int rc = enqueue_solve(h, s)) return rc;
+    HIP_TRY(end(h, s));
+    return DMD_OK;
+}
+
+DMD_API int dmd_stream_eigs(dmd_stream_t* h, double* lam_re, double* lam_im, double* sigma,
+                            int32_t* r_eff) {
+    if (int rc = check_handle(h)) return rc;
+    DeviceGuard g(h->device);
+    if (int rc = wait_solved(h)) return rc;
+    const DevState& st = host_state(h);
+    const int k = st.solve_status == dmd::ST_E_NOT_READY ? 0 : st.r_eff;
+    if (r_eff) *r_eff = k;
+    const double* sig = reinterpret_cast<const double*>(h->res_host + h->L.sigma_off);
+    const double* lam = reinterpret_cast<const double*>(h->res_host + h->L.lam_off);
+    for (int i = 0; i < k; ++i) {
+        if (lam_re) lam_re[i] = lam[2 * i];
+        if (lam_im) lam_im[i] = lam[2 * i + 1];
+        if (sigma) sigma[i] = sig[i];
+    }
+    return solve_status(h);
+}
+
+DMD_API int dmd_stream_svd(dmd_stream_t* h, double* sigma, double* V, int64_t ldv, int32_t* r_eff) {
+    if (int rc = check_handle(h)) return rc;
+    if (V && ldv < h->m) return fail(DMD_E_INVAL, "ldv < m");
+    DeviceGuard g(h->device);
+    if (int rc = wait_solved(h)) return rc;
+    const DevState& st = host_state(h);
+    const int k = st.solve_status == dmd::ST_E_NOT_READY ? 0 : st.r_eff;
+    if (r_eff) *r_eff = k;
+    if (sigma && k > 0) std::memcpy(sigma, h->res_host + h->L.sigma_off, sizeof(double) * h->m);
+    if (V && k > 0) {
+        const int cw = h->cplx ? 2 : 1;
+        HIP_TRY(hipMemcpy2D(V, sizeof(double) * cw * ldv, h->V, sizeof(double) * cw * h->m,
+                            sizeof(double) * cw * h->m, k, hipMemcpyDeviceToHost));
+    }
+    return solve_status(h);
+}
+
+DMD_API int dmd_stream_atilde(dmd_stream_t* h, double* Atilde, int64_t lda, double* W, int64_t ldw,
+                              int32_t* r_eff) {
+    if (int rc = check_handle(h)) return rc;
+    DeviceGuard g(h->device);
+    if (int rc = wait_solved(h)) return rc;
+    const DevState& st = host_state(h);
+    const int k = st.solve_status == dmd::ST_E_NOT_READY ? 0 : st.r_eff;
+    if (r_eff) *r_eff = k;
+    if ((Atilde && lda < k) || (W && ldw < k)) return fail(DMD_E_INVAL, "leading dimension < r_eff");
+    const int cw = h->cplx ? 2 : 1;
+    if (Atilde && k > 0)
+        HIP_TRY(hipMemcpy2D(Atilde, sizeof(double) * cw * lda, h->At, sizeof(double) * cw * k,
+                            sizeof(double) * cw * k, k, hipMemcpyDeviceToHost));
+    if (W && k > 0)
+        HIP_TRY(hipMemcpy2D(W, sizeof(double) * 2 * ldw, h->W, sizeof(double) * 2 * k, sizeof(double) * 2 * k, k,
+                            hipMemcpyDeviceToHost));
+    return solve_status(h);
+}
+
+DMD_API int dmd_stream_gram(dmd_stream_t* h, double* G, int64_t ldg, int32_t* ncols) {
+    if (int rc = check_handle(h)) return rc;
+    if (!G || ldg < h->m + 1) return fail(DMD_E_INVAL, "null G or ldg < m+1");
+    DeviceGuard g(h->device);
+    DevState st;
+    if (int rc = read_state(h, &st)) return rc;
+    const int cw = h->cplx ? 2 : 1;
+    const size_t cnt = (size_t)cw * h->slots * h->slots;
+    double* tmp = new (std::nothrow) double[cnt];
+    if (!tmp) return fail(DMD_E_NOMEM, "host allocation failed");
+    hipError_t e = hipMemcpy(tmp, h->G, sizeof(double) * cnt, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        delete[] tmp;
+        return hip_fail(e, "hipMemcpy(G)");
+    }
+    if (ncols) *ncols = st.count;
+    for (int j = 0; j < st.count; ++j)
+        for (int i = 0; i < st.count; ++i) {
+            const int si = dmd::slot_of(st.oldest, i, h->slots), sj = dmd::slot_of(st.oldest, j, h->slots);
+            for (int c = 0; c < cw; ++c) G[cw * (i + j * ldg) + c] = tmp[cw * (si + (size_t)sj * h->slots) + c];
+        }
+    delete[] tmp;
+    return DMD_OK;
+}
+
+static int project(dmd_stream_t* h, void* out, int64_t ld, void* stream, bool modes) {
+    if (int rc = check_handle(h)) return rc;
+    if (!out) return fail(DMD_E_INVAL, "null output");
+    if (ld < h->n) return fail(DMD_E_INVAL, "ld < n");
+    if (!h->solve_enqueued) return fail(DMD_E_NOT_READY, "no solve has been enqueued");
+    DeviceGuard g(h->device);
+    hipStream_t s = as_stream(stream);
+    HIP_TRY(begin(h, s));
+    dmd::ProjectArgs a{};
+    a.st = reinterpret_cast<const DevState*>(h->res_dev);
+    a.ring = h->ring;
+    a.ld = h->ld;
+    a.n = h->n;
+    a.m = h->m;
+    a.slots = h->slots;
+    a.first = modes ? 1 : 0;
+    a.B = modes ? h->Bphi : h->Bpod;
+    a.kmax = h->r;
+    a.cplx_out = modes ? 1 : 0;
+    a.out = out;
+    a.ldo = ld;
+    a.elem_f64 = h->elem_bytes == 8;
+    a.coef_f64 = h->coef_f64;
+    a.precision = h->opts.precision;
+    HIP_TRY(timed(modes ? "project_modes" : "project_pod", s, [&] { return dmd::launch_project(a, s); }));
+    HIP_TRY(end(h, s));
+    return DMD_OK;
+}
+
+DMD_API int dmd_stream_modes(dmd_stream_t* h, void* phi, int64_t ld, void* stream) {
+    return project(h, phi, ld, stream, true);
+}
+
+DMD_API int dmd_stream_pod(dmd_stream_t* h, void* U, int64_t ld, void* stream) {
+    return project(h, U, ld, stream, false);
+}
+
+DMD_API int dmd_stream_load_window(dmd_stream_t* h, const void* X, int64_t ldx, int32_t ncols, void* stream) {
+    if (int rc = check_handle(h)) return rc;
+    (void)X; (void)ldx; (void)ncols; (void)stream;
+    return fail(DMD_E_UNSUPPORTED, "bulk window load is not available in this build");
+}
+
+DMD_API int dmd_stream_resync(dmd_stream_t* h, void* stream) {
+    if (int rc = check_handle(h)) return rc;
+    (void)stream;
+    return fail(DMD_E_UNSUPPORTED, "Gram resync is not available in this build");
+}
+
+DMD_API int dmd_stream_info(dmd_stream_t* h, dmd_info_t* info) {
+    if (int rc = check_handle(h)) return rc;
+    if (!info) return fail(DMD_E_INVAL, "null info");
+    DeviceGuard g(h->device);
+    DevState st;
+    if (int rc = read_state(h, &st)) return rc;
+    info->n = h->n;
+    info->m = h->m;
+    info->r = h->r;
+    info->dtype = h->opts.dtype;
+    info->precision = h->opts.precision;
+    info->count = st.count;
+    info->r_eff = st.r_eff;
+    info->sweeps = st.sweeps;
+    info->qr_iters = st.qr_iters;
+    info->device_bytes = h->device_bytes;
+    return DMD_OK;
+}
+
+DMD_API int dmd_profile_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return DMD_OK;
+}
+
+DMD_API int dmd_profile_reset(void) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto& r : g_prof) {
+        (void)hipEventSynchronize(r.b);
+        g_prof_pool.push_back(r.a);
+        g_prof_pool.push_back(r.b);
+    }
+    g_prof.clear();
+    return DMD_OK;
+}
+
+DMD_API int dmd_profile_read(const char* kernel, int64_t* launches, double* total_ms) {
+    if (!kernel || !launches || !total_ms) return fail(DMD_E_INVAL, "null argument");
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    int64_t cnt = 0;
+    double tot = 0.0;
+    for (auto& r : g_prof) {
+        if (std::strcmp(r.name, kernel) != 0) continue;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        tot += ms;
+        ++cnt;
+    }
+    *launches = cnt;
+    *total_ms = tot;
+    return DMD_OK;
+}

@@ -1,0 +1,257 @@
+// Streaming Gram update for one dense snapshot (Sec. 3.1, Algorithm 1's
+// non-first-step branch; Algorithm 2's new xty column).
+//
+// Only the new snapshot's inner products are computed: one pass reads the m
+// kept window columns plus the new snapshot and writes the snapshot into the
+// spare ring slot (ingest fused with the dots), so HBM traffic per push is
+// (m+2) * n * sizeof(T) bytes.  The shift of the Gram is a change of the
+// ring's `oldest` index, not a copy.
+//
+// Data are FP32 or FP64; products and sums are FP64 (an FP32 product is exact
+// in FP64), so the Gram keeps the accuracy that the method of snapshots needs
+// after squaring the condition number (Sec. 2.1).
+//
+// Reduction order is fixed: per-thread serial sums, a fixed butterfly inside
+// each 64-wide wavefront, waves summed in index order, then workgroup
+// partials summed in a fixed lane-strided order by the finalize kernel.  No
+// floating-point atomics are used, so every run is bitwise identical.
+#include <cstdlib>
+
+#include "dmd_internal.h"
+
+namespace dmd {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kGroup = 4;  // window columns reduced together
+
+template <typename T> struct Vec16;
+template <> struct Vec16<float>  { using type = float4;  static constexpr int N = 4; };
+template <> struct Vec16<double> { using type = double2; static constexpr int N = 2; };
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Loads the ITER x N elements of this thread from column `col` of a slab.
+// `vec_ok`: the slab is entirely inside [0, n) and `col` is 16-byte aligned.
+template <typename T, int ITER>
+__device__ __forceinline__ void load_slab(const T* __restrict__ col, int64_t base, int64_t n,
+                                          bool vec_ok, T (&v)[ITER][Vec16<T>::N]) {
+    using VT = typename Vec16<T>::type;
+    constexpr int N = Vec16<T>::N;
+    if (vec_ok) {
+#pragma unroll
+        for (int it = 0; it < ITER; ++it) {
+            const VT w = *reinterpret_cast<const VT*>(col + base + (int64_t)(it * kThreads + threadIdx.x) * N);
+            const T* e = reinterpret_cast<const T*>(&w);
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[it][k] = e[k];
+        }
+    } else {
+#pragma unroll
+        for (int it = 0; it < ITER; ++it) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const int64_t i = base + (int64_t)(it * kThreads + threadIdx.x) * N + k;
+                v[it][k] = i < n ? col[i] : T(0);
+            }
+        }
+    }
+}
+
+// One workgroup per slab of kThreads * N * ITER consecutive elements.
+// partials[j * nblk + block] receives the slab's share of <x_j, x_new> for
+// kept column j (window order) and, at j = nkept, of <x_new, x_new>.
+template <typename T, int ITER>
+__global__ __launch_bounds__(kThreads)
+void k_gram_columns(const T* __restrict__ x, T* __restrict__ ring, int64_t ld, int64_t n, int m,
+                    int x_aligned, double* __restrict__ partials, int nblk,
+                    const DevState* __restrict__ st) {
+    constexpr int N = Vec16<T>::N;
+    constexpr int SLAB = kThreads * N * ITER;
+    using VT = typename Vec16<T>::type;
+
+    const int slots = m + 2;
+    const int count = st->count;
+    const int oldest = st->oldest;
+    const int spare = slot_of(oldest, count, slots);
+    const int keep0 = (count == m + 1) ? 1 : 0;  // a full window drops its oldest column
+    const int nkept = count - keep0;
+
+    const int64_t base = (int64_t)blockIdx.x * SLAB;
+    const bool in_range = base + SLAB <= n;
+
+    T xv[ITER][N];
+    load_slab<T, ITER>(x, base, n, in_range && x_aligned, xv);
+
+    // ingest: the new snapshot goes to the spare slot
+    T* dst = ring + (int64_t)spare * ld;
+    if (in_range) {
+#pragma unroll
+        for (int it = 0; it < ITER; ++it)
+            *reinterpret_cast<VT*>(dst + base + (int64_t)(it * kThreads + threadIdx.x) * N) =
+                *reinterpret_cast<const VT*>(&xv[it][0]);
+    } else {
+#pragma unroll
+        for (int it = 0; it < ITER; ++it)
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const int64_t i = base + (int64_t)(it * kThreads + threadIdx.x) * N + k;
+                if (i < n) dst[i] = xv[it][k];
+            }
+    }
+
+    __shared__ double red[kWaves][kGroup];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+
+    for (int j0 = 0; j0 <= nkept; j0 += kGroup) {
+        double acc[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) acc[u] = 0.0;
+        T cv[kGroup][ITER][N];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+            const int j = j0 + u;
+            if (j < nkept) {
+                const T* col = ring + (int64_t)slot_of(oldest, keep0 + j, slots) * ld;
+                load_slab<T, ITER>(col, base, n, in_range, cv[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+            const int j = j0 + u;
+            if (j < nkept) {
+#pragma unroll
+                for (int it = 0; it < ITER; ++it)
+#pragma unroll
+                    for (int k = 0; k < N; ++k)
+                        acc[u] = fma((double)cv[u][it][k], (double)xv[it][k], acc[u]);
+            } else if (j == nkept) {
+#pragma unroll
+                for (int it = 0; it < ITER; ++it)
+#pragma unroll
+                    for (int k = 0; k < N; ++k)
+                        acc[u] = fma((double)xv[it][k], (double)xv[it][k], acc[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+            const double v = wave_sum(acc[u]);
+            if (lane == 0) red[wave][u] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < kGroup && j0 + (int)threadIdx.x <= nkept) {
+            double s = red[0][threadIdx.x];
+#pragma unroll
+            for (int w = 1; w < kWaves; ++w) s += red[w][threadIdx.x];
+            partials[(int64_t)(j0 + threadIdx.x) * nblk + blockIdx.x] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// Sums the partials in a fixed order, rejects non-finite results, writes the
+// new row and column of the (physical-slot indexed) Gram and advances the
+// window: the oldest snapshot leaves a full window (the shift of Algorithm 1).
+__global__ __launch_bounds__(kThreads)
+void k_gram_finalize(double* __restrict__ G, const double* __restrict__ partials, int nblk, int m,
+                     DevState* __restrict__ st) {
+    const int slots = m + 2;
+    const int count = st->count;
+    const int oldest = st->oldest;
+    const int spare = slot_of(oldest, count, slots);
+    const int keep0 = (count == m + 1) ? 1 : 0;
+    const int nkept = count - keep0;
+
+    __shared__ double g[kMaxM + 2];
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    for (int j = wave; j <= nkept; j += kWaves) {
+        double s = 0.0;
+        for (int b = lane; b < nblk; b += 64) s += partials[(int64_t)j * nblk + b];
+        s = wave_sum(s);
+        if (lane == 0) g[j] = s;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j <= nkept; j += kThreads)
+        if (!isfinite(g[j])) bad = 1;
+    __syncthreads();
+    if (bad) {
+        if (threadIdx.x == 0) st->rejected_nonfinite += 1;
+        return;
+    }
+    for (int j = threadIdx.x; j < nkept; j += kThreads) {
+        const int sj = slot_of(oldest, keep0 + j, slots);
+        G[sj + (int64_t)spare * slots] = g[j];  // <x_j, x_new>
+        G[spare + (int64_t)sj * slots] = g[j];  // real data: symmetric
+    }
+    if (threadIdx.x == 0) {
+        G[spare + (int64_t)spare * slots] = g[nkept];
+        if (count == m + 1) st->oldest = slot_of(oldest, 1, slots);
+        else st->count = count + 1;
+        st->pushes += 1;
+    }
+}
+
+template <typename T> constexpr int iter_for(int64_t n) {
+    // Enough workgroups to cover all 256 CUs several times over, with up to
+    // 4 x 16-byte loads per thread and column to keep HBM requests in flight.
+    constexpr int N = Vec16<T>::N;
+    const int64_t per_iter = (int64_t)kThreads * N;
+    if (n >= per_iter * 4 * 1024) return 4;
+    if (n >= per_iter * 2 * 1024) return 2;
+    return 1;
+}
+
+template <typename T> int blocks_for(int64_t n, int iter) {
+    const int64_t slab = (int64_t)kThreads * Vec16<T>::N * iter;
+    return (int)((n + slab - 1) / slab);
+}
+
+}  // namespace
+
+int gram_push_blocks(int64_t n, int elem_bytes) {
+    // capacity of the partials buffer: the smallest ITER gives the most blocks
+    return elem_bytes == 8 ? blocks_for<double>(n, 1) : blocks_for<float>(n, 1);
+}
+
+template <typename T>
+hipError_t launch_gram_columns(const T* x, T* ring, int64_t ld, int64_t n, int m, double* partials,
+                               int nblk_cap, const DevState* st, int* nblk_used, hipStream_t s) {
+    int iter = iter_for<T>(n);
+    if (const char* e = getenv("DMD_GRAM_ITER")) {
+        const int v = atoi(e);
+        if (v == 1 || v == 2 || v == 4) iter = v;
+    }
+    const int nblk = blocks_for<T>(n, iter);
+    if (nblk > nblk_cap) return hipErrorInvalidValue;
+    *nblk_used = nblk;
+    const int x_aligned = ((uintptr_t)x % 16) == 0;
+    dim3 grid(nblk), block(kThreads);
+    switch (iter) {
+        case 4: hipLaunchKernelGGL((k_gram_columns<T, 4>), grid, block, 0, s, x, ring, ld, n, m, x_aligned, partials, nblk, st); break;
+        case 2: hipLaunchKernelGGL((k_gram_columns<T, 2>), grid, block, 0, s, x, ring, ld, n, m, x_aligned, partials, nblk, st); break;
+        default: hipLaunchKernelGGL((k_gram_columns<T, 1>), grid, block, 0, s, x, ring, ld, n, m, x_aligned, partials, nblk, st); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_finalize(double* G, const double* partials, int nblk, int m, DevState* st,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_gram_finalize, dim3(1), dim3(kThreads), 0, s, G, partials, nblk, m, st);
+    return hipGetLastError();
+}
+
+template hipError_t launch_gram_columns<float>(const float*, float*, int64_t, int64_t, int, double*, int,
+                                               const DevState*, int*, hipStream_t);
+template hipError_t launch_gram_columns<double>(const double*, double*, int64_t, int64_t, int, double*, int,
+                                                const DevState*, int*, hipStream_t);
+
+}  // namespace dmd

@@ -1,0 +1,88 @@
+"""The C ABI: the library loads, exports every function the header declares, and
+rejects invalid arguments before touching the GPU (runs without a GPU)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1612_07875_amd as dmd
+from paper_1612_07875_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dmd_stream.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dmd_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_core_calls():
+    names = header_functions()
+    for core in ("dmd_stream_create", "dmd_stream_push", "dmd_stream_eigs", "dmd_stream_modes",
+                 "dmd_stream_push_csr", "dmd_stream_destroy", "dmd_last_error"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = dmd.load()
+    for name in header_functions():
+        assert hasattr(lib, name), name
+        assert name in binding.SIGNATURES or name in binding.STRING_FUNCS, name
+
+
+def test_opts_struct_matches_header_layout():
+    # 6 int32 + 2 double + 8 int32 reserved
+    assert ctypes.sizeof(binding.Opts) == 6 * 4 + 2 * 8 + 8 * 4
+    lib = dmd.load()
+    o = binding.Opts()
+    assert lib.dmd_opts_init(ctypes.byref(o)) == 0
+    assert o.auto_solve == 1 and o.max_sweeps == 40 and o.rcond < 0
+    assert lib.dmd_opts_init(None) == dmd.E_INVAL
+
+
+@pytest.mark.parametrize("n,m,r,msg", [
+    (0, 8, 2, "n must be"),
+    (100, 1, 1, "m must be"),
+    (100, 300, 4, "m must be"),
+    (100, 8, 0, "r must be"),
+    (100, 8, 9, "r must be"),
+    (100, 64, 33, "r must be"),
+])
+def test_create_rejects_bad_sizes_without_gpu(n, m, r, msg):
+    lib = dmd.load()
+    h = ctypes.c_void_p()
+    rc = lib.dmd_stream_create(n, m, r, None, ctypes.byref(h))
+    assert rc == dmd.E_INVAL
+    assert msg in dmd.last_error()
+    assert not h.value
+
+
+def test_create_rejects_bad_options():
+    lib = dmd.load()
+    o = binding.Opts()
+    lib.dmd_opts_init(ctypes.byref(o))
+    o.reserved[3] = 1
+    h = ctypes.c_void_p()
+    assert lib.dmd_stream_create(100, 8, 2, ctypes.byref(o), ctypes.byref(h)) == dmd.E_INVAL
+    lib.dmd_opts_init(ctypes.byref(o))
+    o.dtype = 7
+    assert lib.dmd_stream_create(100, 8, 2, ctypes.byref(o), ctypes.byref(h)) == dmd.E_INVAL
+    assert lib.dmd_stream_create(100, 8, 2, None, None) == dmd.E_INVAL
+
+
+def test_null_handle_calls_fail_cleanly():
+    lib = dmd.load()
+    assert lib.dmd_stream_push(None, None, None) == dmd.E_INVAL
+    assert lib.dmd_stream_eigs(None, None, None, None, None) == dmd.E_INVAL
+    assert lib.dmd_stream_modes(None, None, 0, None) == dmd.E_INVAL
+    assert lib.dmd_stream_sync(None) == dmd.E_INVAL
+    assert lib.dmd_stream_destroy(None) == dmd.OK
+    assert "null handle" in dmd.last_error()
+
+
+def test_version_string():
+    assert b"gfx950" in dmd.load().dmd_version()
