@@ -102,7 +102,11 @@ typedef struct {
                             10 * sqrt(2^-52) ~ 1.5e-7; 0: keep all nonzero)        */
     double  tol;         /* Jacobi stopping threshold: rotate while
                             |a_pq| > tol * sqrt(|a_pp a_qq|) (0 = 1e-15)            */
-    int32_t reserved[8]; /* must be zero                                             */
+    int32_t warm_start;  /* 1: start each Jacobi solve from the previous solve's
+                            eigenvectors, rows shifted by one window position
+                            (consecutive solves then depend on each other); 0
+                            (default): start from the identity                      */
+    int32_t reserved[7]; /* must be zero                                             */
 } dmd_opts_t;
 
 typedef struct dmd_stream dmd_stream_t;
@@ -236,9 +240,9 @@ int dmd_stream_info(dmd_stream_t* h, dmd_info_t* info);
 
 /* Process-wide per-kernel timing for diagnostics and roofline measurement.
  * When enabled, every kernel launch of every handle is bracketed by HIP events
- * recorded on its launch stream.  Kernel names: "gram_columns",
- * "gram_finalize", "solve_sym", "solve_eig", "project_modes", "project_pod",
- * "csr_gram", "csr_finalize", "csr_project", "gram_full".
+ * recorded on its launch stream.  Kernel names: "gram_columns", "gram_finalize", "solve_sym",
+ * "solve_eig", "project_modes", "project_pod", "csr_gram", "csr_project",
+ * "gram_full".
  * dmd_profile_read waits for the recorded events and returns the number of
  * launches of `kernel` and their summed duration in milliseconds since the
  * last dmd_profile_reset. */

@@ -37,7 +37,8 @@ class Opts(ctypes.Structure):
     _fields_ = [
         ("dtype", ctypes.c_int32), ("precision", ctypes.c_int32), ("max_nnz", ctypes.c_int32),
         ("max_sweeps", ctypes.c_int32), ("max_qr_iter", ctypes.c_int32), ("auto_solve", ctypes.c_int32),
-        ("rcond", ctypes.c_double), ("tol", ctypes.c_double), ("reserved", ctypes.c_int32 * 8),
+        ("rcond", ctypes.c_double), ("tol", ctypes.c_double), ("warm_start", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 7),
     ]
 
 
@@ -145,7 +146,7 @@ class Stream:
 
     def __init__(self, n: int, m: int, r: int, dtype: str = "f32", precision: str = "default",
                  auto_solve: bool = True, rcond: Optional[float] = None, tol: float = 0.0,
-                 max_nnz: int = 0, max_sweeps: int = 0, max_qr_iter: int = 0):
+                 max_nnz: int = 0, max_sweeps: int = 0, max_qr_iter: int = 0, warm_start: bool = False):
         if not torch.cuda.is_available():
             raise RuntimeError("libdmdstream needs a HIP GPU; none is available")
         lib = load()
@@ -159,6 +160,7 @@ class Stream:
         o.auto_solve = 1 if auto_solve else 0
         o.rcond = -1.0 if rcond is None else float(rcond)
         o.tol = float(tol)
+        o.warm_start = 1 if warm_start else 0
         h = _P()
         check(lib.dmd_stream_create(int(n), int(m), int(r), ctypes.byref(o), ctypes.byref(h)))
         self._h = h

@@ -26,7 +26,11 @@ struct DevState {
     int32_t qr_iters;           // Hessenberg-QR iterations of the latest solve
     int32_t solves;             // solves run on a full window
     int32_t pushes;             // accepted pushes
-    int32_t pad[6];
+    int32_t vprev_valid;        // Vfull holds the eigenvectors of a converged solve
+    int32_t vprev_push;         // value of `pushes` at that solve
+    int32_t warm;               // latest solve was warm-started (1: shifted, 2: same window)
+    int32_t skipped;            // latest solve found nothing new and kept the previous results
+    int32_t pad[2];
 };
 static_assert(sizeof(DevState) == 64, "DevState must stay 64 bytes");
 
@@ -66,6 +70,9 @@ constexpr int kMaxR = 64;    // truncation rank
 // Dense inner products of one new snapshot with the kept window columns
 // (ingest fused), per-workgroup partial sums, then the fixed-order reduction
 // and Gram update.  T = float or double.
+// Per-workgroup partial sums (ingest fused), then a fixed-order reduction
+// kernel that rejects non-finite results or writes the new Gram row/column
+// and advances the window.
 template <typename T>
 hipError_t launch_gram_columns(const T* x, T* ring, int64_t ld, int64_t n, int m,
                                double* partials, int nblk_cap, const DevState* st,
@@ -90,12 +97,14 @@ struct SolveArgs {
     int cplx;              // 1 for the Hermitian (sparse complex) path
     double rcond, tol;
     int max_sweeps, max_qr_iter;
+    int warm_start;        // start Jacobi from the previous solve's eigenvectors
     double* sigma;         // results block: m sigmas
     double* lam;           // results block: 2 r doubles
     double* V;             // m x r (complex: interleaved), canonical columns
     double* At;            // r x r (complex: interleaved)
     double* W;             // r x r complex
-    double* work;          // global scratch for m > 64: A and V (2 m^2 [x2 complex])
+    double* work;          // global scratch for m > 64: 3 M (M+1) values (A, V, Q)
+    double* Vfull;         // m x m eigenvectors of the latest solve, sigma order
     void* Bphi;            // m x 2r coefficients of Phi (row-major, data precision)
     void* Bpod;            // m x r (real) or m x 2r (complex) coefficients of U
     int coef_f64;          // 1: coefficients stored as double, 0: float

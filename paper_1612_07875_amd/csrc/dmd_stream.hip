@@ -118,6 +118,7 @@ struct dmd_stream {
     double* At = nullptr;
     double* W = nullptr;
     double* work = nullptr;
+    double* Vfull = nullptr;
     void* Bphi = nullptr;
     void* Bpod = nullptr;
 
@@ -162,7 +163,7 @@ int dev_alloc(dmd_stream* h, P** p, size_t bytes) {
 
 void free_all(dmd_stream* h) {
     void* bufs[] = {h->ring, h->ring_idx, h->ring_val, h->ring_nnz, h->scatter, h->G, h->partials,
-                    h->res_dev, h->V, h->At, h->W, h->work, h->Bphi, h->Bpod};
+                    h->res_dev, h->V, h->At, h->W, h->work, h->Vfull, h->Bphi, h->Bpod};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (h->res_host) (void)hipHostFree(h->res_host);
@@ -191,12 +192,14 @@ int enqueue_solve(dmd_stream* h, hipStream_t s) {
     a.tol = h->opts.tol;
     a.max_sweeps = h->opts.max_sweeps;
     a.max_qr_iter = h->opts.max_qr_iter;
+    a.warm_start = h->opts.warm_start;
     a.sigma = reinterpret_cast<double*>(h->res_dev + h->L.sigma_off);
     a.lam = reinterpret_cast<double*>(h->res_dev + h->L.lam_off);
     a.V = h->V;
     a.At = h->At;
     a.W = h->W;
     a.work = h->work;
+    a.Vfull = h->Vfull;
     a.Bphi = h->Bphi;
     a.Bpod = h->Bpod;
     a.coef_f64 = h->coef_f64 ? 1 : 0;
@@ -270,7 +273,7 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
     dmd_opts_init(&o);
     if (opts) {
         o = *opts;
-        for (int i = 0; i < 8; ++i)
+        for (int i = 0; i < 7; ++i)
             if (o.reserved[i] != 0) return fail(DMD_E_INVAL, "opts.reserved must be zero");
         if (o.max_sweeps == 0) o.max_sweeps = 40;
         if (o.max_qr_iter == 0) o.max_qr_iter = 60;
@@ -286,6 +289,7 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
         return fail(DMD_E_INVAL, "unknown precision %d", o.precision);
     if (o.max_sweeps < 1 || o.max_qr_iter < 1) return fail(DMD_E_INVAL, "iteration limits must be positive");
     if (o.auto_solve != 0 && o.auto_solve != 1) return fail(DMD_E_INVAL, "auto_solve must be 0 or 1");
+    if (o.warm_start != 0 && o.warm_start != 1) return fail(DMD_E_INVAL, "warm_start must be 0 or 1");
     if (o.dtype == DMD_C64_CSR) {
         if (o.max_nnz == 0) o.max_nnz = (int32_t)(n < INT32_MAX ? n : INT32_MAX);
         if (o.max_nnz < 1 || o.max_nnz > n) return fail(DMD_E_INVAL, "max_nnz must be in [1, n]");
@@ -326,7 +330,8 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
     ALLOC(h->V, sizeof(double) * cw * (size_t)m * r);
     ALLOC(h->At, sizeof(double) * cw * (size_t)r * r);
     ALLOC(h->W, sizeof(double) * 2 * (size_t)r * r);
-    ALLOC(h->work, sizeof(double) * cw * 2 * (size_t)M * M);
+    ALLOC(h->work, sizeof(double) * cw * 3 * (size_t)M * (M + 1));
+    ALLOC(h->Vfull, sizeof(double) * cw * (size_t)m * m);
     ALLOC(h->Bphi, coef * 2 * (size_t)m * r);
     ALLOC(h->Bpod, coef * cw * (size_t)m * r);
 #undef ALLOC
@@ -393,6 +398,7 @@ namespace dmd {
 __global__ void k_reset_state(DevState* st) {
     st->count = 0;
     st->oldest = 0;
+    st->vprev_valid = 0;
     st->solve_status = ST_E_NOT_READY;
     st->r_eff = 0;
 }

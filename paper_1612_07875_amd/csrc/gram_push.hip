@@ -13,7 +13,7 @@
 //
 // Reduction order is fixed: per-thread serial sums, a fixed butterfly inside
 // each 64-wide wavefront, waves summed in index order, then workgroup
-// partials summed in a fixed lane-strided order by the finalize kernel.  No
+// partials summed in a fixed order by a small finalize kernel.  No
 // floating-point atomics are used, so every run is bitwise identical.
 #include <cstdlib>
 
@@ -60,6 +60,68 @@ __device__ __forceinline__ void load_slab(const T* __restrict__ col, int64_t bas
                 v[it][k] = i < n ? col[i] : T(0);
             }
         }
+    }
+}
+
+// Sums the per-workgroup partials in a fixed order (lane-strided partial sums,
+// then a fixed butterfly), rejects a snapshot whose inner products are not
+// finite, otherwise writes the new Gram row and column and advances the
+// window: the oldest snapshot leaves a full window (the shift of Algorithm 1).
+// 1024 threads; every lane issues its loads independently so that the
+// reduction is bound by memory-level parallelism, not latency.
+constexpr int kFinThreads = 1024;
+constexpr int kFinLanes = 16;  // lanes per column
+
+__global__ __launch_bounds__(kFinThreads)
+void k_gram_finalize(double* __restrict__ G, const double* __restrict__ partials, int nblk, int m,
+                     DevState* __restrict__ st) {
+    const int slots = m + 2;
+    const int count = st->count;
+    const int oldest = st->oldest;
+    const int spare = slot_of(oldest, count, slots);
+    const int keep0 = (count == m + 1) ? 1 : 0;
+    const int nkept = count - keep0;
+
+    __shared__ double g[kMaxM + 2];
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    const int sub = threadIdx.x % kFinLanes;
+    const int grp = threadIdx.x / kFinLanes;
+    constexpr int kGroups = kFinThreads / kFinLanes;
+    for (int j = grp; j <= nkept; j += kGroups) {
+        const double* pj = partials + (int64_t)j * nblk;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int b = sub;
+        for (; b + 3 * kFinLanes < nblk; b += 4 * kFinLanes) {
+            a0 += pj[b];
+            a1 += pj[b + kFinLanes];
+            a2 += pj[b + 2 * kFinLanes];
+            a3 += pj[b + 3 * kFinLanes];
+        }
+        for (; b < nblk; b += kFinLanes) a0 += pj[b];
+        double v = (a0 + a1) + (a2 + a3);
+#pragma unroll
+        for (int off = kFinLanes / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (sub == 0) g[j] = v;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j <= nkept; j += kFinThreads)
+        if (!isfinite(g[j])) bad = 1;
+    __syncthreads();
+    if (bad) {
+        if (threadIdx.x == 0) st->rejected_nonfinite += 1;
+        return;
+    }
+    for (int j = threadIdx.x; j < nkept; j += kFinThreads) {
+        const int sj = slot_of(oldest, keep0 + j, slots);
+        G[sj + (int64_t)spare * slots] = g[j];  // <x_j, x_new>
+        G[spare + (int64_t)sj * slots] = g[j];  // real data: symmetric
+    }
+    if (threadIdx.x == 0) {
+        G[spare + (int64_t)spare * slots] = g[nkept];
+        if (count == m + 1) st->oldest = slot_of(oldest, 1, slots);
+        else st->count = count + 1;
+        st->pushes += 1;
     }
 }
 
@@ -155,51 +217,6 @@ void k_gram_columns(const T* __restrict__ x, T* __restrict__ ring, int64_t ld, i
     }
 }
 
-// Sums the partials in a fixed order, rejects non-finite results, writes the
-// new row and column of the (physical-slot indexed) Gram and advances the
-// window: the oldest snapshot leaves a full window (the shift of Algorithm 1).
-__global__ __launch_bounds__(kThreads)
-void k_gram_finalize(double* __restrict__ G, const double* __restrict__ partials, int nblk, int m,
-                     DevState* __restrict__ st) {
-    const int slots = m + 2;
-    const int count = st->count;
-    const int oldest = st->oldest;
-    const int spare = slot_of(oldest, count, slots);
-    const int keep0 = (count == m + 1) ? 1 : 0;
-    const int nkept = count - keep0;
-
-    __shared__ double g[kMaxM + 2];
-    __shared__ int bad;
-    if (threadIdx.x == 0) bad = 0;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    for (int j = wave; j <= nkept; j += kWaves) {
-        double s = 0.0;
-        for (int b = lane; b < nblk; b += 64) s += partials[(int64_t)j * nblk + b];
-        s = wave_sum(s);
-        if (lane == 0) g[j] = s;
-    }
-    __syncthreads();
-    for (int j = threadIdx.x; j <= nkept; j += kThreads)
-        if (!isfinite(g[j])) bad = 1;
-    __syncthreads();
-    if (bad) {
-        if (threadIdx.x == 0) st->rejected_nonfinite += 1;
-        return;
-    }
-    for (int j = threadIdx.x; j < nkept; j += kThreads) {
-        const int sj = slot_of(oldest, keep0 + j, slots);
-        G[sj + (int64_t)spare * slots] = g[j];  // <x_j, x_new>
-        G[spare + (int64_t)sj * slots] = g[j];  // real data: symmetric
-    }
-    if (threadIdx.x == 0) {
-        G[spare + (int64_t)spare * slots] = g[nkept];
-        if (count == m + 1) st->oldest = slot_of(oldest, 1, slots);
-        else st->count = count + 1;
-        st->pushes += 1;
-    }
-}
-
 template <typename T> constexpr int iter_for(int64_t n) {
     // Enough workgroups to cover all 256 CUs several times over, with up to
     // 4 x 16-byte loads per thread and column to keep HBM requests in flight.
@@ -245,7 +262,7 @@ hipError_t launch_gram_columns(const T* x, T* ring, int64_t ld, int64_t n, int m
 
 hipError_t launch_gram_finalize(double* G, const double* partials, int nblk, int m, DevState* st,
                                 hipStream_t s) {
-    hipLaunchKernelGGL(k_gram_finalize, dim3(1), dim3(kThreads), 0, s, G, partials, nblk, m, st);
+    hipLaunchKernelGGL(k_gram_finalize, dim3(1), dim3(kFinThreads), 0, s, G, partials, nblk, m, st);
     return hipGetLastError();
 }
 

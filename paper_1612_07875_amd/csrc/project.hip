@@ -17,7 +17,8 @@ constexpr int kThreads = 256;
 template <typename TX, typename T, int KC>
 __global__ __launch_bounds__(kThreads)
 void k_project_rows(ProjectArgs a) {
-    __shared__ T Bs[kMaxM * KC];
+    extern __shared__ char dyn_lds[];
+    T* Bs = reinterpret_cast<T*>(dyn_lds);  // m x KC coefficient block
     const DevState* st = a.st;
     if (st->solve_status == ST_E_NOT_READY) return;
     const int k_eff = st->r_eff;
@@ -72,25 +73,38 @@ void k_project_rows(ProjectArgs a) {
     }
 }
 
+template <typename TX, typename T, int KC>
+hipError_t launch_kc(const ProjectArgs& a, hipStream_t s, int kc_max) {
+    const unsigned gx = (unsigned)((a.n + kThreads - 1) / kThreads);
+    dim3 grid(gx, (kc_max + KC - 1) / KC);
+    const size_t lds = sizeof(T) * (size_t)a.m * KC;
+    auto kern = k_project_rows<TX, T, KC>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+// One pass over the window: the column block covers all output columns.
+template <typename TX, typename T>
+hipError_t launch_rows(const ProjectArgs& a, hipStream_t s, int kc_max) {
+    if (kc_max <= 8) return launch_kc<TX, T, 8>(a, s, kc_max);
+    if (kc_max <= 16) return launch_kc<TX, T, 16>(a, s, kc_max);
+    if (kc_max <= 24) return launch_kc<TX, T, 24>(a, s, kc_max);
+    if (kc_max <= 32) return launch_kc<TX, T, 32>(a, s, kc_max);
+    if (kc_max <= 40) return launch_kc<TX, T, 40>(a, s, kc_max);
+    if (kc_max <= 48) return launch_kc<TX, T, 48>(a, s, kc_max);
+    return launch_kc<TX, T, 64>(a, s, kc_max);
+}
+
 }  // namespace
 
 hipError_t launch_project(const ProjectArgs& a, hipStream_t s) {
     const int kc_max = a.cplx_out ? 2 * a.kmax : a.kmax;
-    const unsigned gx = (unsigned)((a.n + kThreads - 1) / kThreads);
-    if (a.elem_f64) {
-        constexpr int KC = 16;
-        dim3 grid(gx, (kc_max + KC - 1) / KC);
-        hipLaunchKernelGGL((k_project_rows<double, double, KC>), grid, dim3(kThreads), 0, s, a);
-    } else if (a.coef_f64) {
-        constexpr int KC = 16;
-        dim3 grid(gx, (kc_max + KC - 1) / KC);
-        hipLaunchKernelGGL((k_project_rows<float, double, KC>), grid, dim3(kThreads), 0, s, a);
-    } else {
-        constexpr int KC = 32;
-        dim3 grid(gx, (kc_max + KC - 1) / KC);
-        hipLaunchKernelGGL((k_project_rows<float, float, KC>), grid, dim3(kThreads), 0, s, a);
-    }
-    return hipGetLastError();
+    if (a.elem_f64) return launch_rows<double, double>(a, s, kc_max);
+    if (a.coef_f64) return launch_rows<float, double>(a, s, kc_max);
+    return launch_rows<float, float>(a, s, kc_max);
 }
 
 }  // namespace dmd

@@ -60,6 +60,42 @@ __device__ __forceinline__ void rr_pair(int rd, int i, int M, int& p, int& q) {
     }
 }
 
+// 1/sqrt(x) to full FP64 accuracy: hardware estimate plus two Newton steps
+// (the estimate carries ~23 correct bits).  Dependent FP64 operations cost
+// ~32 cycles each here, so this replaces the longer correctly-rounded
+// sqrt/division sequences on the latency-bound paths.
+__device__ __forceinline__ double rsqrt_acc(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    double e = fma(-h * y, y, 0.5);
+    y = fma(y, e, y);
+    e = fma(-h * y, y, 0.5);
+    return fma(y, e, y);
+}
+// 1/x to ~46 bits (estimate plus one Newton step).
+__device__ __forceinline__ double rcp_fast(double x) {
+    const double y = __builtin_amdgcn_rcp(x);
+    return fma(y, fma(-x, y, 1.0), y);
+}
+
+// Rotation (c, s) with c^2 + s^2 = 1 to working precision that annihilates
+// the off-diagonal of the real 2x2 [[a, g], [g, b]] (g > 0): t = tan(phi) is
+// the root of t^2 + 2 theta t - 1 = 0 of smaller modulus, theta = (b-a)/(2g).
+__device__ __forceinline__ void jacobi_cs(double a, double b, double g, double& c, double& s) {
+    const double theta = 0.5 * (b - a) * rcp_fast(g);
+    double t;
+    if (fabs(theta) > 1e100) {
+        t = 0.5 * rcp_fast(theta);
+    } else {
+        const double q = fma(theta, theta, 1.0);
+        const double den = fabs(theta) + q * rsqrt_acc(q);
+        t = copysign(rcp_fast(den), theta);
+        if (theta == 0.0) t = 1.0;
+    }
+    c = rsqrt_acc(fma(t, t, 1.0));
+    s = t * c;
+}
+
 // Copies the results block (state, sigma, lambda) to its pinned host mirror so
 // that the host reads a consistent snapshot of this solve after one event wait.
 __device__ void publish(const SolveArgs& a) {
@@ -74,9 +110,58 @@ __device__ void publish(const SolveArgs& a) {
 // --------------------------------------------------------------------------
 // k_solve_sym
 // --------------------------------------------------------------------------
-template <typename S, int NT>
+
+// C = op(A) B for M x M matrices with leading dimension ld (op = identity or
+// conjugate transpose).  LDS path: each thread owns a 4 x 4 block with rows
+// strided by 16 so that a wavefront reads 16 consecutive rows per access.
+template <typename S, int NT, bool CONJ_A>
+__device__ void gemm_sq(S* __restrict__ C, const S* __restrict__ A, const S* __restrict__ B, int M, int ld) {
+    using SC = Scal<S>;
+    const int nrg = (M + 63) / 64;  // row/column super-groups of 64
+    for (int t = threadIdx.x; t < 256 * nrg * nrg; t += NT) {
+        const int g = t / 256, w = t % 256;
+        const int i0 = (g % nrg) * 64 + (w % 16), j0 = (g / nrg) * 64 + (w / 16);
+        S acc[4][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[r][c] = SC::zero();
+        for (int k = 0; k < M; ++k) {
+            S av[4], bv[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + 16 * r;
+                av[r] = i < M ? (CONJ_A ? SC::cj(A[k + (size_t)i * ld]) : A[i + (size_t)k * ld]) : SC::zero();
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int j = j0 + 16 * c;
+                bv[c] = j < M ? B[k + (size_t)j * ld] : SC::zero();
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[r][c] = acc[r][c] + mulr(av[r], bv[c]);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int i = i0 + 16 * r, j = j0 + 16 * c;
+                if (i < M && j < M) C[i + (size_t)j * ld] = acc[r][c];
+            }
+    }
+}
+
+template <typename S> __device__ __forceinline__ S load_s(const double* p, int64_t i);
+template <> __device__ __forceinline__ double load_s<double>(const double* p, int64_t i) { return p[i]; }
+template <> __device__ __forceinline__ cplx load_s<cplx>(const double* p, int64_t i) { return cplx{p[2 * i], p[2 * i + 1]}; }
+
+// LDS: matrices in dynamic LDS (real, M <= 64); else in the global workspace.
+// PMAX: largest number of rotation pairs per round (M / 2).
+template <typename S, int NT, bool LDS, int PMAX>
 __global__ __launch_bounds__(NT)
-void k_solve_sym(SolveArgs a, int M, int use_lds) {
+void k_solve_sym(SolveArgs a, int M) {
     using SC = Scal<S>;
     extern __shared__ double dyn[];
     const int tid = threadIdx.x;
@@ -92,42 +177,91 @@ void k_solve_sym(SolveArgs a, int M, int use_lds) {
         }
         return;
     }
-    const int oldest = st->oldest;
-
-    S* A;
-    S* V;
-    if (use_lds) {
-        A = reinterpret_cast<S*>(dyn);
-        V = A + (size_t)M * M;
-    } else {
-        A = reinterpret_cast<S*>(a.work);
-        V = A + (size_t)M * M;
+    if (st->vprev_valid && st->pushes == st->vprev_push) {
+        // no snapshot was accepted since the last converged solve: its results stand
+        if (tid == 0) st->skipped = 1;
+        return;
     }
+    const int oldest = st->oldest;
+    const int ld = M + 1;  // odd leading dimension: column accesses spread over LDS banks
+    const size_t MM = (size_t)M * ld;
+    S* bufA;
+    if constexpr (LDS) bufA = reinterpret_cast<S*>(dyn);
+    else bufA = reinterpret_cast<S*>(a.work);
+    S* bufV = bufA + MM;
+    S* bufQ = bufV + MM;
     const int P = M / 2;
 
-    __shared__ double s_c[kMaxM / 2], s_s[kMaxM / 2], s_t[kMaxM / 2];
-    __shared__ S s_e[kMaxM / 2];
-    __shared__ int s_p[kMaxM / 2], s_q[kMaxM / 2];
-    __shared__ int s_rot;
+    __shared__ double s_c[PMAX], s_s[PMAX];
+    __shared__ S s_e[PMAX];
+    __shared__ int s_p[PMAX], s_q[PMAX];
+    __shared__ int s_rot, s_reff, s_warm;
     __shared__ double s_red[NT / 64];
-    __shared__ double s_sig[kMaxM];
-    __shared__ int s_perm[kMaxM];
-    __shared__ int s_reff;
+    __shared__ double s_sig[2 * PMAX];
+    __shared__ int s_perm[2 * PMAX];
 
-    // gather xtx (logical window columns 0 .. m-1); pad to even M with a decoupled zero
+    if (tid == 0) {
+        // warm start from the previous solve's eigenvectors when the window
+        // moved by exactly one snapshot (or not at all) since then
+        int w = 0;
+        if (a.warm_start && st->vprev_valid) {
+            if (st->pushes == st->vprev_push + 1) w = 1;
+            else if (st->pushes == st->vprev_push) w = 2;
+        }
+        s_warm = w;
+    }
+    // xtx = Gram of the first m window columns; padded to even M with a decoupled zero
     for (int idx = tid; idx < M * M; idx += NT) {
         const int i = idx % M, j = idx / M;
         S v = SC::zero();
         if (i < m && j < m) v = gram_at<S>(a.G, slot_of(oldest, i, slots), slot_of(oldest, j, slots), slots);
-        A[idx] = v;
-        V[idx] = (i == j) ? SC::one() : SC::zero();
+        bufA[i + (size_t)j * ld] = v;
+    }
+    __syncthreads();
+    const int warm = s_warm;
+    if (warm) {
+        // Q = previous eigenvectors with rows shifted by one window position:
+        // row i of Q is row i+1 of the previous V and the last row is the
+        // previous first row (the departed snapshot), so Q stays unitary and
+        // Q^* xtx Q is close to diagonal.
+        const int shift = warm == 1 ? 1 : 0;
+        for (int idx = tid; idx < M * M; idx += NT) {
+            const int i = idx % M, j = idx / M;
+            S v = (i == j) ? SC::one() : SC::zero();
+            if (i < m && j < m) {
+                int src = i + shift;
+                if (src >= m) src -= m;
+                v = load_s<S>(a.Vfull, src + (int64_t)j * m);
+            }
+            bufQ[i + (size_t)j * ld] = v;
+        }
+        __syncthreads();
+        gemm_sq<S, NT, false>(bufV, bufA, bufQ, M, ld);  // T = xtx Q
+        __syncthreads();
+        gemm_sq<S, NT, true>(bufA, bufQ, bufV, M, ld);   // B = Q^* T
+        __syncthreads();
+        for (int idx = tid; idx < M * M; idx += NT) {    // exact Hermitian symmetry
+            const int i = idx % M, j = idx / M;
+            if (i < j) {
+                const cplx u = SC::toc(bufA[i + (size_t)j * ld]), w = conj(SC::toc(bufA[j + (size_t)i * ld]));
+                const S avg = SC::fromc(0.5 * (u + w));
+                bufA[i + (size_t)j * ld] = avg;
+                bufA[j + (size_t)i * ld] = SC::cj(avg);
+            } else if (i == j) {
+                bufA[i + (size_t)i * ld] = SC::fromc(mkc(SC::re(bufA[i + (size_t)i * ld])));
+            }
+        }
+    }
+    for (int idx = tid; idx < M * M; idx += NT) {
+        const int i = idx % M, j = idx / M;
+        bufV[i + (size_t)j * ld] = (i == j) ? SC::one() : SC::zero();
     }
     __syncthreads();
 
     // rotation floor: entries below 1e-18 * trace cannot move any eigenvalue
     // that a Gram accumulated in FP64 resolves
     double tr = 0.0;
-    for (int i = tid; i < m; i += NT) tr += fabs(SC::re(A[i + i * M]));
+    for (int i = tid; i < m; i += NT) tr += fabs(SC::re(bufA[i + (size_t)i * ld]));
     for (int off = 32; off >= 1; off >>= 1) tr += __shfl_xor(tr, off, 64);
     if ((tid & 63) == 0) s_red[tid >> 6] = tr;
     __syncthreads();
@@ -135,6 +269,9 @@ void k_solve_sym(SolveArgs a, int M, int use_lds) {
     for (int w = 0; w < NT / 64; ++w) tr += s_red[w];
     const double floor_abs = 1e-18 * tr;
     const double tol = a.tol;
+    S* A = bufA;
+    S* V = bufV;
+    const int nw = NT / 64, lane = tid & 63, wv = tid >> 6;
 
     int sweep = 0;
     bool converged = false;
@@ -145,83 +282,87 @@ void k_solve_sym(SolveArgs a, int M, int use_lds) {
             if (tid < P) {
                 int p, q;
                 rr_pair(rd, tid, M, p, q);
-                const S apq = A[p + q * M];
-                const double app = SC::re(A[p + p * M]);
-                const double aqq = SC::re(A[q + q * M]);
+                const S apq = A[p + (size_t)q * ld];
+                const double app = SC::re(A[p + (size_t)p * ld]);
+                const double aqq = SC::re(A[q + (size_t)q * ld]);
                 const double g = SC::absv(apq);
-                double c = 1.0, s = 0.0, t = 0.0;
+                double c = 1.0, s = 0.0;
                 S e = SC::one();
-                if (g > floor_abs && g > tol * sqrt(fabs(app * aqq))) {
-                    const double theta = (aqq - app) / (2.0 * g);
-                    if (fabs(theta) > 1e100) {
-                        t = 0.5 / theta;
-                    } else {
-                        t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
-                    }
-                    c = 1.0 / sqrt(1.0 + t * t);
-                    s = t * c;
+                if (g > floor_abs && g * g > tol * tol * fabs(app * aqq)) {
+                    jacobi_cs(app, aqq, g, c, s);
                     e = SC::phase(apq);
                     s_rot = 1;
                 }
                 s_c[tid] = c;
                 s_s[tid] = s;
-                s_t[tid] = t * g;
                 s_e[tid] = e;
                 s_p[tid] = p;
                 s_q[tid] = q;
             }
             __syncthreads();
-            // A <- J^* A J, 2x2 blocks of (pair k rows, pair l columns), k <= l,
-            // mirrored so that A stays exactly Hermitian
-            for (int idx = tid; idx < P * P; idx += NT) {
-                const int k = idx / P, l = idx % P;
-                if (k > l) continue;
-                const double sk = s_s[k], sl = s_s[l];
-                if (sk == 0.0 && sl == 0.0) continue;
+            // A <- J^* A J on 2x2 blocks (rows of pair k, columns of pair l), k <= l,
+            // mirrored so that A stays exactly Hermitian.  Each half-wavefront
+            // owns one row pair (its rotation is uniform) and its lanes walk l.
+            for (int k = 2 * wv + (lane >> 5); k < P; k += 2 * nw) {
+                const double sk = s_s[k], ck = s_c[k];
+                const S ek = s_e[k];
                 const int p = s_p[k], q = s_q[k];
-                if (k == l) {
-                    const double dt = s_t[k];
-                    A[p + p * M] = SC::fromc(SC::toc(A[p + p * M]) - mkc(dt));
-                    A[q + q * M] = SC::fromc(SC::toc(A[q + q * M]) + mkc(dt));
-                    A[p + q * M] = SC::zero();
-                    A[q + p * M] = SC::zero();
-                    continue;
+                for (int l = k + (lane & 31); l < P; l += 32) {
+                    const double sl = s_s[l];
+                    if (sk == 0.0 && sl == 0.0) continue;
+                    if (l == k) {
+                        // the pair's own 2x2 block, rotated exactly as the others
+                        // (in the basis where a_pq = g e is real): the new
+                        // off-diagonal is zero up to rounding of (c, s)
+                        const double aa = SC::re(A[p + (size_t)p * ld]), bb = SC::re(A[q + (size_t)q * ld]);
+                        const double g = SC::absv(A[p + (size_t)q * ld]);
+                        const double cs = ck * sk, c2 = ck * ck, s2 = sk * sk;
+                        const double na = c2 * aa - 2.0 * cs * g + s2 * bb;
+                        const double nb = s2 * aa + 2.0 * cs * g + c2 * bb;
+                        const double nx = cs * (aa - bb) + (c2 - s2) * g;
+                        A[p + (size_t)p * ld] = SC::fromc(mkc(na));
+                        A[q + (size_t)q * ld] = SC::fromc(mkc(nb));
+                        A[p + (size_t)q * ld] = nx * ek;
+                        A[q + (size_t)p * ld] = SC::cj(nx * ek);
+                        continue;
+                    }
+                    const int u = s_p[l], v = s_q[l];
+                    const double cl = s_c[l];
+                    const S el = s_e[l];
+                    const S apu = A[p + (size_t)u * ld], apv = A[p + (size_t)v * ld];
+                    const S aqu = A[q + (size_t)u * ld], aqv = A[q + (size_t)v * ld];
+                    // rows: p' = c p - s e q ;  q' = s conj(e) p + c q
+                    const S bpu = ck * apu - sk * mulr(ek, aqu);
+                    const S bpv = ck * apv - sk * mulr(ek, aqv);
+                    const S bqu = sk * mulr(SC::cj(ek), apu) + ck * aqu;
+                    const S bqv = sk * mulr(SC::cj(ek), apv) + ck * aqv;
+                    // columns: u' = c u - s conj(e) v ;  v' = s e u + c v
+                    const S npu = cl * bpu - sl * mulr(SC::cj(el), bpv);
+                    const S npv = sl * mulr(el, bpu) + cl * bpv;
+                    const S nqu = cl * bqu - sl * mulr(SC::cj(el), bqv);
+                    const S nqv = sl * mulr(el, bqu) + cl * bqv;
+                    A[p + (size_t)u * ld] = npu;
+                    A[p + (size_t)v * ld] = npv;
+                    A[q + (size_t)u * ld] = nqu;
+                    A[q + (size_t)v * ld] = nqv;
+                    A[u + (size_t)p * ld] = SC::cj(npu);
+                    A[v + (size_t)p * ld] = SC::cj(npv);
+                    A[u + (size_t)q * ld] = SC::cj(nqu);
+                    A[v + (size_t)q * ld] = SC::cj(nqv);
                 }
-                const int u = s_p[l], v = s_q[l];
-                const double ck = s_c[k], cl = s_c[l];
-                const S ek = s_e[k], el = s_e[l];
-                const S apu = A[p + u * M], apv = A[p + v * M];
-                const S aqu = A[q + u * M], aqv = A[q + v * M];
-                // rows: p' = c p - s e q ;  q' = s conj(e) p + c q
-                const S bpu = ck * apu - sk * mulr(ek, aqu);
-                const S bpv = ck * apv - sk * mulr(ek, aqv);
-                const S bqu = sk * mulr(SC::cj(ek), apu) + ck * aqu;
-                const S bqv = sk * mulr(SC::cj(ek), apv) + ck * aqv;
-                // columns: u' = c u - s conj(e) v ;  v' = s e u + c v
-                const S npu = cl * bpu - sl * mulr(SC::cj(el), bpv);
-                const S npv = sl * mulr(el, bpu) + cl * bpv;
-                const S nqu = cl * bqu - sl * mulr(SC::cj(el), bqv);
-                const S nqv = sl * mulr(el, bqu) + cl * bqv;
-                A[p + u * M] = npu;
-                A[u + p * M] = SC::cj(npu);
-                A[p + v * M] = npv;
-                A[v + p * M] = SC::cj(npv);
-                A[q + u * M] = nqu;
-                A[u + q * M] = SC::cj(nqu);
-                A[q + v * M] = nqv;
-                A[v + q * M] = SC::cj(nqv);
             }
-            // V <- V J
-            for (int idx = tid; idx < M * P; idx += NT) {
-                const int i = idx % M, k = idx / M;
+            // V <- V J: one wavefront per pair, lanes over rows
+            for (int k = wv; k < P; k += nw) {
                 const double sk = s_s[k];
                 if (sk == 0.0) continue;
-                const int p = s_p[k], q = s_q[k];
                 const double ck = s_c[k];
                 const S ek = s_e[k];
-                const S vp = V[i + p * M], vq = V[i + q * M];
-                V[i + p * M] = ck * vp - sk * mulr(SC::cj(ek), vq);
-                V[i + q * M] = sk * mulr(ek, vp) + ck * vq;
+                const int p = s_p[k], q = s_q[k];
+                for (int i = lane; i < M; i += 64) {
+                    const S vp = V[i + (size_t)p * ld], vq = V[i + (size_t)q * ld];
+                    V[i + (size_t)p * ld] = ck * vp - sk * mulr(SC::cj(ek), vq);
+                    V[i + (size_t)q * ld] = sk * mulr(ek, vp) + ck * vq;
+                }
             }
             __syncthreads();
         }
@@ -232,9 +373,23 @@ void k_solve_sym(SolveArgs a, int M, int use_lds) {
         __syncthreads();
     }
 
-    // sigma = sqrt(|d|), sorted descending (stable in the index)
-    for (int i = tid; i < m; i += NT) s_sig[i] = sqrt(fabs(SC::re(A[i + i * M])));
+    // eigenvalues d, then eigenvectors of xtx: V (cold) or Q V (warm)
+    for (int i = tid; i < m; i += NT) s_sig[i] = sqrt(fabs(SC::re(A[i + (size_t)i * ld])));
     __syncthreads();
+    S* Vc;
+    S* spare1;
+    S* spare2;
+    if (warm) {
+        gemm_sq<S, NT, false>(bufA, bufQ, bufV, M, ld);
+        Vc = bufA;
+        spare1 = bufV;
+        spare2 = bufQ;
+    } else {
+        Vc = bufV;
+        spare1 = bufA;
+        spare2 = bufQ;
+    }
+    // sigma = sqrt(|d|), sorted descending (stable in the index)
     for (int i = tid; i < m; i += NT) {
         const double si = s_sig[i];
         int rank = 0;
@@ -256,19 +411,23 @@ void k_solve_sym(SolveArgs a, int M, int use_lds) {
         }
         s_reff = k;
     }
+    // all m eigenvectors in sigma order, kept for the next solve's warm start
+    for (int idx = tid; idx < m * m; idx += NT) {
+        const int i = idx % m, k = idx / m;
+        store_s<S>(a.Vfull, i + (int64_t)k * m, Vc[i + (size_t)s_perm[k] * ld]);
+    }
     __syncthreads();
     const int k_eff = s_reff;
 
     // canonical V_r: column perm[k] of V, phase so that its largest-modulus
-    // entry (lowest index on ties) is real positive.  Stored in A's space.
-    S* Vr = A;  // m x k_eff, leading dimension m
-    const int nw = NT / 64, lane = tid & 63, wv = tid >> 6;
+    // entry (lowest index on ties) is real positive
+    S* Vr = spare1;  // m x k_eff, leading dimension ld
     for (int k = wv; k < k_eff; k += nw) {
         const int col = s_perm[k];
         double best = -1.0;
         int bi = 0;
         for (int i = lane; i < m; i += 64) {
-            const double v = SC::absv(V[i + col * M]);
+            const double v = SC::absv(Vc[i + (size_t)col * ld]);
             if (v > best) { best = v; bi = i; }
         }
         for (int off = 32; off >= 1; off >>= 1) {
@@ -276,25 +435,24 @@ void k_solve_sym(SolveArgs a, int M, int use_lds) {
             const int oi = __shfl_xor(bi, off, 64);
             if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
         }
-        const S ph = SC::cj(SC::phase(V[bi + col * M]));
-        // every lane has read V[bi][col] before any lane overwrites A (distinct storage)
+        const S ph = SC::cj(SC::phase(Vc[bi + (size_t)col * ld]));
         for (int i = lane; i < m; i += 64) {
-            const S v = mulr(V[i + col * M], ph);
-            Vr[i + (size_t)k * m] = v;
+            const S v = mulr(Vc[i + (size_t)col * ld], ph);
+            Vr[i + (size_t)k * ld] = v;
             store_s<S>(a.V, i + (int64_t)k * m, v);
         }
     }
     __syncthreads();
 
-    // T = xty V_r (m x k_eff) with xty[i][j] = <x_i, x_{j+1}>; stored in V's space
-    S* T = V;
+    // T = xty V_r (m x k_eff) with xty[i][j] = <x_i, x_{j+1}>
+    S* T = spare2;
     for (int idx = tid; idx < m * k_eff; idx += NT) {
         const int i = idx % m, b = idx / m;
         const int si = slot_of(oldest, i, slots);
         S acc = SC::zero();
         for (int j = 0; j < m; ++j)
-            acc = acc + mulr(gram_at<S>(a.G, si, slot_of(oldest, j + 1, slots), slots), Vr[j + (size_t)b * m]);
-        T[i + (size_t)b * m] = acc;
+            acc = acc + mulr(gram_at<S>(a.G, si, slot_of(oldest, j + 1, slots), slots), Vr[j + (size_t)b * ld]);
+        T[i + (size_t)b * ld] = acc;
     }
     __syncthreads();
 
@@ -302,15 +460,15 @@ void k_solve_sym(SolveArgs a, int M, int use_lds) {
     for (int idx = tid; idx < k_eff * k_eff; idx += NT) {
         const int p = idx % k_eff, q = idx / k_eff;
         S acc = SC::zero();
-        for (int i = 0; i < m; ++i) acc = acc + mulr(SC::cj(Vr[i + (size_t)p * m]), T[i + (size_t)q * m]);
+        for (int i = 0; i < m; ++i) acc = acc + mulr(SC::cj(Vr[i + (size_t)p * ld]), T[i + (size_t)q * ld]);
         const double sp = s_sig[s_perm[p]], sq = s_sig[s_perm[q]];
         store_s<S>(a.At, p + (int64_t)q * k_eff, acc * (1.0 / (sp * sq)));
     }
-    // POD coefficients V_r Sigma^-1 (row-major m x kmax, real or interleaved complex)
+    // POD coefficients V_r Sigma^-1 (row-major m x r, real or interleaved complex)
     const int cw = (sizeof(S) == sizeof(cplx)) ? 2 : 1;
     for (int idx = tid; idx < m * k_eff; idx += NT) {
         const int i = idx / k_eff, q = idx % k_eff;
-        const S v = Vr[i + (size_t)q * m] * (1.0 / s_sig[s_perm[q]]);
+        const S v = Vr[i + (size_t)q * ld] * (1.0 / s_sig[s_perm[q]]);
         const cplx cv = SC::toc(v);
         const int64_t o = (int64_t)i * cw * a.r + (int64_t)cw * q;
         if (a.coef_f64) {
@@ -324,10 +482,15 @@ void k_solve_sym(SolveArgs a, int M, int use_lds) {
         }
     }
     if (tid == 0) {
+        const int lim = a.r < m ? a.r : m;
+        st->skipped = 0;
         st->r_eff = k_eff;
         st->sweeps = sweep + (converged ? 1 : 0);
-        st->solve_status = converged ? (k_eff < (a.r < m ? a.r : m) ? ST_W_RANK : ST_OK) : ST_E_CONVERGENCE;
+        st->solve_status = converged ? (k_eff < lim ? ST_W_RANK : ST_OK) : ST_E_CONVERGENCE;
         if (k_eff == 0) st->solve_status = ST_W_RANK;
+        st->vprev_valid = converged ? 1 : 0;
+        st->vprev_push = st->pushes;
+        st->warm = warm;
     }
 }
 
@@ -343,6 +506,10 @@ void k_solve_eig(SolveArgs a) {
     const int status0 = st->solve_status;
     const int k = st->r_eff;
     const int m = a.m;
+    if (st->skipped) {
+        publish(a);
+        return;
+    }
     if (status0 == ST_E_NOT_READY || k == 0) {
         if (lane == 0 && status0 != ST_E_NOT_READY) st->solves += 1;
         publish(a);
@@ -477,18 +644,23 @@ void k_solve_eig(SolveArgs a) {
                 x = H[kk + (kk - 1) * LDH];
                 y = H[(kk + 1) + (kk - 1) * LDH];
             }
-            // G = [[c, s], [-conj(s), c]] with G [x; y] = [rho; 0]
+            // G = [[c, s], [-conj(s), c]] with G [x; y] = [rho; 0]:
+            // c = |x| / r, s = (x / |x|) conj(y) / r, r^2 = |x|^2 + |y|^2
             double c;
             cplx s;
-            const double ax = cabs(x), ay = cabs(y);
-            if (ay == 0.0) {
+            const double x2 = abs2(x), y2 = abs2(y);
+            if (y2 == 0.0) {
                 c = 1.0;
                 s = mkc(0.0);
-            } else if (ax == 0.0) {
+            } else if (x2 == 0.0) {
                 c = 0.0;
                 s = mkc(1.0);
+            } else if (x2 > 1e-250 && y2 > 1e-250 && x2 < 1e250 && y2 < 1e250) {
+                const double rx = rsqrt_acc(x2), rr = rsqrt_acc(x2 + y2);
+                c = x2 * rx * rr;
+                s = (rx * rr) * mul_conj(x, y);
             } else {
-                const double rr = hypot(ax, ay);
+                const double ax = cabs(x), rr = hypot(ax, cabs(y));
                 c = ax / rr;
                 s = (1.0 / rr) * mul_conj(cplx{x.re / ax, x.im / ax}, y);
             }
@@ -560,7 +732,61 @@ void k_solve_eig(SolveArgs a) {
     // normalise column q (lane q): unit norm, largest-modulus entry (lowest
     // index on ties) real positive; rank by |lambda| descending, arg ascending
     __shared__ cplx s_lam[kRMax];
+    __shared__ int s_partner[kRMax];
     if (lane < k) s_lam[lane] = lam_q;
+    __syncthreads();
+    if (!a.cplx) {
+        // A real A~ has a spectrum closed under conjugation.  The complex QR
+        // returns each conjugate pair with independent rounding; pair them
+        // up and make the member with negative imaginary part the exact
+        // conjugate of its partner (eigenvector too), and make numerically
+        // real eigenvalues exactly real, so that the order of eigenpairs does
+        // not depend on rounding.
+        const double dl = 1e-10;
+        int partner = -1;
+        if (lane < k && lam_q.im < -dl * cabs(lam_q)) {
+            double best = 1e300;
+            for (int p = 0; p < k; ++p) {
+                const cplx lp = s_lam[p];
+                if (!(lp.im > dl * cabs(lp))) continue;
+                const double d = cabs(conj(lp) - lam_q);
+                if (d < best) { best = d; partner = p; }
+            }
+        }
+        if (lane < k) s_partner[lane] = partner;
+        __syncthreads();
+        // accept the pairing only if it is a bijection between the two halves
+        int npos = 0, nneg = 0, ok = 1;
+        for (int p = 0; p < k; ++p) {
+            const cplx lp = s_lam[p];
+            if (lp.im > dl * cabs(lp)) ++npos;
+            if (lp.im < -dl * cabs(lp)) {
+                ++nneg;
+                if (s_partner[p] < 0) ok = 0;
+                for (int q2 = 0; q2 < p; ++q2)
+                    if (s_partner[q2] == s_partner[p] && s_partner[p] >= 0) ok = 0;
+            }
+        }
+        ok = ok && (npos == nneg);
+        __syncthreads();
+        if (ok && lane < k) {
+            const int pr = s_partner[lane];
+            if (pr >= 0) {
+                lam_q = conj(s_lam[pr]);
+                for (int i = 0; i < k; ++i) H[i + lane * LDH] = conj(H[i + pr * LDH]);
+            } else if (!(lam_q.im > dl * cabs(lam_q))) {
+                lam_q.im = 0.0;
+            }
+        }
+        __syncthreads();
+        if (lane < k) s_lam[lane] = lam_q;
+        __syncthreads();
+    }
+    __shared__ double s_mod[kRMax], s_arg[kRMax];
+    if (lane < k) {
+        s_mod[lane] = cabs(lam_q);
+        s_arg[lane] = atan2(lam_q.im, lam_q.re);
+    }
     __syncthreads();
     if (lane < k) {
         const int q = lane;
@@ -575,11 +801,10 @@ void k_solve_eig(SolveArgs a) {
         const double ap = cabs(piv);
         const cplx ph = ap > 0.0 ? cplx{piv.re / ap, -piv.im / ap} : mkc(1.0);
         const cplx scale_q = (nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 1.0) * ph;
-        const double mq = cabs(lam_q), aq = atan2(lam_q.im, lam_q.re);
+        const double mq = s_mod[q], aq = s_arg[q];
         int rank = 0;
         for (int p = 0; p < k; ++p) {
-            const cplx lp = s_lam[p];
-            const double mp = cabs(lp), app = atan2(lp.im, lp.re);
+            const double mp = s_mod[p], app = s_arg[p];
             rank += (mp > mq) || (mp == mq && app < aq) || (mp == mq && app == aq && p < q);
         }
         s_rank[q] = rank;
@@ -594,16 +819,28 @@ void k_solve_eig(SolveArgs a) {
     }
     __syncthreads();
 
-    // ---- C = V_r Sigma^-1 W (m x k complex), row-major with row stride 2 r
+    // ---- C = V_r Sigma^-1 W (m x k complex), row-major with row stride 2 r;
+    // lane i keeps row i of V_r Sigma^-1 in registers, W (sorted) is in LDS
     for (int i = lane; i < m; i += 64) {
-        for (int q = 0; q < k; ++q) {
-            cplx acc = mkc(0.0);
-            for (int p = 0; p < k; ++p) {
-                cplx vip;
-                if (a.cplx) vip = cplx{a.V[2 * (i + (int64_t)p * m)], a.V[2 * (i + (int64_t)p * m) + 1]};
-                else vip = mkc(a.V[i + (int64_t)p * m]);
-                acc = acc + (vip * (1.0 / s_sig[p])) * Y[p + q * LDH];
+        cplx vrow[kRMax];
+#pragma unroll
+        for (int p = 0; p < kRMax; ++p) {
+            cplx v = mkc(0.0);
+            if (p < k) {
+                if (a.cplx) v = cplx{a.V[2 * (i + (int64_t)p * m)], a.V[2 * (i + (int64_t)p * m) + 1]};
+                else v = mkc(a.V[i + (int64_t)p * m]);
+                v = v * (1.0 / s_sig[p]);
             }
+            vrow[p] = v;
+        }
+        for (int q = 0; q < k; ++q) {
+            cplx acc0 = mkc(0.0), acc1 = mkc(0.0);
+#pragma unroll
+            for (int p = 0; p < kRMax; p += 2) {
+                if (p < k) acc0 = acc0 + vrow[p] * Y[p + q * LDH];
+                if (p + 1 < k) acc1 = acc1 + vrow[p + 1] * Y[p + 1 + q * LDH];
+            }
+            const cplx acc = acc0 + acc1;
             const int64_t o = (int64_t)i * 2 * a.r + 2 * q;
             if (a.coef_f64) {
                 double* B = reinterpret_cast<double*>(a.Bphi);
@@ -630,15 +867,16 @@ hipError_t launch_solve_sym(const SolveArgs& a, hipStream_t s) {
     if (a.r > kRMax || a.m > kMaxM) return hipErrorInvalidValue;
     const int M = a.m + (a.m & 1);
     if (!a.cplx && M <= 64) {
-        const size_t lds = 2 * sizeof(double) * (size_t)M * M;
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_solve_sym<double, 256>),
+        const size_t lds = 3 * sizeof(double) * (size_t)M * (M + 1);
+        auto kern = k_solve_sym<double, 1024, true, 32>;
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_solve_sym<double, 256>), dim3(1), dim3(256), lds, s, a, M, 1);
+        hipLaunchKernelGGL(kern, dim3(1), dim3(1024), lds, s, a, M);
     } else if (!a.cplx) {
-        hipLaunchKernelGGL((k_solve_sym<double, 1024>), dim3(1), dim3(1024), 0, s, a, M, 0);
+        hipLaunchKernelGGL((k_solve_sym<double, 1024, false, kMaxM / 2>), dim3(1), dim3(1024), 0, s, a, M);
     } else {
-        hipLaunchKernelGGL((k_solve_sym<cplx, 1024>), dim3(1), dim3(1024), 0, s, a, M, 0);
+        hipLaunchKernelGGL((k_solve_sym<cplx, 1024, false, kMaxM / 2>), dim3(1), dim3(1024), 0, s, a, M);
     }
     return hipGetLastError();
 }

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_opts_struct_matches_header_layout():
-    # 6 int32 + 2 double + 8 int32 reserved
+    # 6 int32 + 2 double + warm_start + 7 int32 reserved
     assert ctypes.sizeof(binding.Opts) == 6 * 4 + 2 * 8 + 8 * 4
     lib = dmd.load()
     o = binding.Opts()

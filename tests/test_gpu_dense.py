@@ -214,3 +214,19 @@ def test_rank_deficient_window_reports_w_rank():
     assert rc == dmd.W_RANK and lam.size == 10
     err, _ = metrics.eig_relerr(lam, g.true_eigs())
     assert err.max() < 1e-9
+
+
+def test_warm_start_option_matches_oracle():
+    """Jacobi started from the previous solve's eigenvectors (rows shifted by one
+    window position) reaches the same decomposition as a cold start."""
+    dmd = _dmd()
+    v = gen.BlobVideo(height=90, width=160, blob_sigma=3.0)
+    m, r = 32, 12
+    T = m + 8
+    frames = v.frames(0, T)
+    X = torch.from_numpy(frames.T.copy()).cuda()
+    with dmd.Stream(90 * 160, m, r, warm_start=True) as s:
+        for t in range(T):
+            s.push(X[t])
+            if t >= m:
+                check_window(s, frames[:, t - m:t + 1], m, r, phi_tol=2e-4)
