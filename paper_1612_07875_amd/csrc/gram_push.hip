@@ -217,13 +217,14 @@ void k_gram_columns(const T* __restrict__ x, T* __restrict__ ring, int64_t ld, i
     }
 }
 
-template <typename T> constexpr int iter_for(int64_t n) {
-    // Enough workgroups to cover all 256 CUs several times over, with up to
-    // 4 x 16-byte loads per thread and column to keep HBM requests in flight.
+template <typename T> int iter_for(int64_t n) {
+    // The largest slab (up to 4 x 16-byte loads per thread and column) that
+    // still gives at least 256 workgroups, one per CU: big slabs keep many
+    // requests in flight and leave few partial sums for the finalize kernel.
     constexpr int N = Vec16<T>::N;
     const int64_t per_iter = (int64_t)kThreads * N;
-    if (n >= per_iter * 4 * 1024) return 4;
-    if (n >= per_iter * 2 * 1024) return 2;
+    if (n >= per_iter * 4 * 256) return 4;
+    if (n >= per_iter * 2 * 256) return 2;
     return 1;
 }
 

@@ -4,107 +4,182 @@
 // out (n x kcols) = X_sub (n x m, ring columns in window order) * B (m x kcols),
 // B row-major.  For the modes B holds the complex m x r_eff matrix
 // C = V Sigma^-1 W as 2 r_eff interleaved real columns, so a real window gives
-// interleaved complex output directly.  Each thread owns one row; the
-// coefficient block sits in LDS and is read as a broadcast.
+// interleaved complex output directly.
+//
+// Dense contraction on the matrix cores: v_mfma_f32_16x16x4f32 (FP32) or
+// v_mfma_f64_16x16x4f64 (FP64).  A wavefront owns 64 rows (four 16-row
+// tiles) and all output columns (up to four 16-column tiles); per step of
+// four window columns it loads its A fragments straight from the ring (each
+// lane one element, 16 consecutive rows per column) and the B fragments from
+// the (L2-resident) coefficient matrix.
+//
+// Fragment layouts of the 16x16x4 instructions (checked on the device):
+//   A: lane l holds A[l % 16][l / 16];  B: lane l holds B[l / 16][l % 16];
+//   D (f32): lane l holds D[4 (l / 16) + v][l % 16], v = 0..3;
+//   D (f64): lane l holds D[(l / 16) + 4 v][l % 16], v = 0..3.
 #include "dmd_internal.h"
 
 namespace dmd {
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;   // 4 wavefronts
+constexpr int kRowsPerWave = 64;
+constexpr int kRowsPerBlock = kThreads / 64 * kRowsPerWave;
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Acc;
+template <> struct Acc<float> {
+    using type = v4f;
+    static __device__ __forceinline__ v4f mma(float a, float b, v4f c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int g, int v) { return 4 * g + v; }
+};
+template <> struct Acc<double> {
+    using type = v4d;
+    static __device__ __forceinline__ v4d mma(double a, double b, v4d c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int g, int v) { return g + 4 * v; }
+};
 
 // TX: ring element type; T: coefficient, accumulation and output type.
-template <typename TX, typename T, int KC>
+// NT: number of 16-column output tiles (kcols <= 16 NT).
+// The A and B fragments of the next group of four k-steps are loaded while
+// the current group's MFMAs run; output tiles go through LDS so that every
+// store instruction writes 64 consecutive rows of one output column.
+template <typename TX, typename T, int NT>
 __global__ __launch_bounds__(kThreads)
-void k_project_rows(ProjectArgs a) {
-    extern __shared__ char dyn_lds[];
-    T* Bs = reinterpret_cast<T*>(dyn_lds);  // m x KC coefficient block
+void k_project_mfma(ProjectArgs a) {
+    using AccT = typename Acc<T>::type;
+    constexpr int KG = sizeof(T) == 8 ? 2 : 4;  // k-steps (of 4 columns) per group
+    constexpr int OLD = 17;                // padded row length of the output stage
+    __shared__ T stage[kThreads / 64][64 * OLD];
     const DevState* st = a.st;
     if (st->solve_status == ST_E_NOT_READY) return;
     const int k_eff = st->r_eff;
     const int kcols = a.cplx_out ? 2 * k_eff : k_eff;
-    const int col0 = blockIdx.y * KC;
-    if (col0 >= kcols) return;
+    if (kcols == 0) return;
     const int m = a.m;
     const int rowstride = a.cplx_out ? 2 * a.kmax : a.kmax;
     const T* B = reinterpret_cast<const T*>(a.B);
-    for (int idx = threadIdx.x; idx < m * KC; idx += kThreads) {
-        const int j = idx / KC, c = idx % KC;
-        Bs[idx] = (col0 + c < kcols) ? B[(int64_t)j * rowstride + col0 + c] : T(0);
-    }
-    __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= a.n) return;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t row0 = (int64_t)blockIdx.x * kRowsPerBlock + wave * kRowsPerWave;
     const int oldest = st->oldest;
     const TX* ring = reinterpret_cast<const TX*>(a.ring);
-    T acc[KC];
+
+    AccT acc[4][NT];
 #pragma unroll
-    for (int c = 0; c < KC; ++c) acc[c] = T(0);
-    int j = 0;
-    for (; j + 4 <= m; j += 4) {
-        T x[4];
+    for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-            x[u] = (T)ring[(int64_t)slot_of(oldest, a.first + j + u, a.slots) * a.ld + i];
+        for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = AccT{0, 0, 0, 0};
+
+    bool rin[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+    for (int rt = 0; rt < 4; ++rt) rin[rt] = row0 + 16 * rt + li < a.n;
+
+    T av[2][KG][4], bv[2][KG][NT];
+    auto load_group = [&](int buf, int k0) {
 #pragma unroll
-            for (int c = 0; c < KC; ++c) acc[c] = fma(x[u], Bs[(j + u) * KC + c], acc[c]);
-    }
-    for (; j < m; ++j) {
-        const T x = (T)ring[(int64_t)slot_of(oldest, a.first + j, a.slots) * a.ld + i];
+        for (int g = 0; g < KG; ++g) {
+            const int col = k0 + 4 * g + lk;
+            const bool cin = col < m;
+            const TX* cp = ring + (int64_t)slot_of(oldest, a.first + (cin ? col : 0), a.slots) * a.ld;
 #pragma unroll
-        for (int c = 0; c < KC; ++c) acc[c] = fma(x, Bs[j * KC + c], acc[c]);
-    }
-    T* out = reinterpret_cast<T*>(a.out);
-    if (a.cplx_out) {
+            for (int rt = 0; rt < 4; ++rt) av[buf][g][rt] = (cin && rin[rt]) ? (T)cp[row0 + 16 * rt + li] : T(0);
 #pragma unroll
-        for (int c = 0; c < KC; c += 2) {
-            if (col0 + c < kcols) {
-                const int64_t o = 2 * (i + (int64_t)((col0 + c) / 2) * a.ldo);
-                out[o] = acc[c];
-                out[o + 1] = acc[c + 1];
+            for (int nt = 0; nt < NT; ++nt) {
+                const int c = 16 * nt + li;
+                bv[buf][g][nt] = (cin && c < kcols) ? B[(int64_t)col * rowstride + c] : T(0);
             }
         }
-    } else {
+    };
+    auto mma_group = [&](int buf) {
 #pragma unroll
-        for (int c = 0; c < KC; ++c)
-            if (col0 + c < kcols) out[i + (int64_t)(col0 + c) * a.ldo] = acc[c];
+        for (int g = 0; g < KG; ++g)
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[rt][nt] = Acc<T>::mma(av[buf][g][rt], bv[buf][g][nt], acc[rt][nt]);
+    };
+    // two groups per iteration so that both register buffers have static indices
+    const int ngroups = (m + 4 * KG - 1) / (4 * KG);
+    load_group(0, 0);
+    for (int gi = 0; gi < ngroups; gi += 2) {
+        if (gi + 1 < ngroups) load_group(1, (gi + 1) * 4 * KG);
+        mma_group(0);
+        if (gi + 1 >= ngroups) break;
+        if (gi + 2 < ngroups) load_group(0, (gi + 2) * 4 * KG);
+        mma_group(1);
+    }
+
+    T* out = reinterpret_cast<T*>(a.out);
+    T* sw = stage[wave];
+    const int64_t row = row0 + lane;  // the row this lane stores
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        if (16 * nt >= kcols) break;
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sw[(16 * rt + Acc<T>::row(lk, v)) * OLD + li] = acc[rt][nt][v];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (row < a.n) {
+            if (a.cplx_out) {
+#pragma unroll
+                for (int cc = 0; cc < 16; cc += 2) {
+                    const int c = 16 * nt + cc;
+                    if (c < kcols) {
+                        const int64_t o = 2 * (row + (int64_t)(c >> 1) * a.ldo);
+                        out[o] = sw[lane * OLD + cc];
+                        out[o + 1] = sw[lane * OLD + cc + 1];
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int cc = 0; cc < 16; ++cc) {
+                    const int c = 16 * nt + cc;
+                    if (c < kcols) out[row + (int64_t)c * a.ldo] = sw[lane * OLD + cc];
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
-template <typename TX, typename T, int KC>
-hipError_t launch_kc(const ProjectArgs& a, hipStream_t s, int kc_max) {
-    const unsigned gx = (unsigned)((a.n + kThreads - 1) / kThreads);
-    dim3 grid(gx, (kc_max + KC - 1) / KC);
-    const size_t lds = sizeof(T) * (size_t)a.m * KC;
-    auto kern = k_project_rows<TX, T, KC>;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, s, a);
+template <typename TX, typename T, int NT>
+hipError_t launch_nt(const ProjectArgs& a, hipStream_t s) {
+    const unsigned gx = (unsigned)((a.n + kRowsPerBlock - 1) / kRowsPerBlock);
+    hipLaunchKernelGGL((k_project_mfma<TX, T, NT>), dim3(gx), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 
-// One pass over the window: the column block covers all output columns.
 template <typename TX, typename T>
-hipError_t launch_rows(const ProjectArgs& a, hipStream_t s, int kc_max) {
-    if (kc_max <= 8) return launch_kc<TX, T, 8>(a, s, kc_max);
-    if (kc_max <= 16) return launch_kc<TX, T, 16>(a, s, kc_max);
-    if (kc_max <= 24) return launch_kc<TX, T, 24>(a, s, kc_max);
-    if (kc_max <= 32) return launch_kc<TX, T, 32>(a, s, kc_max);
-    if (kc_max <= 40) return launch_kc<TX, T, 40>(a, s, kc_max);
-    if (kc_max <= 48) return launch_kc<TX, T, 48>(a, s, kc_max);
-    return launch_kc<TX, T, 64>(a, s, kc_max);
+hipError_t launch_tiles(const ProjectArgs& a, hipStream_t s, int kc_max) {
+    if (kc_max <= 16) return launch_nt<TX, T, 1>(a, s);
+    if (kc_max <= 32) return launch_nt<TX, T, 2>(a, s);
+    if (kc_max <= 48) return launch_nt<TX, T, 3>(a, s);
+    return launch_nt<TX, T, 4>(a, s);
 }
 
 }  // namespace
 
 hipError_t launch_project(const ProjectArgs& a, hipStream_t s) {
     const int kc_max = a.cplx_out ? 2 * a.kmax : a.kmax;
-    if (a.elem_f64) return launch_rows<double, double>(a, s, kc_max);
-    if (a.coef_f64) return launch_rows<float, double>(a, s, kc_max);
-    return launch_rows<float, float>(a, s, kc_max);
+    if (kc_max > 64) return hipErrorInvalidValue;
+    if (a.elem_f64) return launch_tiles<double, double>(a, s, kc_max);
+    if (a.coef_f64) return launch_tiles<float, double>(a, s, kc_max);
+    return launch_tiles<float, float>(a, s, kc_max);
 }
 
 }  // namespace dmd
