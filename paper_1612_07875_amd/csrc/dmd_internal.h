@@ -81,12 +81,14 @@ hipError_t launch_gram_finalize(double* G, const double* partials, int nblk, int
                                 DevState* st, hipStream_t s);
 int gram_push_blocks(int64_t n, int elem_bytes);
 
-// Sparse complex snapshot: ingest into the CSR ring and Hermitian inner
-// products through a dense scatter buffer.
-hipError_t launch_csr_push(const int32_t* idx, const float2* val, int nnz,
+// Sparse complex snapshot: ingest into the CSR ring (with index checks),
+// Hermitian inner products through a dense scatter vector, fixed-order
+// reduction and Gram update, scatter vector cleared again.
+hipError_t launch_csr_push(const int32_t* idx, const float2* val, int nnz, int64_t n,
                            int32_t* ring_idx, float2* ring_val, int32_t* ring_nnz,
-                           int max_nnz, int64_t n, int m, float2* scatter,
+                           int max_nnz, int m, float2* scatter, int* flag,
                            double* G, double* partials, DevState* st, hipStream_t s);
+int csr_partials_per_column();
 
 // FP64 small solves for the current window: Jacobi eig of X^*X, sigma, V,
 // A~, eig(A~) by Hessenberg-QR, coefficient matrices for the projections.
@@ -133,16 +135,23 @@ struct ProjectArgs {
 };
 hipError_t launch_project(const ProjectArgs& a, hipStream_t s);
 
-// Sparse projection: Phi = X'_sparse * C into a dense n x r complex64 output.
+// Sparse projection: out = X_sub * B (complex) into a dense n x r_eff
+// complex64 output (zero outside the window's support).
 hipError_t launch_csr_project(const DevState* st, const int32_t* ring_idx,
                               const float2* ring_val, const int32_t* ring_nnz,
-                              int max_nnz, int m, int slots, int first,
-                              const float2* B, int kmax, int cplx_rows,
+                              int max_nnz, int m, int first, const float2* B, int kmax,
                               float2* out, int64_t ldo, int64_t n, hipStream_t s);
 
-// Whole Gram of k dense columns (MFMA): G_sub = X^* X for logical columns.
-hipError_t launch_gram_full(const void* ring, int64_t ld, int64_t n, int m, int slots,
-                            int elem_f64, int precision, double* G, DevState* st,
-                            double* work, hipStream_t s);
+// Whole Gram of the window's first kcols columns on the matrix cores (FP64,
+// FP32 or BF16x3 products), split over rows with a fixed-order FP64 sum.
+// oldest_override >= 0 places the window at that slot (new window, set_window
+// = 1); -1 uses the device state (recomputation, set_window = 2).
+hipError_t launch_gram_full(const void* ring, int64_t ld, int64_t n, int m, int slots, int elem_f64,
+                            int precision, int kcols, int oldest_override, double* partial, double* G,
+                            DevState* st, int set_window, hipStream_t s);
+hipError_t launch_copy_columns(const void* X, int64_t ldx, void* ring, int64_t ld, int64_t n, int k,
+                               int elem_f64, hipStream_t s);
+int gram_full_tiles(int m);
+int gram_full_splits(int m);
 
 }  // namespace dmd

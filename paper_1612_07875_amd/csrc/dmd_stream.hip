@@ -105,6 +105,7 @@ struct dmd_stream {
     float2* ring_val = nullptr;   // sparse: slots x max_nnz values
     int32_t* ring_nnz = nullptr;  // sparse: slots counts
     float2* scatter = nullptr;    // sparse: n dense scratch (kept zero)
+    int* flag = nullptr;          // sparse: bad-index flag of the push in flight
     int max_nnz = 0;
 
     double* G = nullptr;
@@ -119,6 +120,7 @@ struct dmd_stream {
     double* W = nullptr;
     double* work = nullptr;
     double* Vfull = nullptr;
+    double* gfull = nullptr;      // per-split tiles of the whole-window Gram
     void* Bphi = nullptr;
     void* Bpod = nullptr;
 
@@ -162,8 +164,8 @@ int dev_alloc(dmd_stream* h, P** p, size_t bytes) {
 }
 
 void free_all(dmd_stream* h) {
-    void* bufs[] = {h->ring, h->ring_idx, h->ring_val, h->ring_nnz, h->scatter, h->G, h->partials,
-                    h->res_dev, h->V, h->At, h->W, h->work, h->Vfull, h->Bphi, h->Bpod};
+    void* bufs[] = {h->ring, h->ring_idx, h->ring_val, h->ring_nnz, h->scatter, h->flag, h->G, h->partials,
+                    h->res_dev, h->V, h->At, h->W, h->work, h->Vfull, h->gfull, h->Bphi, h->Bpod};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (h->res_host) (void)hipHostFree(h->res_host);
@@ -294,10 +296,11 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
         if (o.max_nnz == 0) o.max_nnz = (int32_t)(n < INT32_MAX ? n : INT32_MAX);
         if (o.max_nnz < 1 || o.max_nnz > n) return fail(DMD_E_INVAL, "max_nnz must be in [1, n]");
         if (n > INT32_MAX) return fail(DMD_E_INVAL, "sparse streams need n <= 2^31-1");
-        return fail(DMD_E_UNSUPPORTED, "sparse complex streams are not available in this build");
+        if (o.precision != DMD_PREC_DEFAULT && o.precision != DMD_PREC_FP32)
+            return fail(DMD_E_UNSUPPORTED, "sparse streams project in FP32");
     }
-    if (o.precision == DMD_PREC_BF16X3)
-        return fail(DMD_E_UNSUPPORTED, "BF16X3 projections are not available in this build");
+    if (o.precision == DMD_PREC_BF16X3 && o.dtype != DMD_F32)
+        return fail(DMD_E_UNSUPPORTED, "BF16X3 applies to FP32 data");
 
     dmd_stream* h = new (std::nothrow) dmd_stream();
     if (!h) return fail(DMD_E_NOMEM, "host allocation failed");
@@ -323,7 +326,18 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
     const size_t coef = h->coef_f64 ? 8 : 4;
 #define ALLOC(p, bytes)                                  \
     if (rc == DMD_OK) rc = dev_alloc(h, &(p), (bytes));
-    ALLOC(h->ring, (size_t)h->slots * h->ld * h->elem_bytes);
+    if (h->cplx) {
+        h->max_nnz = o.max_nnz;
+        h->nblk_cap = dmd::csr_partials_per_column();
+        ALLOC(h->ring_idx, sizeof(int32_t) * (size_t)h->slots * h->max_nnz);
+        ALLOC(h->ring_val, sizeof(float2) * (size_t)h->slots * h->max_nnz);
+        ALLOC(h->ring_nnz, sizeof(int32_t) * (size_t)h->slots);
+        ALLOC(h->scatter, sizeof(float2) * (size_t)n);
+        ALLOC(h->flag, sizeof(int));
+    } else {
+        ALLOC(h->ring, (size_t)h->slots * h->ld * h->elem_bytes);
+        ALLOC(h->gfull, sizeof(double) * 64 * 64 * (size_t)dmd::gram_full_tiles(m) * dmd::gram_full_splits(m));
+    }
     ALLOC(h->G, sizeof(double) * cw * h->slots * h->slots);
     ALLOC(h->partials, sizeof(double) * cw * (size_t)(m + 2) * h->nblk_cap);
     ALLOC(h->res_dev, h->L.bytes);
@@ -445,8 +459,23 @@ DMD_API int dmd_stream_push(dmd_stream_t* h, const void* x, void* stream) {
 DMD_API int dmd_stream_push_csr(dmd_stream_t* h, int32_t nnz, const int32_t* idx, const void* val,
                                 void* stream) {
     if (int rc = check_handle(h)) return rc;
-    (void)nnz; (void)idx; (void)val; (void)stream;
-    return fail(DMD_E_UNSUPPORTED, "sparse complex streams are not available in this build");
+    if (!h->cplx) return fail(DMD_E_INVAL, "dense stream: use dmd_stream_push");
+    if (nnz < 0 || nnz > h->max_nnz) return fail(DMD_E_INVAL, "nnz must be in [0, max_nnz=%d] (got %d)", h->max_nnz, nnz);
+    if (nnz > 0 && (!idx || !val)) return fail(DMD_E_INVAL, "null idx or val");
+    if ((uintptr_t)idx % 4 || (uintptr_t)val % 8) return fail(DMD_E_INVAL, "idx must be 4-byte and val 8-byte aligned");
+    DeviceGuard g(h->device);
+    hipStream_t s = as_stream(stream);
+    HIP_TRY(begin(h, s));
+    DevState* st = reinterpret_cast<DevState*>(h->res_dev);
+    hipError_t e = timed("csr_gram", s, [&] {
+        return dmd::launch_csr_push(idx, static_cast<const float2*>(val), nnz, h->n, h->ring_idx, h->ring_val,
+                                    h->ring_nnz, h->max_nnz, h->m, h->scatter, h->flag, h->G, h->partials, st, s);
+    });
+    if (e != hipSuccess) return hip_fail(e, "sparse push launch");
+    if (h->opts.auto_solve)
+        if (int rc = enqueue_solve(h, s)) return rc;
+    HIP_TRY(end(h, s));
+    return DMD_OK;
 }
 
 DMD_API int dmd_stream_push_block(dmd_stream_t* h, const void* X_new, int64_t ldx, int32_t k,
@@ -553,6 +582,16 @@ static int project(dmd_stream_t* h, void* out, int64_t ld, void* stream, bool mo
     DeviceGuard g(h->device);
     hipStream_t s = as_stream(stream);
     HIP_TRY(begin(h, s));
+    if (h->cplx) {
+        HIP_TRY(timed("csr_project", s, [&] {
+            return dmd::launch_csr_project(reinterpret_cast<const DevState*>(h->res_dev), h->ring_idx, h->ring_val,
+                                           h->ring_nnz, h->max_nnz, h->m, modes ? 1 : 0,
+                                           static_cast<const float2*>(modes ? h->Bphi : h->Bpod), h->r,
+                                           static_cast<float2*>(out), ld, h->n, s);
+        }));
+        HIP_TRY(end(h, s));
+        return DMD_OK;
+    }
     dmd::ProjectArgs a{};
     a.st = reinterpret_cast<const DevState*>(h->res_dev);
     a.ring = h->ring;
@@ -584,14 +623,41 @@ DMD_API int dmd_stream_pod(dmd_stream_t* h, void* U, int64_t ld, void* stream) {
 
 DMD_API int dmd_stream_load_window(dmd_stream_t* h, const void* X, int64_t ldx, int32_t ncols, void* stream) {
     if (int rc = check_handle(h)) return rc;
-    (void)X; (void)ldx; (void)ncols; (void)stream;
-    return fail(DMD_E_UNSUPPORTED, "bulk window load is not available in this build");
+    if (h->cplx) return fail(DMD_E_UNSUPPORTED, "bulk window load is for dense streams");
+    if (!X) return fail(DMD_E_INVAL, "null X");
+    if (ncols < 1 || ncols > h->m + 1) return fail(DMD_E_INVAL, "ncols must be in [1, m+1] (got %d)", ncols);
+    if (ldx < h->n) return fail(DMD_E_INVAL, "ldx < n");
+    if ((uintptr_t)X % h->elem_bytes) return fail(DMD_E_INVAL, "X not %d-byte aligned", h->elem_bytes);
+    DeviceGuard g(h->device);
+    hipStream_t s = as_stream(stream);
+    HIP_TRY(begin(h, s));
+    DevState* st = reinterpret_cast<DevState*>(h->res_dev);
+    HIP_TRY(dmd::launch_copy_columns(X, ldx, h->ring, h->ld, h->n, ncols, h->elem_bytes == 8, s));
+    HIP_TRY(timed("gram_full", s, [&] {
+        return dmd::launch_gram_full(h->ring, h->ld, h->n, h->m, h->slots, h->elem_bytes == 8, h->opts.precision,
+                                     ncols, 0, h->gfull, h->G, st, 1, s);
+    }));
+    if (h->opts.auto_solve)
+        if (int rc = enqueue_solve(h, s)) return rc;
+    HIP_TRY(end(h, s));
+    return DMD_OK;
 }
 
 DMD_API int dmd_stream_resync(dmd_stream_t* h, void* stream) {
     if (int rc = check_handle(h)) return rc;
-    (void)stream;
-    return fail(DMD_E_UNSUPPORTED, "Gram resync is not available in this build");
+    if (h->cplx) return fail(DMD_E_UNSUPPORTED, "Gram resync is for dense streams");
+    DeviceGuard g(h->device);
+    hipStream_t s = as_stream(stream);
+    HIP_TRY(begin(h, s));
+    DevState* st = reinterpret_cast<DevState*>(h->res_dev);
+    HIP_TRY(timed("gram_full", s, [&] {
+        return dmd::launch_gram_full(h->ring, h->ld, h->n, h->m, h->slots, h->elem_bytes == 8, h->opts.precision,
+                                     h->m + 1, -1, h->gfull, h->G, st, 2, s);
+    }));
+    if (h->opts.auto_solve)
+        if (int rc = enqueue_solve(h, s)) return rc;
+    HIP_TRY(end(h, s));
+    return DMD_OK;
 }
 
 DMD_API int dmd_stream_info(dmd_stream_t* h, dmd_info_t* info) {
