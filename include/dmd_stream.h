@@ -236,13 +236,66 @@ typedef struct {
 /* Wait for the handle's work and describe it. */
 int dmd_stream_info(dmd_stream_t* h, dmd_info_t* info);
 
+/* ------------------------------------------------------------ batched tick */
+
+/* A batch groups streams so that one tick processes a new snapshot for many
+ * of them with one launch per phase: one Gram pass over all their windows,
+ * one finalize, the Jacobi solves of all streams side by side (one workgroup,
+ * i.e. one CU, per stream), one eig launch and one projection launch.  Only
+ * dense FP32 streams with auto_solve on can join (any m, n, r); their
+ * projections run in FP32.  Results stay per stream: after a tick,
+ * dmd_stream_eigs/svd/atilde/modes of each member return that member's latest
+ * solve exactly as after dmd_stream_push.
+ *
+ * Admission: a batch has an HBM budget; dmd_batch_attach fails with
+ * DMD_E_NOMEM when the stream's device footprint (ring, Gram, workspaces)
+ * would exceed it, so a server admits a new stream only once others have
+ * detached and freed their share. */
+typedef struct dmd_batch dmd_batch_t;
+
+typedef struct {
+    int32_t max_streams;  /* capacity, 1 .. 1024 (0 = 256)                          */
+    int32_t reserved0;    /* must be zero                                            */
+    int64_t hbm_budget;   /* bytes the attached streams may own together
+                             (0 = 90 % of the device memory free at creation)       */
+    int32_t reserved[8];  /* must be zero                                            */
+} dmd_batch_opts_t;
+
+int dmd_batch_opts_init(dmd_batch_opts_t* opts);
+
+/* Create a batch on the current device.  opts may be NULL. */
+int dmd_batch_create(const dmd_batch_opts_t* opts, dmd_batch_t** out);
+
+/* Wait for the batch's ticks and free it (attached streams are not freed). */
+int dmd_batch_destroy(dmd_batch_t* b);
+
+/* Admit a stream (DMD_E_NOMEM over budget, DMD_E_INVAL if already attached or
+ * full, DMD_E_UNSUPPORTED unless dense FP32 with auto_solve on the batch's
+ * device).  Detach returns its footprint to the budget. */
+int dmd_batch_attach(dmd_batch_t* b, dmd_stream_t* h);
+int dmd_batch_detach(dmd_batch_t* b, dmd_stream_t* h);
+
+/* One tick on `stream`: push snapshots[i] (n_i FP32 values, device) into
+ * streams[i] for i < count (attached, pairwise distinct), run every small
+ * solve and, where modes != NULL and modes[i] != NULL, write that stream's
+ * Phi into modes[i] (complex64, leading dimension ld_modes[i] >= n_i).
+ * Equivalent to dmd_stream_push + dmd_stream_modes per stream; asynchronous.
+ * Each member's later calls are ordered after the tick. */
+int dmd_batch_tick(dmd_batch_t* b, int32_t count, dmd_stream_t* const* streams,
+                   const void* const* snapshots, void* const* modes,
+                   const int64_t* ld_modes, void* stream);
+
+/* Attached streams, their total device footprint and the budget. */
+int dmd_batch_info(dmd_batch_t* b, int32_t* nstreams, int64_t* used_bytes,
+                   int64_t* budget);
+
 /* ------------------------------------------------------------ kernel timing */
 
 /* Process-wide per-kernel timing for diagnostics and roofline measurement.
  * When enabled, every kernel launch of every handle is bracketed by HIP events
  * recorded on its launch stream.  Kernel names: "gram_columns", "gram_finalize", "solve_sym",
  * "solve_eig", "project_modes", "project_pod", "csr_gram", "csr_project",
- * "gram_full".
+ * "gram_full", and for batch ticks "batch_gram", "batch_solve", "batch_project".
  * dmd_profile_read waits for the recorded events and returns the number of
  * launches of `kernel` and their summed duration in milliseconds since the
  * last dmd_profile_reset. */

@@ -6,13 +6,13 @@ with ``python -m paper_1612_07875_amd.build``.
 """
 
 from .binding import (
-    Stream, DMDError, load, last_error, LIB_PATH, SIGNATURES, STRING_FUNCS,
+    Stream, Batch, DMDError, load, last_error, LIB_PATH, SIGNATURES, STRING_FUNCS,
     profile_enable, profile_reset, profile_read,
     OK, W_RANK, E_INVAL, E_NOMEM, E_NOT_READY, E_NONFINITE, E_CONVERGENCE, E_DEVICE, E_UNSUPPORTED,
 )
 
 __all__ = [
-    "Stream", "DMDError", "load", "last_error", "LIB_PATH", "SIGNATURES", "STRING_FUNCS",
+    "Stream", "Batch", "DMDError", "load", "last_error", "LIB_PATH", "SIGNATURES", "STRING_FUNCS",
     "profile_enable", "profile_reset", "profile_read",
     "OK", "W_RANK", "E_INVAL", "E_NOMEM", "E_NOT_READY", "E_NONFINITE", "E_CONVERGENCE",
     "E_DEVICE", "E_UNSUPPORTED",

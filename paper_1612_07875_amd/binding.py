@@ -42,6 +42,11 @@ class Opts(ctypes.Structure):
     ]
 
 
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("max_streams", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_int64), ("reserved", ctypes.c_int32 * 8)]
+
+
 class Info(ctypes.Structure):
     _fields_ = [
         ("n", ctypes.c_int64), ("m", ctypes.c_int32), ("r", ctypes.c_int32), ("dtype", ctypes.c_int32),
@@ -76,6 +81,14 @@ SIGNATURES = {
     "dmd_stream_load_window": [_P, _P, _I64, _I32, _P],
     "dmd_stream_resync": [_P, _P],
     "dmd_stream_info": [_P, ctypes.POINTER(Info)],
+    "dmd_batch_opts_init": [ctypes.POINTER(BatchOpts)],
+    "dmd_batch_create": [ctypes.POINTER(BatchOpts), ctypes.POINTER(_P)],
+    "dmd_batch_destroy": [_P],
+    "dmd_batch_attach": [_P, _P],
+    "dmd_batch_detach": [_P, _P],
+    "dmd_batch_tick": [_P, _I32, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                       ctypes.POINTER(_I64), _P],
+    "dmd_batch_info": [_P, _I32P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)],
     "dmd_profile_enable": [ctypes.c_int],
     "dmd_profile_reset": [],
     "dmd_profile_read": [ctypes.c_char_p, ctypes.POINTER(_I64), _DP],
@@ -305,3 +318,69 @@ class Stream:
         if not (out.is_cuda and out.dtype == dt and out.dim() == 2 and out.shape[0] == self.n
                 and out.shape[1] >= self.r and out.stride(0) == 1):
             raise ValueError(f"output must be an (n, >= r) column-major CUDA tensor of {dt}")
+
+
+class Batch:
+    """Many streams advanced together (see dmd_batch_create / dmd_batch_tick)."""
+
+    def __init__(self, max_streams: int = 256, hbm_budget: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libdmdstream needs a HIP GPU; none is available")
+        lib = load()
+        o = BatchOpts()
+        check(lib.dmd_batch_opts_init(ctypes.byref(o)))
+        o.max_streams = int(max_streams)
+        o.hbm_budget = int(hbm_budget)
+        h = _P()
+        check(lib.dmd_batch_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.members = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().dmd_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def attach(self, s: "Stream"):
+        check(load().dmd_batch_attach(self._h, s._h))
+        self.members.append(s)
+
+    def detach(self, s: "Stream"):
+        check(load().dmd_batch_detach(self._h, s._h))
+        self.members.remove(s)
+
+    def info(self):
+        n = ctypes.c_int32(0)
+        used = ctypes.c_int64(0)
+        bud = ctypes.c_int64(0)
+        check(load().dmd_batch_info(self._h, ctypes.byref(n), ctypes.byref(used), ctypes.byref(bud)))
+        return n.value, used.value, bud.value
+
+    def tick(self, streams, snapshots, modes=None, stream=None):
+        k = len(streams)
+        hs = (_P * k)(*[s._h for s in streams])
+        for s, x in zip(streams, snapshots):
+            if not (x.is_cuda and x.dtype == torch.float32 and x.numel() == s.n and x.is_contiguous()):
+                raise ValueError("snapshots must be contiguous float32 CUDA tensors of n elements")
+        xs = (_P * k)(*[x.data_ptr() for x in snapshots])
+        if modes is not None:
+            ms = (_P * k)(*[(o.data_ptr() if o is not None else None) for o in modes])
+            lds = (_I64 * k)(*[(o.stride(1) if o is not None else 0) for o in modes])
+            for s, o in zip(streams, modes):
+                if o is not None:
+                    s._check_out(o, s.mode_dtype)
+        else:
+            ms, lds = None, None
+        return check(load().dmd_batch_tick(self._h, k, hs, xs, ms, lds, _stream_ptr(stream)))

@@ -81,6 +81,22 @@ hipError_t launch_gram_finalize(double* G, const double* partials, int nblk, int
                                 DevState* st, hipStream_t s);
 int gram_push_blocks(int64_t n, int elem_bytes);
 
+// One stream's share of a grouped (batched) push: FP32 data.
+struct GramItem {
+    const void* x;
+    void* ring;
+    int64_t ld, n;
+    int m, x_aligned, nblk, iter;
+    double* partials;
+    double* G;
+    DevState* st;
+};
+// Gram pass and finalize for many streams in two launches; the blocks of item
+// i are blk_start[i] .. blk_start[i+1]-1, with (iter, nblk) from gram_item_shape.
+hipError_t launch_gram_grouped(const GramItem* items, const int* blk_start, int nitems, int total_blocks,
+                               hipStream_t s);
+void gram_item_shape(int64_t n, int* iter, int* nblk);
+
 // Sparse complex snapshot: ingest into the CSR ring (with index checks),
 // Hermitian inner products through a dense scatter vector, fixed-order
 // reduction and Gram update, scatter vector cleared again.
@@ -116,6 +132,10 @@ struct SolveArgs {
 };
 hipError_t launch_solve_sym(const SolveArgs& a, hipStream_t s);
 hipError_t launch_solve_eig(const SolveArgs& a, hipStream_t s);
+// Grouped solves, one workgroup per stream: Jacobi kernels for real windows
+// with m <= 64 (LDS) and m > 64 (global workspace), then the eig kernel for all.
+hipError_t launch_solve_grouped(const SolveArgs* items_lds, int n_lds, const SolveArgs* items_glb, int n_glb,
+                                const SolveArgs* items_all, int n_all, hipStream_t s);
 
 // Tall-skinny projection out = X_sub * B for the ring's logical columns
 // first .. first+m-1 (X' for first = 1, X for first = 0).
@@ -134,6 +154,10 @@ struct ProjectArgs {
     int precision;         // DMD_PREC_* used for float data
 };
 hipError_t launch_project(const ProjectArgs& a, hipStream_t s);
+// Grouped FP32 projections of many streams in one launch.
+hipError_t launch_project_grouped(const ProjectArgs* items, const int* blk_start, int nitems, int total_blocks,
+                                  hipStream_t s);
+int project_item_blocks(int64_t n);
 
 // Sparse projection: out = X_sub * B (complex) into a dense n x r_eff
 // complex64 output (zero outside the window's support).

@@ -182,8 +182,8 @@ const DevState& host_state(const dmd_stream* h) {
     return *reinterpret_cast<const DevState*>(h->res_host);
 }
 
-int enqueue_solve(dmd_stream* h, hipStream_t s) {
-    dmd::SolveArgs a{};
+void fill_solve_args(const dmd_stream* h, dmd::SolveArgs& a) {
+    a = dmd::SolveArgs{};
     a.st = reinterpret_cast<DevState*>(h->res_dev);
     a.G = h->G;
     a.m = h->m;
@@ -208,6 +208,30 @@ int enqueue_solve(dmd_stream* h, hipStream_t s) {
     a.res_block = h->res_dev;
     a.res_host = h->res_host_dev;
     a.res_bytes = (int)h->L.bytes;
+}
+
+void fill_project_args(const dmd_stream* h, dmd::ProjectArgs& a, void* out, int64_t ld, bool modes) {
+    a = dmd::ProjectArgs{};
+    a.st = reinterpret_cast<const DevState*>(h->res_dev);
+    a.ring = h->ring;
+    a.ld = h->ld;
+    a.n = h->n;
+    a.m = h->m;
+    a.slots = h->slots;
+    a.first = modes ? 1 : 0;
+    a.B = modes ? h->Bphi : h->Bpod;
+    a.kmax = h->r;
+    a.cplx_out = modes ? 1 : 0;
+    a.out = out;
+    a.ldo = ld;
+    a.elem_f64 = h->elem_bytes == 8;
+    a.coef_f64 = h->coef_f64;
+    a.precision = h->opts.precision;
+}
+
+int enqueue_solve(dmd_stream* h, hipStream_t s) {
+    dmd::SolveArgs a;
+    fill_solve_args(h, a);
     HIP_TRY(timed("solve_sym", s, [&] { return dmd::launch_solve_sym(a, s); }));
     HIP_TRY(timed("solve_eig", s, [&] { return dmd::launch_solve_eig(a, s); }));
     HIP_TRY(hipEventRecord(h->ev_solved, s));
@@ -592,22 +616,8 @@ static int project(dmd_stream_t* h, void* out, int64_t ld, void* stream, bool mo
         HIP_TRY(end(h, s));
         return DMD_OK;
     }
-    dmd::ProjectArgs a{};
-    a.st = reinterpret_cast<const DevState*>(h->res_dev);
-    a.ring = h->ring;
-    a.ld = h->ld;
-    a.n = h->n;
-    a.m = h->m;
-    a.slots = h->slots;
-    a.first = modes ? 1 : 0;
-    a.B = modes ? h->Bphi : h->Bpod;
-    a.kmax = h->r;
-    a.cplx_out = modes ? 1 : 0;
-    a.out = out;
-    a.ldo = ld;
-    a.elem_f64 = h->elem_bytes == 8;
-    a.coef_f64 = h->coef_f64;
-    a.precision = h->opts.precision;
+    dmd::ProjectArgs a;
+    fill_project_args(h, a, out, ld, modes);
     HIP_TRY(timed(modes ? "project_modes" : "project_pod", s, [&] { return dmd::launch_project(a, s); }));
     HIP_TRY(end(h, s));
     return DMD_OK;
@@ -713,5 +723,251 @@ DMD_API int dmd_profile_read(const char* kernel, int64_t* launches, double* tota
     }
     *launches = cnt;
     *total_ms = tot;
+    return DMD_OK;
+}
+
+// ------------------------------------------------------------------ batches
+
+namespace {
+
+// Per-tick argument tables: one contiguous block, staged in pinned memory and
+// copied to the device before the grouped launches (two copies alternate so
+// that the host never overwrites a table a tick in flight still reads).
+struct TickLayout {
+    size_t gram, gblk, lds, glb, all, proj, pblk, bytes;
+    static TickLayout make(int cap) {
+        TickLayout L;
+        auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+        L.gram = 0;
+        L.gblk = al(L.gram + sizeof(dmd::GramItem) * cap);
+        L.lds = al(L.gblk + sizeof(int) * (cap + 1));
+        L.glb = al(L.lds + sizeof(dmd::SolveArgs) * cap);
+        L.all = al(L.glb + sizeof(dmd::SolveArgs) * cap);
+        L.proj = al(L.all + sizeof(dmd::SolveArgs) * cap);
+        L.pblk = al(L.proj + sizeof(dmd::ProjectArgs) * cap);
+        L.bytes = al(L.pblk + sizeof(int) * (cap + 1));
+        return L;
+    }
+};
+
+}  // namespace
+
+struct dmd_batch {
+    int device = 0;
+    int cap = 0;
+    int64_t budget = 0, used = 0;
+    std::vector<dmd_stream*> members;
+    TickLayout L{};
+    char* host[2] = {nullptr, nullptr};
+    char* dev[2] = {nullptr, nullptr};
+    hipEvent_t done[2] = {nullptr, nullptr};
+    bool used_buf[2] = {false, false};
+    int next = 0;
+    hipEvent_t ev_last = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool has_last = false;
+};
+
+DMD_API int dmd_batch_opts_init(dmd_batch_opts_t* o) {
+    if (!o) return fail(DMD_E_INVAL, "null opts");
+    std::memset(o, 0, sizeof(*o));
+    o->max_streams = 256;
+    return DMD_OK;
+}
+
+static void batch_free(dmd_batch* b) {
+    for (int i = 0; i < 2; ++i) {
+        if (b->host[i]) (void)hipHostFree(b->host[i]);
+        if (b->dev[i]) (void)hipFree(b->dev[i]);
+        if (b->done[i]) (void)hipEventDestroy(b->done[i]);
+    }
+    if (b->ev_last) (void)hipEventDestroy(b->ev_last);
+}
+
+DMD_API int dmd_batch_create(const dmd_batch_opts_t* opts, dmd_batch_t** out) {
+    if (!out) return fail(DMD_E_INVAL, "null output pointer");
+    *out = nullptr;
+    dmd_batch_opts_t o;
+    dmd_batch_opts_init(&o);
+    if (opts) {
+        o = *opts;
+        if (o.reserved0) return fail(DMD_E_INVAL, "opts.reserved0 must be zero");
+        for (int i = 0; i < 8; ++i)
+            if (o.reserved[i]) return fail(DMD_E_INVAL, "opts.reserved must be zero");
+        if (o.max_streams == 0) o.max_streams = 256;
+    }
+    if (o.max_streams < 1 || o.max_streams > 1024) return fail(DMD_E_INVAL, "max_streams must be in [1, 1024]");
+    if (o.hbm_budget < 0) return fail(DMD_E_INVAL, "hbm_budget must be >= 0");
+    dmd_batch* b = new (std::nothrow) dmd_batch();
+    if (!b) return fail(DMD_E_NOMEM, "host allocation failed");
+    if (hipGetDevice(&b->device) != hipSuccess) {
+        delete b;
+        return fail(DMD_E_DEVICE, "no HIP device");
+    }
+    b->cap = o.max_streams;
+    b->budget = o.hbm_budget;
+    if (b->budget == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+            delete b;
+            return fail(DMD_E_DEVICE, "hipMemGetInfo failed");
+        }
+        b->budget = (int64_t)(0.9 * (double)fr);
+    }
+    b->L = TickLayout::make(b->cap);
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        e = hipHostMalloc((void**)&b->host[i], b->L.bytes, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc((void**)&b->dev[i], b->L.bytes);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done[i], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_last, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        batch_free(b);
+        delete b;
+        return fail(DMD_E_NOMEM, "batch tables: %s", hipGetErrorString(e));
+    }
+    *out = b;
+    return DMD_OK;
+}
+
+DMD_API int dmd_batch_destroy(dmd_batch_t* b) {
+    if (!b) return DMD_OK;
+    DeviceGuard g(b->device);
+    if (b->has_last) (void)hipEventSynchronize(b->ev_last);
+    batch_free(b);
+    delete b;
+    return DMD_OK;
+}
+
+DMD_API int dmd_batch_attach(dmd_batch_t* b, dmd_stream_t* h) {
+    if (!b) return fail(DMD_E_INVAL, "null batch");
+    if (int rc = check_handle(h)) return rc;
+    if (h->device != b->device) return fail(DMD_E_UNSUPPORTED, "stream and batch are on different devices");
+    if (h->cplx || h->elem_bytes != 4 || h->coef_f64 || !h->opts.auto_solve)
+        return fail(DMD_E_UNSUPPORTED, "batches take dense FP32 streams with FP32 projections and auto_solve");
+    for (dmd_stream* x : b->members)
+        if (x == h) return fail(DMD_E_INVAL, "stream already attached");
+    if ((int)b->members.size() >= b->cap) return fail(DMD_E_INVAL, "batch is full (%d streams)", b->cap);
+    if (b->used + h->device_bytes > b->budget)
+        return fail(DMD_E_NOMEM, "admission refused: %lld + %lld bytes exceed the budget of %lld",
+                    (long long)b->used, (long long)h->device_bytes, (long long)b->budget);
+    b->members.push_back(h);
+    b->used += h->device_bytes;
+    return DMD_OK;
+}
+
+DMD_API int dmd_batch_detach(dmd_batch_t* b, dmd_stream_t* h) {
+    if (!b) return fail(DMD_E_INVAL, "null batch");
+    if (int rc = check_handle(h)) return rc;
+    for (size_t i = 0; i < b->members.size(); ++i)
+        if (b->members[i] == h) {
+            b->members.erase(b->members.begin() + i);
+            b->used -= h->device_bytes;
+            return DMD_OK;
+        }
+    return fail(DMD_E_INVAL, "stream is not attached");
+}
+
+DMD_API int dmd_batch_info(dmd_batch_t* b, int32_t* nstreams, int64_t* used_bytes, int64_t* budget) {
+    if (!b) return fail(DMD_E_INVAL, "null batch");
+    if (nstreams) *nstreams = (int32_t)b->members.size();
+    if (used_bytes) *used_bytes = b->used;
+    if (budget) *budget = b->budget;
+    return DMD_OK;
+}
+
+DMD_API int dmd_batch_tick(dmd_batch_t* b, int32_t count, dmd_stream_t* const* streams,
+                           const void* const* snapshots, void* const* modes, const int64_t* ld_modes,
+                           void* stream) {
+    if (!b) return fail(DMD_E_INVAL, "null batch");
+    if (count < 0 || count > b->cap) return fail(DMD_E_INVAL, "count must be in [0, %d]", b->cap);
+    if (count == 0) return DMD_OK;
+    if (!streams || !snapshots) return fail(DMD_E_INVAL, "null streams or snapshots");
+    for (int i = 0; i < count; ++i) {
+        dmd_stream* h = streams[i];
+        bool member = false;
+        for (dmd_stream* x : b->members) member |= (x == h);
+        if (!member) return fail(DMD_E_INVAL, "streams[%d] is not attached to the batch", i);
+        for (int j = 0; j < i; ++j)
+            if (streams[j] == h) return fail(DMD_E_INVAL, "streams[%d] appears twice in one tick", i);
+        if (!snapshots[i] || (uintptr_t)snapshots[i] % 4) return fail(DMD_E_INVAL, "snapshots[%d] null or misaligned", i);
+        if (modes && modes[i]) {
+            if (!ld_modes || ld_modes[i] < h->n) return fail(DMD_E_INVAL, "ld_modes[%d] < n", i);
+        }
+    }
+    DeviceGuard g(b->device);
+    hipStream_t s = as_stream(stream);
+    const int buf = b->next;
+    if (b->used_buf[buf]) HIP_TRY(hipEventSynchronize(b->done[buf]));
+    char* H = b->host[buf];
+    char* D = b->dev[buf];
+    auto* gi = reinterpret_cast<dmd::GramItem*>(H + b->L.gram);
+    int* gblk = reinterpret_cast<int*>(H + b->L.gblk);
+    auto* sl = reinterpret_cast<dmd::SolveArgs*>(H + b->L.lds);
+    auto* sg = reinterpret_cast<dmd::SolveArgs*>(H + b->L.glb);
+    auto* sa = reinterpret_cast<dmd::SolveArgs*>(H + b->L.all);
+    auto* pa = reinterpret_cast<dmd::ProjectArgs*>(H + b->L.proj);
+    int* pblk = reinterpret_cast<int*>(H + b->L.pblk);
+    int nl = 0, ng = 0, np = 0, gtot = 0, ptot = 0;
+    for (int i = 0; i < count; ++i) {
+        dmd_stream* h = streams[i];
+        dmd::GramItem& it = gi[i];
+        it = dmd::GramItem{};
+        it.x = snapshots[i];
+        it.ring = h->ring;
+        it.ld = h->ld;
+        it.n = h->n;
+        it.m = h->m;
+        it.x_aligned = ((uintptr_t)snapshots[i] % 16) == 0;
+        dmd::gram_item_shape(h->n, &it.iter, &it.nblk);
+        it.partials = h->partials;
+        it.G = h->G;
+        it.st = reinterpret_cast<DevState*>(h->res_dev);
+        gblk[i] = gtot;
+        gtot += it.nblk;
+        dmd::SolveArgs a;
+        fill_solve_args(h, a);
+        sa[i] = a;
+        if (h->m + (h->m & 1) <= 64) sl[nl++] = a;
+        else sg[ng++] = a;
+        if (modes && modes[i]) {
+            fill_project_args(h, pa[np], modes[i], ld_modes[i], true);
+            pblk[np] = ptot;
+            ptot += dmd::project_item_blocks(h->n);
+            ++np;
+        }
+    }
+    gblk[count] = gtot;
+    pblk[np] = ptot;
+    // order after every member's earlier work and the batch's previous tick
+    for (int i = 0; i < count; ++i) HIP_TRY(begin(streams[i], s));
+    if (b->has_last && b->last_stream != s) HIP_TRY(hipStreamWaitEvent(s, b->ev_last, 0));
+    HIP_TRY(hipMemcpyAsync(D, H, b->L.bytes, hipMemcpyHostToDevice, s));
+    auto* dgi = reinterpret_cast<const dmd::GramItem*>(D + b->L.gram);
+    auto* dgblk = reinterpret_cast<const int*>(D + b->L.gblk);
+    HIP_TRY(timed("batch_gram", s, [&] { return dmd::launch_gram_grouped(dgi, dgblk, count, gtot, s); }));
+    HIP_TRY(timed("batch_solve", s, [&] {
+        return dmd::launch_solve_grouped(reinterpret_cast<const dmd::SolveArgs*>(D + b->L.lds), nl,
+                                         reinterpret_cast<const dmd::SolveArgs*>(D + b->L.glb), ng,
+                                         reinterpret_cast<const dmd::SolveArgs*>(D + b->L.all), count, s);
+    }));
+    if (np > 0)
+        HIP_TRY(timed("batch_project", s, [&] {
+            return dmd::launch_project_grouped(reinterpret_cast<const dmd::ProjectArgs*>(D + b->L.proj),
+                                               reinterpret_cast<const int*>(D + b->L.pblk), np, ptot, s);
+        }));
+    HIP_TRY(hipEventRecord(b->done[buf], s));
+    b->used_buf[buf] = true;
+    b->next ^= 1;
+    for (int i = 0; i < count; ++i) {
+        dmd_stream* h = streams[i];
+        HIP_TRY(hipEventRecord(h->ev_solved, s));
+        h->solve_enqueued = true;
+        HIP_TRY(end(h, s));
+    }
+    b->last_stream = s;
+    b->has_last = true;
+    HIP_TRY(hipEventRecord(b->ev_last, s));
     return DMD_OK;
 }

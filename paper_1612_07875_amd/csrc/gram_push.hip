@@ -72,9 +72,8 @@ __device__ __forceinline__ void load_slab(const T* __restrict__ col, int64_t bas
 constexpr int kFinThreads = 1024;
 constexpr int kFinLanes = 16;  // lanes per column
 
-__global__ __launch_bounds__(kFinThreads)
-void k_gram_finalize(double* __restrict__ G, const double* __restrict__ partials, int nblk, int m,
-                     DevState* __restrict__ st) {
+__device__ void gram_finalize_body(double* __restrict__ G, const double* __restrict__ partials, int nblk, int m,
+                                   DevState* __restrict__ st) {
     const int slots = m + 2;
     const int count = st->count;
     const int oldest = st->oldest;
@@ -125,14 +124,25 @@ void k_gram_finalize(double* __restrict__ G, const double* __restrict__ partials
     }
 }
 
+__global__ __launch_bounds__(kFinThreads)
+void k_gram_finalize(double* __restrict__ G, const double* __restrict__ partials, int nblk, int m,
+                     DevState* __restrict__ st) {
+    gram_finalize_body(G, partials, nblk, m, st);
+}
+
+__global__ __launch_bounds__(kFinThreads)
+void k_gram_finalize_grouped(const GramItem* __restrict__ items) {
+    const GramItem& g = items[blockIdx.x];
+    gram_finalize_body(g.G, g.partials, g.nblk, g.m, g.st);
+}
+
 // One workgroup per slab of kThreads * N * ITER consecutive elements.
 // partials[j * nblk + block] receives the slab's share of <x_j, x_new> for
 // kept column j (window order) and, at j = nkept, of <x_new, x_new>.
 template <typename T, int ITER>
-__global__ __launch_bounds__(kThreads)
-void k_gram_columns(const T* __restrict__ x, T* __restrict__ ring, int64_t ld, int64_t n, int m,
-                    int x_aligned, double* __restrict__ partials, int nblk,
-                    const DevState* __restrict__ st) {
+__device__ void gram_slab(const T* __restrict__ x, T* __restrict__ ring, int64_t ld, int64_t n, int m,
+                          int x_aligned, double* __restrict__ partials, int nblk,
+                          const DevState* __restrict__ st, int blk) {
     constexpr int N = Vec16<T>::N;
     constexpr int SLAB = kThreads * N * ITER;
     using VT = typename Vec16<T>::type;
@@ -144,7 +154,7 @@ void k_gram_columns(const T* __restrict__ x, T* __restrict__ ring, int64_t ld, i
     const int keep0 = (count == m + 1) ? 1 : 0;  // a full window drops its oldest column
     const int nkept = count - keep0;
 
-    const int64_t base = (int64_t)blockIdx.x * SLAB;
+    const int64_t base = (int64_t)blk * SLAB;
     const bool in_range = base + SLAB <= n;
 
     T xv[ITER][N];
@@ -211,9 +221,44 @@ void k_gram_columns(const T* __restrict__ x, T* __restrict__ ring, int64_t ld, i
             double s = red[0][threadIdx.x];
 #pragma unroll
             for (int w = 1; w < kWaves; ++w) s += red[w][threadIdx.x];
-            partials[(int64_t)(j0 + threadIdx.x) * nblk + blockIdx.x] = s;
+            partials[(int64_t)(j0 + threadIdx.x) * nblk + blk] = s;
         }
         __syncthreads();
+    }
+}
+
+template <typename T, int ITER>
+__global__ __launch_bounds__(kThreads)
+void k_gram_columns(const T* __restrict__ x, T* __restrict__ ring, int64_t ld, int64_t n, int m,
+                    int x_aligned, double* __restrict__ partials, int nblk, const DevState* __restrict__ st) {
+    gram_slab<T, ITER>(x, ring, ld, n, m, x_aligned, partials, nblk, st, blockIdx.x);
+}
+
+// Grouped form: one launch covers the new snapshots of many streams; block b
+// belongs to the item i with blk_start[i] <= b < blk_start[i+1].
+__device__ __forceinline__ int find_item(const int* __restrict__ blk_start, int nitems, int b) {
+    int lo = 0, hi = nitems - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (blk_start[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Each item keeps the slab size its stream uses on its own, so a stream's
+// inner products are summed in the same order alone and in a batch.
+__global__ __launch_bounds__(kThreads)
+void k_gram_columns_grouped(const GramItem* __restrict__ items, const int* __restrict__ blk_start, int nitems) {
+    const int i = find_item(blk_start, nitems, blockIdx.x);
+    const GramItem g = items[i];
+    const int blk = blockIdx.x - blk_start[i];
+    const float* x = static_cast<const float*>(g.x);
+    float* ring = static_cast<float*>(g.ring);
+    switch (g.iter) {
+        case 4: gram_slab<float, 4>(x, ring, g.ld, g.n, g.m, g.x_aligned, g.partials, g.nblk, g.st, blk); break;
+        case 2: gram_slab<float, 2>(x, ring, g.ld, g.n, g.m, g.x_aligned, g.partials, g.nblk, g.st, blk); break;
+        default: gram_slab<float, 1>(x, ring, g.ld, g.n, g.m, g.x_aligned, g.partials, g.nblk, g.st, blk); break;
     }
 }
 
@@ -264,6 +309,30 @@ hipError_t launch_gram_columns(const T* x, T* ring, int64_t ld, int64_t n, int m
 hipError_t launch_gram_finalize(double* G, const double* partials, int nblk, int m, DevState* st,
                                 hipStream_t s) {
     hipLaunchKernelGGL(k_gram_finalize, dim3(1), dim3(kFinThreads), 0, s, G, partials, nblk, m, st);
+    return hipGetLastError();
+}
+
+static int stream_iter(int64_t n) {
+    int iter = iter_for<float>(n);
+    if (const char* e = getenv("DMD_GRAM_ITER")) {
+        const int v = atoi(e);
+        if (v == 1 || v == 2 || v == 4) iter = v;
+    }
+    return iter;
+}
+
+void gram_item_shape(int64_t n, int* iter, int* nblk) {
+    *iter = stream_iter(n);
+    *nblk = blocks_for<float>(n, *iter);
+}
+
+hipError_t launch_gram_grouped(const GramItem* items, const int* blk_start, int nitems, int total_blocks,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_gram_columns_grouped, dim3(total_blocks), dim3(kThreads), 0, s, items, blk_start,
+                       nitems);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gram_finalize_grouped, dim3(nitems), dim3(kFinThreads), 0, s, items);
     return hipGetLastError();
 }
 

@@ -51,8 +51,7 @@ template <> struct Acc<double> {
 // the current group's MFMAs run; output tiles go through LDS so that every
 // store instruction writes 64 consecutive rows of one output column.
 template <typename TX, typename T, int NT>
-__global__ __launch_bounds__(kThreads)
-void k_project_mfma(ProjectArgs a) {
+__device__ void project_body(const ProjectArgs& a, int blk) {
     using AccT = typename Acc<T>::type;
     constexpr int KG = sizeof(T) == 8 ? 2 : 4;  // k-steps (of 4 columns) per group
     constexpr int OLD = 17;                // padded row length of the output stage
@@ -69,7 +68,7 @@ void k_project_mfma(ProjectArgs a) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    const int64_t row0 = (int64_t)blockIdx.x * kRowsPerBlock + wave * kRowsPerWave;
+    const int64_t row0 = (int64_t)blk * kRowsPerBlock + wave * kRowsPerWave;
     const int oldest = st->oldest;
     const TX* ring = reinterpret_cast<const TX*>(a.ring);
 
@@ -158,6 +157,28 @@ void k_project_mfma(ProjectArgs a) {
 }
 
 template <typename TX, typename T, int NT>
+__global__ __launch_bounds__(kThreads)
+void k_project_mfma(ProjectArgs a) {
+    project_body<TX, T, NT>(a, blockIdx.x);
+}
+
+// Grouped form over many streams (FP32 ring and coefficients): block b
+// belongs to item i with blk_start[i] <= b < blk_start[i+1].
+template <int NT>
+__global__ __launch_bounds__(kThreads)
+void k_project_grouped(const ProjectArgs* __restrict__ items, const int* __restrict__ blk_start, int nitems) {
+    int lo = 0, hi = nitems - 1;
+    const int b = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (blk_start[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const ProjectArgs a = items[lo];
+    project_body<float, float, NT>(a, b - blk_start[lo]);
+}
+
+template <typename TX, typename T, int NT>
 hipError_t launch_nt(const ProjectArgs& a, hipStream_t s) {
     const unsigned gx = (unsigned)((a.n + kRowsPerBlock - 1) / kRowsPerBlock);
     hipLaunchKernelGGL((k_project_mfma<TX, T, NT>), dim3(gx), dim3(kThreads), 0, s, a);
@@ -173,6 +194,15 @@ hipError_t launch_tiles(const ProjectArgs& a, hipStream_t s, int kc_max) {
 }
 
 }  // namespace
+
+int project_item_blocks(int64_t n) { return (int)((n + kRowsPerBlock - 1) / kRowsPerBlock); }
+
+hipError_t launch_project_grouped(const ProjectArgs* items, const int* blk_start, int nitems, int total_blocks,
+                                  hipStream_t s) {
+    // four 16-column tiles cover every r <= 32
+    hipLaunchKernelGGL(k_project_grouped<4>, dim3(total_blocks), dim3(kThreads), 0, s, items, blk_start, nitems);
+    return hipGetLastError();
+}
 
 hipError_t launch_project(const ProjectArgs& a, hipStream_t s) {
     const int kc_max = a.cplx_out ? 2 * a.kmax : a.kmax;

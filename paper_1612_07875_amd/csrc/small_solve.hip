@@ -160,8 +160,7 @@ template <> __device__ __forceinline__ cplx load_s<cplx>(const double* p, int64_
 // LDS: matrices in dynamic LDS (real, M <= 64); else in the global workspace.
 // PMAX: largest number of rotation pairs per round (M / 2).
 template <typename S, int NT, bool LDS, int PMAX>
-__global__ __launch_bounds__(NT)
-void k_solve_sym(SolveArgs a, int M) {
+__device__ void solve_sym_body(const SolveArgs& a, int M) {
     using SC = Scal<S>;
     extern __shared__ double dyn[];
     const int tid = threadIdx.x;
@@ -494,13 +493,26 @@ void k_solve_sym(SolveArgs a, int M) {
     }
 }
 
+template <typename S, int NT, bool LDS, int PMAX>
+__global__ __launch_bounds__(NT)
+void k_solve_sym(SolveArgs a, int M) {
+    solve_sym_body<S, NT, LDS, PMAX>(a, M);
+}
+
+// Grouped form: one workgroup per stream (independent solves run on separate CUs).
+template <typename S, int NT, bool LDS, int PMAX>
+__global__ __launch_bounds__(NT)
+void k_solve_sym_grouped(const SolveArgs* __restrict__ items) {
+    const SolveArgs a = items[blockIdx.x];
+    solve_sym_body<S, NT, LDS, PMAX>(a, a.m + (a.m & 1));
+}
+
 // --------------------------------------------------------------------------
 // k_solve_eig: one wavefront, A~ (k x k, k <= 32) in LDS
 // --------------------------------------------------------------------------
 constexpr int LDH = kRMax;
 
-__global__ __launch_bounds__(64)
-void k_solve_eig(SolveArgs a) {
+__device__ void solve_eig_body(const SolveArgs& a) {
     const int lane = threadIdx.x;
     DevState* st = a.st;
     const int status0 = st->solve_status;
@@ -861,6 +873,17 @@ void k_solve_eig(SolveArgs a) {
     publish(a);
 }
 
+__global__ __launch_bounds__(64)
+void k_solve_eig(SolveArgs a) {
+    solve_eig_body(a);
+}
+
+__global__ __launch_bounds__(64)
+void k_solve_eig_grouped(const SolveArgs* __restrict__ items) {
+    const SolveArgs a = items[blockIdx.x];
+    solve_eig_body(a);
+}
+
 }  // namespace
 
 hipError_t launch_solve_sym(const SolveArgs& a, hipStream_t s) {
@@ -884,6 +907,31 @@ hipError_t launch_solve_sym(const SolveArgs& a, hipStream_t s) {
 hipError_t launch_solve_eig(const SolveArgs& a, hipStream_t s) {
     if (a.r > kRMax) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_solve_eig, dim3(1), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace dmd
+
+namespace dmd {
+
+hipError_t launch_solve_grouped(const SolveArgs* items_lds, int n_lds, const SolveArgs* items_glb, int n_glb,
+                                const SolveArgs* items_all, int n_all, hipStream_t s) {
+    if (n_lds > 0) {
+        const size_t lds = 3 * sizeof(double) * 64 * 65;  // sized for M <= 64
+        auto kern = k_solve_sym_grouped<double, 1024, true, 32>;
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(n_lds), dim3(1024), lds, s, items_lds);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (n_glb > 0) {
+        hipLaunchKernelGGL((k_solve_sym_grouped<double, 1024, false, kMaxM / 2>), dim3(n_glb), dim3(1024), 0, s,
+                           items_glb);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_solve_eig_grouped, dim3(n_all), dim3(64), 0, s, items_all);
     return hipGetLastError();
 }
 
