@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--latency-frames", type=int, default=40)
-    ap.add_argument("--cpu-windows", type=int, default=3, help="windows in the oracle's timed sample")
+    ap.add_argument("--cpu-windows", type=int, default=4, help="windows in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", action="store_true",
                     help="run the 64-stream serving mix (Poisson arrivals) instead of the single-stream workload")

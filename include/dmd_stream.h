@@ -106,7 +106,10 @@ typedef struct {
                             eigenvectors, rows shifted by one window position
                             (consecutive solves then depend on each other); 0
                             (default): start from the identity                      */
-    int32_t reserved[7]; /* must be zero                                             */
+    int32_t max_block;   /* largest k of dmd_stream_push_block, 1 .. 64 (0 = 1);
+                            dense streams only.  The ring keeps max_block spare
+                            slots and max_block - 1 extra solve workspaces       */
+    int32_t reserved[6]; /* must be zero                                             */
 } dmd_opts_t;
 
 typedef struct dmd_stream dmd_stream_t;
@@ -120,8 +123,9 @@ int dmd_opts_init(dmd_opts_t* opts);
  * window holds m+1 snapshots) and truncation rank r on the current HIP device.
  * Requires n >= 1, 2 <= m <= 256, 1 <= r <= min(m, 32); for DMD_C64_CSR also
  * 1 <= max_nnz <= n.  opts may be NULL (defaults).  Allocates the ring of
- * snapshots (m+2 slots of n elements: the window plus one slot being filled),
- * the (m+2) x (m+2) FP64 Gram and the solve workspaces, all zeroed.
+ * snapshots (m+1+B slots of n elements, B = opts->max_block: the window plus
+ * the slots being filled), the FP64 Gram over those slots and the solve
+ * workspaces, all zeroed.
  * Errors: DMD_E_INVAL, DMD_E_NOMEM, DMD_E_DEVICE.  *out is NULL on error. */
 int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t* opts,
                       dmd_stream_t** out);
@@ -159,12 +163,39 @@ int dmd_stream_push(dmd_stream_t* h, const void* x, void* stream);
 int dmd_stream_push_csr(dmd_stream_t* h, int32_t nnz, const int32_t* idx,
                         const void* val, void* stream);
 
-/* Append k dense snapshots at once: X_new is n x k (device, column-major,
- * leading dimension ldx >= n), 1 <= k <= m+1.  Equivalent to k pushes in
- * column order; the k new Gram columns come from one pass over the window
- * (Sec. 5, updating with more than one column at a time). */
+/* Append k dense snapshots at once (Sec. 5, updating with more than one new
+ * column at a time): X_new is n x k in the stream's dtype (device,
+ * column-major, leading dimension ldx >= n), 1 <= k <= opts.max_block.
+ * Enqueues on `stream`: one pass over the window and X_new that computes the
+ * (count+k) x k block of new inner products on the matrix cores (FP64
+ * products and sums, fixed reduction order) and copies X_new into the ring,
+ * the Gram update, and -- with auto_solve on -- the FP64 small solves of every
+ * window the k single pushes would pass through, run side by side (one CU
+ * each).  Afterwards the stream is in the state k dmd_stream_push calls in
+ * column order would leave (up to the summation order of the inner
+ * products); dmd_stream_eigs/svd/atilde/modes describe the last window and
+ * dmd_stream_block_eigs returns every window's eigenvalues.
+ * Unlike k single pushes, a non-finite inner product anywhere in the block
+ * rejects the whole block (window, Gram and results unchanged; DMD_E_NONFINITE
+ * at the next synchronising call).  Asynchronous.
+ * Errors: DMD_E_INVAL (NULL, k out of range, ldx < n, misaligned),
+ * DMD_E_UNSUPPORTED (sparse stream), DMD_E_DEVICE. */
 int dmd_stream_push_block(dmd_stream_t* h, const void* X_new, int64_t ldx,
                           int32_t k, void* stream);
+
+/* Results of every window of the latest push when it was a block push with
+ * auto_solve on (waits for its solves).  *k receives the block size k.  For
+ * window w < k -- the window that ends at the block's snapshot w, so window
+ * k-1 is the current one -- status[w] receives its status (DMD_OK,
+ * DMD_W_RANK, DMD_E_NOT_READY if the window was not full yet,
+ * DMD_E_CONVERGENCE, or DMD_E_NONFINITE for every window of a rejected block),
+ * r_eff[w] its rank, and lam_re, lam_im and sigma (host, k x ld row-major,
+ * ld >= r) its r_eff[w] leading eigenvalues and singular values at offset
+ * w * ld.  Any pointer except k may be NULL.  Returns DMD_E_NOT_READY if the
+ * latest push was not such a block push, otherwise the status of the current
+ * window as dmd_stream_eigs does. */
+int dmd_stream_block_eigs(dmd_stream_t* h, int32_t* k, double* lam_re, double* lam_im,
+                          double* sigma, int64_t ld, int32_t* r_eff, int32_t* status);
 
 /* ------------------------------------------------------------ small solves (Alg. 1-2) */
 
@@ -295,7 +326,9 @@ int dmd_batch_info(dmd_batch_t* b, int32_t* nstreams, int64_t* used_bytes,
  * When enabled, every kernel launch of every handle is bracketed by HIP events
  * recorded on its launch stream.  Kernel names: "gram_columns", "gram_finalize", "solve_sym",
  * "solve_eig", "project_modes", "project_pod", "csr_gram", "csr_project",
- * "gram_full", and for batch ticks "batch_gram", "batch_solve", "batch_project".
+ * "gram_full", for block pushes "gram_block" (block Gram pass, reduction and
+ * commit) and "block_solve" (all windows' solves), and for batch ticks
+ * "batch_gram", "batch_solve", "batch_project".
  * dmd_profile_read waits for the recorded events and returns the number of
  * launches of `kernel` and their summed duration in milliseconds since the
  * last dmd_profile_reset. */

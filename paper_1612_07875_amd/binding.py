@@ -38,7 +38,7 @@ class Opts(ctypes.Structure):
         ("dtype", ctypes.c_int32), ("precision", ctypes.c_int32), ("max_nnz", ctypes.c_int32),
         ("max_sweeps", ctypes.c_int32), ("max_qr_iter", ctypes.c_int32), ("auto_solve", ctypes.c_int32),
         ("rcond", ctypes.c_double), ("tol", ctypes.c_double), ("warm_start", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 7),
+        ("max_block", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6),
     ]
 
 
@@ -71,6 +71,7 @@ SIGNATURES = {
     "dmd_stream_push": [_P, _P, _P],
     "dmd_stream_push_csr": [_P, _I32, _P, _P, _P],
     "dmd_stream_push_block": [_P, _P, _I64, _I32, _P],
+    "dmd_stream_block_eigs": [_P, _I32P, _DP, _DP, _DP, _I64, _I32P, _I32P],
     "dmd_stream_solve": [_P, _P],
     "dmd_stream_eigs": [_P, _DP, _DP, _DP, _I32P],
     "dmd_stream_svd": [_P, _DP, _DP, _I64, _I32P],
@@ -159,7 +160,8 @@ class Stream:
 
     def __init__(self, n: int, m: int, r: int, dtype: str = "f32", precision: str = "default",
                  auto_solve: bool = True, rcond: Optional[float] = None, tol: float = 0.0,
-                 max_nnz: int = 0, max_sweeps: int = 0, max_qr_iter: int = 0, warm_start: bool = False):
+                 max_nnz: int = 0, max_sweeps: int = 0, max_qr_iter: int = 0, warm_start: bool = False,
+                 max_block: int = 1):
         if not torch.cuda.is_available():
             raise RuntimeError("libdmdstream needs a HIP GPU; none is available")
         lib = load()
@@ -174,10 +176,12 @@ class Stream:
         o.rcond = -1.0 if rcond is None else float(rcond)
         o.tol = float(tol)
         o.warm_start = 1 if warm_start else 0
+        o.max_block = int(max_block)
         h = _P()
         check(lib.dmd_stream_create(int(n), int(m), int(r), ctypes.byref(o), ctypes.byref(h)))
         self._h = h
         self.n, self.m, self.r = int(n), int(m), int(r)
+        self.max_block = int(max_block)
         self.dtype = dtype
         self.precision = precision
         self.elem = {"f32": torch.float32, "f64": torch.float64, "c64_csr": torch.complex64}[dtype]
@@ -234,6 +238,25 @@ class Stream:
             raise ValueError("X must be a (k, n) CUDA tensor with unit stride along n")
         return check(load().dmd_stream_push_block(self._h, X.data_ptr(), X.stride(0), X.shape[0],
                                                   _stream_ptr(stream)))
+
+    def block_eigs(self):
+        """Per window of the latest block push: list of (status, lambda complex128[r_eff],
+        sigma float64[r_eff]); the last entry is the current window.  Also returns the
+        call's own status (that of the current window)."""
+        kb = self.max_block
+        re = np.zeros((kb, self.r))
+        im = np.zeros((kb, self.r))
+        sg = np.zeros((kb, self.r))
+        reff = np.zeros(kb, dtype=np.int32)
+        stat = np.zeros(kb, dtype=np.int32)
+        k = ctypes.c_int32(0)
+        rc = check(load().dmd_stream_block_eigs(self._h, ctypes.byref(k), _dp(re), _dp(im), _dp(sg), self.r,
+                                                reff.ctypes.data_as(_I32P), stat.ctypes.data_as(_I32P)))
+        out = []
+        for w in range(k.value):
+            q = int(reff[w])
+            out.append((int(stat[w]), re[w, :q] + 1j * im[w, :q], sg[w, :q].copy()))
+        return out, rc
 
     def load_window(self, X: torch.Tensor, stream=None) -> int:
         if not (X.is_cuda and X.dtype == self.elem and X.dim() == 2 and X.shape[1] == self.n

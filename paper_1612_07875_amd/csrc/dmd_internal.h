@@ -12,9 +12,10 @@ namespace dmd {
 // sigma and lambda.  Kernels read and update it, so the host can enqueue a
 // whole frame without knowing whether earlier pushes were accepted.
 //
-// The ring holds slots = m+2 snapshots: the window (count <= m+1 snapshots
-// starting at physical slot `oldest`) and one spare slot that the next push
-// fills.  A rejected push therefore never touches the window.
+// The ring holds slots = m+1+B snapshots: the window (count <= m+1 snapshots
+// starting at physical slot `oldest`) and B >= 1 spare slots (B = the largest
+// block push allowed) that the next push or block push fills.  A rejected push
+// therefore never touches the window.
 struct DevState {
     int32_t oldest;             // physical slot of the oldest window snapshot
     int32_t count;              // snapshots in the window (0 .. m+1)
@@ -30,7 +31,8 @@ struct DevState {
     int32_t vprev_push;         // value of `pushes` at that solve
     int32_t warm;               // latest solve was warm-started (1: shifted, 2: same window)
     int32_t skipped;            // latest solve found nothing new and kept the previous results
-    int32_t pad[2];
+    int32_t block_rejected;     // the latest block push was rejected (non-finite inner products)
+    int32_t pad;
 };
 static_assert(sizeof(DevState) == 64, "DevState must stay 64 bytes");
 
@@ -74,10 +76,10 @@ constexpr int kMaxR = 64;    // truncation rank
 // kernel that rejects non-finite results or writes the new Gram row/column
 // and advances the window.
 template <typename T>
-hipError_t launch_gram_columns(const T* x, T* ring, int64_t ld, int64_t n, int m,
+hipError_t launch_gram_columns(const T* x, T* ring, int64_t ld, int64_t n, int m, int slots,
                                double* partials, int nblk_cap, const DevState* st,
                                int* nblk_used, hipStream_t s);
-hipError_t launch_gram_finalize(double* G, const double* partials, int nblk, int m,
+hipError_t launch_gram_finalize(double* G, const double* partials, int nblk, int m, int slots,
                                 DevState* st, hipStream_t s);
 int gram_push_blocks(int64_t n, int elem_bytes);
 
@@ -86,7 +88,7 @@ struct GramItem {
     const void* x;
     void* ring;
     int64_t ld, n;
-    int m, x_aligned, nblk, iter;
+    int m, slots, x_aligned, nblk, iter;
     double* partials;
     double* G;
     DevState* st;
@@ -136,6 +138,34 @@ hipError_t launch_solve_eig(const SolveArgs& a, hipStream_t s);
 // with m <= 64 (LDS) and m > 64 (global workspace), then the eig kernel for all.
 hipError_t launch_solve_grouped(const SolveArgs* items_lds, int n_lds, const SolveArgs* items_glb, int n_glb,
                                 const SolveArgs* items_all, int n_all, hipStream_t s);
+
+// Multi-column update (k new snapshots at once): one pass over the window and
+// the k new columns gives the (count+k) x k block of new inner products on the
+// matrix cores (FP64 products and sums), with the new columns copied into the
+// spare slots in the same pass; a reduction kernel sums the row splits in a
+// fixed order into gblock (leading dimension `slots`) and raises *flag on a
+// non-finite entry; the commit kernel then rejects the whole block or writes
+// the Gram, advances the window by k and prepares the state of every
+// intermediate window (window w < k-1 in shadow state kmax-k+w).
+struct BlockArgs {
+    const void* ring;
+    int64_t ld, n;
+    const void* xnew;
+    int64_t ldx;
+    int m, slots, k, x_aligned;
+    int ntile_i, ntile_j, nsplit;
+    int64_t rows_per_split;
+    double* partial;       // [nsplit][ntile_i * ntile_j][64 * 64]
+    double* gblock;        // slots x k, column-major
+    int* flag;
+    double* G;
+    DevState* st;
+    char* shadow;          // states of the intermediate windows, shadow_stride bytes apart
+    int shadow_stride, kmax;
+};
+hipError_t launch_gram_block(BlockArgs a, int elem_f64, hipStream_t s);
+int gram_block_splits(int m, int kmax);
+int gram_block_tiles(int m, int kmax);
 
 // Tall-skinny projection out = X_sub * B for the ring's logical columns
 // first .. first+m-1 (X' for first = 1, X for first = 0).

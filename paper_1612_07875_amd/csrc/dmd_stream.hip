@@ -124,6 +124,27 @@ struct dmd_stream {
     void* Bphi = nullptr;
     void* Bpod = nullptr;
 
+    // block pushes: up to kmax snapshots at once (ring has kmax spare slots)
+    int kmax = 1;
+    int bsplit_cap = 0;
+    double* bpartial = nullptr;   // per-split partial blocks of new inner products
+    double* gblock = nullptr;     // their fixed-order sums
+    int* bflag = nullptr;         // non-finite flag of the block in flight
+    // one solve set per intermediate window of a block (kmax - 1 sets)
+    size_t sh_stride = 0;         // bytes between results blocks
+    char* sh_dev = nullptr;
+    char* sh_host = nullptr;      // pinned, mapped
+    char* sh_host_dev = nullptr;
+    double* sh_V = nullptr;
+    double* sh_At = nullptr;
+    double* sh_W = nullptr;
+    double* sh_work = nullptr;
+    double* sh_Vfull = nullptr;
+    void* sh_Bphi = nullptr;
+    void* sh_Bpod = nullptr;
+    dmd::SolveArgs* solve_tbl = nullptr;  // device: sets 0 .. kmax-2, then the current window
+    int32_t last_block_k = 0;     // k of the latest push if it was a solved block push, else 0
+
     hipEvent_t ev_last = nullptr;
     hipEvent_t ev_solved = nullptr;
     hipStream_t last_stream = nullptr;
@@ -165,10 +186,13 @@ int dev_alloc(dmd_stream* h, P** p, size_t bytes) {
 
 void free_all(dmd_stream* h) {
     void* bufs[] = {h->ring, h->ring_idx, h->ring_val, h->ring_nnz, h->scatter, h->flag, h->G, h->partials,
-                    h->res_dev, h->V, h->At, h->W, h->work, h->Vfull, h->gfull, h->Bphi, h->Bpod};
+                    h->res_dev, h->V, h->At, h->W, h->work, h->Vfull, h->gfull, h->Bphi, h->Bpod,
+                    h->bpartial, h->gblock, h->bflag, h->sh_dev, h->sh_V, h->sh_At, h->sh_W, h->sh_work,
+                    h->sh_Vfull, h->sh_Bphi, h->sh_Bpod, h->solve_tbl};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (h->res_host) (void)hipHostFree(h->res_host);
+    if (h->sh_host) (void)hipHostFree(h->sh_host);
     if (h->ev_last) (void)hipEventDestroy(h->ev_last);
     if (h->ev_solved) (void)hipEventDestroy(h->ev_solved);
 }
@@ -181,6 +205,21 @@ int check_handle(dmd_stream* h) {
 const DevState& host_state(const dmd_stream* h) {
     return *reinterpret_cast<const DevState*>(h->res_host);
 }
+
+// Sizes (in elements) of one solve set's matrices.
+struct SetSizes {
+    size_t V, At, W, work, Vfull, Bphi, Bpod;  // doubles, except Bphi/Bpod in bytes
+};
+SetSizes set_sizes(const dmd_stream* h) {
+    const size_t cw = h->cplx ? 2 : 1, m = h->m, r = h->r;
+    const size_t M = m + (m & 1);
+    const size_t coef = h->coef_f64 ? 8 : 4;
+    return SetSizes{cw * m * r, cw * r * r, 2 * r * r, cw * 3 * M * (M + 1), cw * m * m, coef * 2 * m * r,
+                    coef * cw * m * r};
+}
+
+// Solve descriptor of intermediate-window set e (0 .. kmax-2) of block pushes.
+void fill_shadow_args(const dmd_stream* h, dmd::SolveArgs& a, int e);
 
 void fill_solve_args(const dmd_stream* h, dmd::SolveArgs& a) {
     a = dmd::SolveArgs{};
@@ -210,6 +249,25 @@ void fill_solve_args(const dmd_stream* h, dmd::SolveArgs& a) {
     a.res_bytes = (int)h->L.bytes;
 }
 
+void fill_shadow_args(const dmd_stream* h, dmd::SolveArgs& a, int e) {
+    fill_solve_args(h, a);
+    const SetSizes z = set_sizes(h);
+    char* res = h->sh_dev + (size_t)e * h->sh_stride;
+    a.st = reinterpret_cast<DevState*>(res);
+    a.warm_start = 0;
+    a.sigma = reinterpret_cast<double*>(res + h->L.sigma_off);
+    a.lam = reinterpret_cast<double*>(res + h->L.lam_off);
+    a.V = h->sh_V + e * z.V;
+    a.At = h->sh_At + e * z.At;
+    a.W = h->sh_W + e * z.W;
+    a.work = h->sh_work + e * z.work;
+    a.Vfull = h->sh_Vfull + e * z.Vfull;
+    a.Bphi = static_cast<char*>(h->sh_Bphi) + e * z.Bphi;
+    a.Bpod = static_cast<char*>(h->sh_Bpod) + e * z.Bpod;
+    a.res_block = res;
+    a.res_host = h->sh_host_dev + (size_t)e * h->sh_stride;
+}
+
 void fill_project_args(const dmd_stream* h, dmd::ProjectArgs& a, void* out, int64_t ld, bool modes) {
     a = dmd::ProjectArgs{};
     a.st = reinterpret_cast<const DevState*>(h->res_dev);
@@ -230,6 +288,7 @@ void fill_project_args(const dmd_stream* h, dmd::ProjectArgs& a, void* out, int6
 }
 
 int enqueue_solve(dmd_stream* h, hipStream_t s) {
+    h->last_block_k = 0;
     dmd::SolveArgs a;
     fill_solve_args(h, a);
     HIP_TRY(timed("solve_sym", s, [&] { return dmd::launch_solve_sym(a, s); }));
@@ -299,7 +358,7 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
     dmd_opts_init(&o);
     if (opts) {
         o = *opts;
-        for (int i = 0; i < 7; ++i)
+        for (int i = 0; i < 6; ++i)
             if (o.reserved[i] != 0) return fail(DMD_E_INVAL, "opts.reserved must be zero");
         if (o.max_sweeps == 0) o.max_sweeps = 40;
         if (o.max_qr_iter == 0) o.max_qr_iter = 60;
@@ -316,6 +375,9 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
     if (o.max_sweeps < 1 || o.max_qr_iter < 1) return fail(DMD_E_INVAL, "iteration limits must be positive");
     if (o.auto_solve != 0 && o.auto_solve != 1) return fail(DMD_E_INVAL, "auto_solve must be 0 or 1");
     if (o.warm_start != 0 && o.warm_start != 1) return fail(DMD_E_INVAL, "warm_start must be 0 or 1");
+    if (o.max_block == 0) o.max_block = 1;
+    if (o.max_block < 1 || o.max_block > 64) return fail(DMD_E_INVAL, "max_block must be in [1, 64] (got %d)", o.max_block);
+    if (o.dtype == DMD_C64_CSR && o.max_block != 1) return fail(DMD_E_UNSUPPORTED, "block pushes are for dense streams");
     if (o.dtype == DMD_C64_CSR) {
         if (o.max_nnz == 0) o.max_nnz = (int32_t)(n < INT32_MAX ? n : INT32_MAX);
         if (o.max_nnz < 1 || o.max_nnz > n) return fail(DMD_E_INVAL, "max_nnz must be in [1, n]");
@@ -331,7 +393,8 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
     h->n = n;
     h->m = m;
     h->r = r;
-    h->slots = m + 2;
+    h->kmax = o.max_block;
+    h->slots = m + 1 + h->kmax;
     h->opts = o;
     h->cplx = (o.dtype == DMD_C64_CSR);
     h->elem_bytes = (o.dtype == DMD_F64) ? 8 : 4;
@@ -361,6 +424,10 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
     } else {
         ALLOC(h->ring, (size_t)h->slots * h->ld * h->elem_bytes);
         ALLOC(h->gfull, sizeof(double) * 64 * 64 * (size_t)dmd::gram_full_tiles(m) * dmd::gram_full_splits(m));
+        h->bsplit_cap = dmd::gram_block_splits(m, h->kmax);
+        ALLOC(h->bpartial, sizeof(double) * (size_t)h->bsplit_cap * h->slots * h->kmax);
+        ALLOC(h->gblock, sizeof(double) * (size_t)h->slots * h->kmax);
+        ALLOC(h->bflag, sizeof(int));
     }
     ALLOC(h->G, sizeof(double) * cw * h->slots * h->slots);
     ALLOC(h->partials, sizeof(double) * cw * (size_t)(m + 2) * h->nblk_cap);
@@ -372,6 +439,30 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
     ALLOC(h->Vfull, sizeof(double) * cw * (size_t)m * m);
     ALLOC(h->Bphi, coef * 2 * (size_t)m * r);
     ALLOC(h->Bpod, coef * cw * (size_t)m * r);
+    h->sh_stride = (h->L.bytes + 255) / 256 * 256;
+    if (h->kmax > 1) {
+        const SetSizes z = set_sizes(h);
+        const size_t ns = (size_t)h->kmax - 1;
+        ALLOC(h->sh_dev, ns * h->sh_stride);
+        ALLOC(h->sh_V, sizeof(double) * ns * z.V);
+        ALLOC(h->sh_At, sizeof(double) * ns * z.At);
+        ALLOC(h->sh_W, sizeof(double) * ns * z.W);
+        ALLOC(h->sh_work, sizeof(double) * ns * z.work);
+        ALLOC(h->sh_Vfull, sizeof(double) * ns * z.Vfull);
+        ALLOC(h->sh_Bphi, ns * z.Bphi);
+        ALLOC(h->sh_Bpod, ns * z.Bpod);
+        if (rc == DMD_OK) {
+            hipError_t e = hipHostMalloc((void**)&h->sh_host, ns * h->sh_stride,
+                                         hipHostMallocMapped | hipHostMallocCoherent);
+            if (e != hipSuccess) rc = fail(DMD_E_NOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+            else std::memset(h->sh_host, 0, ns * h->sh_stride);
+        }
+        if (rc == DMD_OK) {
+            hipError_t e = hipHostGetDevicePointer((void**)&h->sh_host_dev, h->sh_host, 0);
+            if (e != hipSuccess) rc = hip_fail(e, "hipHostGetDevicePointer");
+        }
+    }
+    if (!h->cplx) ALLOC(h->solve_tbl, sizeof(dmd::SolveArgs) * (size_t)h->kmax);
 #undef ALLOC
     if (rc == DMD_OK) {
         hipError_t e = hipHostMalloc((void**)&h->res_host, h->L.bytes, hipHostMallocMapped | hipHostMallocCoherent);
@@ -388,6 +479,13 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
         std::memcpy(h->res_host, &init, sizeof(init));
         hipError_t e = hipMemcpy(h->res_dev, &init, sizeof(init), hipMemcpyHostToDevice);
         if (e != hipSuccess) rc = hip_fail(e, "hipMemcpy(state)");
+    }
+    if (rc == DMD_OK && h->solve_tbl) {
+        std::vector<dmd::SolveArgs> tbl(h->kmax);
+        for (int e = 0; e + 1 < h->kmax; ++e) fill_shadow_args(h, tbl[e], e);
+        fill_solve_args(h, tbl[h->kmax - 1]);
+        hipError_t e = hipMemcpy(h->solve_tbl, tbl.data(), sizeof(dmd::SolveArgs) * tbl.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) rc = hip_fail(e, "hipMemcpy(solve table)");
     }
     if (rc == DMD_OK) {
         hipError_t e = hipEventCreateWithFlags(&h->ev_last, hipEventDisableTiming);
@@ -450,6 +548,7 @@ DMD_API int dmd_stream_reset(dmd_stream_t* h, void* stream) {
     hipLaunchKernelGGL(dmd::k_reset_state, dim3(1), dim3(1), 0, s, reinterpret_cast<DevState*>(h->res_dev));
     HIP_TRY(hipGetLastError());
     h->solve_enqueued = false;
+    h->last_block_k = 0;
     HIP_TRY(end(h, s));
     return DMD_OK;
 }
@@ -467,13 +566,16 @@ DMD_API int dmd_stream_push(dmd_stream_t* h, const void* x, void* stream) {
     hipError_t e = timed("gram_columns", s, [&] {
         if (h->elem_bytes == 8)
             return dmd::launch_gram_columns<double>(static_cast<const double*>(x), static_cast<double*>(h->ring),
-                                                    h->ld, h->n, h->m, h->partials, h->nblk_cap, st, &nblk, s);
+                                                    h->ld, h->n, h->m, h->slots, h->partials, h->nblk_cap, st,
+                                                    &nblk, s);
         return dmd::launch_gram_columns<float>(static_cast<const float*>(x), static_cast<float*>(h->ring), h->ld,
-                                               h->n, h->m, h->partials, h->nblk_cap, st, &nblk, s);
+                                               h->n, h->m, h->slots, h->partials, h->nblk_cap, st, &nblk, s);
     });
     if (e == hipSuccess)
-        e = timed("gram_finalize", s, [&] { return dmd::launch_gram_finalize(h->G, h->partials, nblk, h->m, st, s); });
+        e = timed("gram_finalize", s,
+                  [&] { return dmd::launch_gram_finalize(h->G, h->partials, nblk, h->m, h->slots, st, s); });
     if (e != hipSuccess) return hip_fail(e, "gram push launch");
+    h->last_block_k = 0;
     if (h->opts.auto_solve)
         if (int rc = enqueue_solve(h, s)) return rc;
     HIP_TRY(end(h, s));
@@ -496,6 +598,7 @@ DMD_API int dmd_stream_push_csr(dmd_stream_t* h, int32_t nnz, const int32_t* idx
                                     h->ring_nnz, h->max_nnz, h->m, h->scatter, h->flag, h->G, h->partials, st, s);
     });
     if (e != hipSuccess) return hip_fail(e, "sparse push launch");
+    h->last_block_k = 0;
     if (h->opts.auto_solve)
         if (int rc = enqueue_solve(h, s)) return rc;
     HIP_TRY(end(h, s));
@@ -505,8 +608,76 @@ DMD_API int dmd_stream_push_csr(dmd_stream_t* h, int32_t nnz, const int32_t* idx
 DMD_API int dmd_stream_push_block(dmd_stream_t* h, const void* X_new, int64_t ldx, int32_t k,
                                   void* stream) {
     if (int rc = check_handle(h)) return rc;
-    (void)X_new; (void)ldx; (void)k; (void)stream;
-    return fail(DMD_E_UNSUPPORTED, "block pushes are not available in this build");
+    if (h->cplx) return fail(DMD_E_UNSUPPORTED, "block pushes are for dense streams");
+    if (!X_new) return fail(DMD_E_INVAL, "null X_new");
+    if (k < 1 || k > h->kmax) return fail(DMD_E_INVAL, "k must be in [1, max_block=%d] (got %d)", h->kmax, k);
+    if (ldx < h->n) return fail(DMD_E_INVAL, "ldx < n");
+    if ((uintptr_t)X_new % h->elem_bytes) return fail(DMD_E_INVAL, "X_new not %d-byte aligned", h->elem_bytes);
+    DeviceGuard g(h->device);
+    hipStream_t s = as_stream(stream);
+    HIP_TRY(begin(h, s));
+    dmd::BlockArgs a{};
+    a.ring = h->ring;
+    a.ld = h->ld;
+    a.n = h->n;
+    a.xnew = X_new;
+    a.ldx = ldx;
+    a.m = h->m;
+    a.slots = h->slots;
+    a.k = k;
+    a.x_aligned = ((uintptr_t)X_new % 16 == 0) && ((ldx * h->elem_bytes) % 16 == 0);
+    a.partial = h->bpartial;
+    a.gblock = h->gblock;
+    a.flag = h->bflag;
+    a.G = h->G;
+    a.st = reinterpret_cast<DevState*>(h->res_dev);
+    a.shadow = h->sh_dev;
+    a.shadow_stride = (int)h->sh_stride;
+    a.kmax = h->kmax;
+    HIP_TRY(timed("gram_block", s, [&] { return dmd::launch_gram_block(a, h->elem_bytes == 8, s); }));
+    h->last_block_k = 0;
+    if (h->opts.auto_solve) {
+        const dmd::SolveArgs* t = h->solve_tbl + (h->kmax - k);
+        const bool lds = h->m + (h->m & 1) <= 64;
+        HIP_TRY(timed("block_solve", s,
+                      [&] { return dmd::launch_solve_grouped(t, lds ? k : 0, t, lds ? 0 : k, t, k, s); }));
+        HIP_TRY(hipEventRecord(h->ev_solved, s));
+        h->solve_enqueued = true;
+        h->last_block_k = k;
+    }
+    HIP_TRY(end(h, s));
+    return DMD_OK;
+}
+
+DMD_API int dmd_stream_block_eigs(dmd_stream_t* h, int32_t* k, double* lam_re, double* lam_im, double* sigma,
+                                  int64_t ld, int32_t* r_eff, int32_t* status) {
+    if (int rc = check_handle(h)) return rc;
+    if (!k) return fail(DMD_E_INVAL, "null k");
+    *k = 0;
+    if (h->last_block_k == 0) return fail(DMD_E_NOT_READY, "the latest push was not a solved block push");
+    if ((lam_re || lam_im || sigma) && ld < h->r) return fail(DMD_E_INVAL, "ld < r");
+    DeviceGuard g(h->device);
+    if (int rc = wait_solved(h)) return rc;
+    const int kb = h->last_block_k;
+    *k = kb;
+    for (int w = 0; w < kb; ++w) {
+        const char* res = (w == kb - 1) ? h->res_host : h->sh_host + (size_t)(h->kmax - kb + w) * h->sh_stride;
+        const DevState& st = *reinterpret_cast<const DevState*>(res);
+        const bool rejected = reinterpret_cast<const DevState*>(h->res_host)->block_rejected != 0;
+        int code = st.solve_status;
+        if (rejected) code = DMD_E_NONFINITE;
+        const int re = (code == DMD_OK || code == DMD_W_RANK) ? st.r_eff : 0;
+        if (status) status[w] = code;
+        if (r_eff) r_eff[w] = re;
+        const double* sg = reinterpret_cast<const double*>(res + h->L.sigma_off);
+        const double* lm = reinterpret_cast<const double*>(res + h->L.lam_off);
+        for (int i = 0; i < re; ++i) {
+            if (lam_re) lam_re[w * ld + i] = lm[2 * i];
+            if (lam_im) lam_im[w * ld + i] = lm[2 * i + 1];
+            if (sigma) sigma[w * ld + i] = sg[i];
+        }
+    }
+    return solve_status(h);
 }
 
 DMD_API int dmd_stream_solve(dmd_stream_t* h, void* stream) {
@@ -642,6 +813,7 @@ DMD_API int dmd_stream_load_window(dmd_stream_t* h, const void* X, int64_t ldx, 
     hipStream_t s = as_stream(stream);
     HIP_TRY(begin(h, s));
     DevState* st = reinterpret_cast<DevState*>(h->res_dev);
+    h->last_block_k = 0;
     HIP_TRY(dmd::launch_copy_columns(X, ldx, h->ring, h->ld, h->n, ncols, h->elem_bytes == 8, s));
     HIP_TRY(timed("gram_full", s, [&] {
         return dmd::launch_gram_full(h->ring, h->ld, h->n, h->m, h->slots, h->elem_bytes == 8, h->opts.precision,
@@ -660,6 +832,7 @@ DMD_API int dmd_stream_resync(dmd_stream_t* h, void* stream) {
     hipStream_t s = as_stream(stream);
     HIP_TRY(begin(h, s));
     DevState* st = reinterpret_cast<DevState*>(h->res_dev);
+    h->last_block_k = 0;
     HIP_TRY(timed("gram_full", s, [&] {
         return dmd::launch_gram_full(h->ring, h->ld, h->n, h->m, h->slots, h->elem_bytes == 8, h->opts.precision,
                                      h->m + 1, -1, h->gfull, h->G, st, 2, s);
@@ -919,6 +1092,7 @@ DMD_API int dmd_batch_tick(dmd_batch_t* b, int32_t count, dmd_stream_t* const* s
         it.ld = h->ld;
         it.n = h->n;
         it.m = h->m;
+        it.slots = h->slots;
         it.x_aligned = ((uintptr_t)snapshots[i] % 16) == 0;
         dmd::gram_item_shape(h->n, &it.iter, &it.nblk);
         it.partials = h->partials;
@@ -964,6 +1138,7 @@ DMD_API int dmd_batch_tick(dmd_batch_t* b, int32_t count, dmd_stream_t* const* s
         dmd_stream* h = streams[i];
         HIP_TRY(hipEventRecord(h->ev_solved, s));
         h->solve_enqueued = true;
+        h->last_block_k = 0;
         HIP_TRY(end(h, s));
     }
     b->last_stream = s;

@@ -3,7 +3,7 @@
 //
 // Only the new snapshot's inner products are computed: one pass reads the m
 // kept window columns plus the new snapshot and writes the snapshot into the
-// spare ring slot (ingest fused with the dots), so HBM traffic per push is
+// first spare ring slot (ingest fused with the dots), so HBM traffic per push is
 // (m+2) * n * sizeof(T) bytes.  The shift of the Gram is a change of the
 // ring's `oldest` index, not a copy.
 //
@@ -73,8 +73,7 @@ constexpr int kFinThreads = 1024;
 constexpr int kFinLanes = 16;  // lanes per column
 
 __device__ void gram_finalize_body(double* __restrict__ G, const double* __restrict__ partials, int nblk, int m,
-                                   DevState* __restrict__ st) {
-    const int slots = m + 2;
+                                   int slots, DevState* __restrict__ st) {
     const int count = st->count;
     const int oldest = st->oldest;
     const int spare = slot_of(oldest, count, slots);
@@ -125,29 +124,28 @@ __device__ void gram_finalize_body(double* __restrict__ G, const double* __restr
 }
 
 __global__ __launch_bounds__(kFinThreads)
-void k_gram_finalize(double* __restrict__ G, const double* __restrict__ partials, int nblk, int m,
+void k_gram_finalize(double* __restrict__ G, const double* __restrict__ partials, int nblk, int m, int slots,
                      DevState* __restrict__ st) {
-    gram_finalize_body(G, partials, nblk, m, st);
+    gram_finalize_body(G, partials, nblk, m, slots, st);
 }
 
 __global__ __launch_bounds__(kFinThreads)
 void k_gram_finalize_grouped(const GramItem* __restrict__ items) {
     const GramItem& g = items[blockIdx.x];
-    gram_finalize_body(g.G, g.partials, g.nblk, g.m, g.st);
+    gram_finalize_body(g.G, g.partials, g.nblk, g.m, g.slots, g.st);
 }
 
 // One workgroup per slab of kThreads * N * ITER consecutive elements.
 // partials[j * nblk + block] receives the slab's share of <x_j, x_new> for
 // kept column j (window order) and, at j = nkept, of <x_new, x_new>.
 template <typename T, int ITER>
-__device__ void gram_slab(const T* __restrict__ x, T* __restrict__ ring, int64_t ld, int64_t n, int m,
+__device__ void gram_slab(const T* __restrict__ x, T* __restrict__ ring, int64_t ld, int64_t n, int m, int slots,
                           int x_aligned, double* __restrict__ partials, int nblk,
                           const DevState* __restrict__ st, int blk) {
     constexpr int N = Vec16<T>::N;
     constexpr int SLAB = kThreads * N * ITER;
     using VT = typename Vec16<T>::type;
 
-    const int slots = m + 2;
     const int count = st->count;
     const int oldest = st->oldest;
     const int spare = slot_of(oldest, count, slots);
@@ -229,9 +227,9 @@ __device__ void gram_slab(const T* __restrict__ x, T* __restrict__ ring, int64_t
 
 template <typename T, int ITER>
 __global__ __launch_bounds__(kThreads)
-void k_gram_columns(const T* __restrict__ x, T* __restrict__ ring, int64_t ld, int64_t n, int m,
+void k_gram_columns(const T* __restrict__ x, T* __restrict__ ring, int64_t ld, int64_t n, int m, int slots,
                     int x_aligned, double* __restrict__ partials, int nblk, const DevState* __restrict__ st) {
-    gram_slab<T, ITER>(x, ring, ld, n, m, x_aligned, partials, nblk, st, blockIdx.x);
+    gram_slab<T, ITER>(x, ring, ld, n, m, slots, x_aligned, partials, nblk, st, blockIdx.x);
 }
 
 // Grouped form: one launch covers the new snapshots of many streams; block b
@@ -256,9 +254,9 @@ void k_gram_columns_grouped(const GramItem* __restrict__ items, const int* __res
     const float* x = static_cast<const float*>(g.x);
     float* ring = static_cast<float*>(g.ring);
     switch (g.iter) {
-        case 4: gram_slab<float, 4>(x, ring, g.ld, g.n, g.m, g.x_aligned, g.partials, g.nblk, g.st, blk); break;
-        case 2: gram_slab<float, 2>(x, ring, g.ld, g.n, g.m, g.x_aligned, g.partials, g.nblk, g.st, blk); break;
-        default: gram_slab<float, 1>(x, ring, g.ld, g.n, g.m, g.x_aligned, g.partials, g.nblk, g.st, blk); break;
+        case 4: gram_slab<float, 4>(x, ring, g.ld, g.n, g.m, g.slots, g.x_aligned, g.partials, g.nblk, g.st, blk); break;
+        case 2: gram_slab<float, 2>(x, ring, g.ld, g.n, g.m, g.slots, g.x_aligned, g.partials, g.nblk, g.st, blk); break;
+        default: gram_slab<float, 1>(x, ring, g.ld, g.n, g.m, g.slots, g.x_aligned, g.partials, g.nblk, g.st, blk); break;
     }
 }
 
@@ -286,7 +284,7 @@ int gram_push_blocks(int64_t n, int elem_bytes) {
 }
 
 template <typename T>
-hipError_t launch_gram_columns(const T* x, T* ring, int64_t ld, int64_t n, int m, double* partials,
+hipError_t launch_gram_columns(const T* x, T* ring, int64_t ld, int64_t n, int m, int slots, double* partials,
                                int nblk_cap, const DevState* st, int* nblk_used, hipStream_t s) {
     int iter = iter_for<T>(n);
     if (const char* e = getenv("DMD_GRAM_ITER")) {
@@ -299,16 +297,16 @@ hipError_t launch_gram_columns(const T* x, T* ring, int64_t ld, int64_t n, int m
     const int x_aligned = ((uintptr_t)x % 16) == 0;
     dim3 grid(nblk), block(kThreads);
     switch (iter) {
-        case 4: hipLaunchKernelGGL((k_gram_columns<T, 4>), grid, block, 0, s, x, ring, ld, n, m, x_aligned, partials, nblk, st); break;
-        case 2: hipLaunchKernelGGL((k_gram_columns<T, 2>), grid, block, 0, s, x, ring, ld, n, m, x_aligned, partials, nblk, st); break;
-        default: hipLaunchKernelGGL((k_gram_columns<T, 1>), grid, block, 0, s, x, ring, ld, n, m, x_aligned, partials, nblk, st); break;
+        case 4: hipLaunchKernelGGL((k_gram_columns<T, 4>), grid, block, 0, s, x, ring, ld, n, m, slots, x_aligned, partials, nblk, st); break;
+        case 2: hipLaunchKernelGGL((k_gram_columns<T, 2>), grid, block, 0, s, x, ring, ld, n, m, slots, x_aligned, partials, nblk, st); break;
+        default: hipLaunchKernelGGL((k_gram_columns<T, 1>), grid, block, 0, s, x, ring, ld, n, m, slots, x_aligned, partials, nblk, st); break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_gram_finalize(double* G, const double* partials, int nblk, int m, DevState* st,
+hipError_t launch_gram_finalize(double* G, const double* partials, int nblk, int m, int slots, DevState* st,
                                 hipStream_t s) {
-    hipLaunchKernelGGL(k_gram_finalize, dim3(1), dim3(kFinThreads), 0, s, G, partials, nblk, m, st);
+    hipLaunchKernelGGL(k_gram_finalize, dim3(1), dim3(kFinThreads), 0, s, G, partials, nblk, m, slots, st);
     return hipGetLastError();
 }
 
@@ -336,9 +334,9 @@ hipError_t launch_gram_grouped(const GramItem* items, const int* blk_start, int 
     return hipGetLastError();
 }
 
-template hipError_t launch_gram_columns<float>(const float*, float*, int64_t, int64_t, int, double*, int,
+template hipError_t launch_gram_columns<float>(const float*, float*, int64_t, int64_t, int, int, double*, int,
                                                const DevState*, int*, hipStream_t);
-template hipError_t launch_gram_columns<double>(const double*, double*, int64_t, int64_t, int, double*, int,
+template hipError_t launch_gram_columns<double>(const double*, double*, int64_t, int64_t, int, int, double*, int,
                                                 const DevState*, int*, hipStream_t);
 
 }  // namespace dmd

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_opts_struct_matches_header_layout():
-    # 6 int32 + 2 double + warm_start + 7 int32 reserved
+    # 6 int32 + 2 double + warm_start + max_block + 6 int32 reserved
     assert ctypes.sizeof(binding.Opts) == 6 * 4 + 2 * 8 + 8 * 4
     lib = dmd.load()
     o = binding.Opts()
@@ -86,3 +86,20 @@ def test_null_handle_calls_fail_cleanly():
 
 def test_version_string():
     assert b"gfx950" in dmd.load().dmd_version()
+
+
+@pytest.mark.parametrize("dtype,max_block,code,msg", [
+    (0, 65, dmd.E_INVAL, "max_block must be"),
+    (0, -1, dmd.E_INVAL, "max_block must be"),
+    (2, 2, dmd.E_UNSUPPORTED, "block pushes are for dense"),
+])
+def test_create_rejects_bad_block_options_without_gpu(dtype, max_block, code, msg):
+    lib = dmd.load()
+    o = binding.Opts()
+    lib.dmd_opts_init(ctypes.byref(o))
+    o.dtype = dtype
+    o.max_block = max_block
+    h = ctypes.c_void_p()
+    rc = lib.dmd_stream_create(1000, 8, 4, ctypes.byref(o), ctypes.byref(h))
+    assert rc == code
+    assert msg in dmd.last_error()

@@ -1,0 +1,211 @@
+"""Multi-column updates (Sec. 5: more than one new column per update).
+
+A block push of k snapshots must leave the stream as k single pushes would,
+and every window the block passes through is solved.  Each is compared with
+the FP64 oracle on the same frames.
+
+Tolerances: the block's inner products are exact products summed in FP64 in
+another order than the one-column update, so the Gram bound of the dense path
+applies (|dG_ij| <= 1e-12 sqrt(G_ii G_jj)); sigma, lambda and Phi as in the
+dense tests (sigma_k: 1e-11 + 1e-13 (sigma_1/sigma_k)^2, lambda 1e-8, Phi 1e-8
+with FP64 projections, 2e-4 with FP32 projections).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from oracle import metrics
+from test_gpu_dense import check_gram, check_window, sigma_tol
+
+pytestmark = pytest.mark.gpu
+
+BLOCKS = [3, 5, 5, 4, 1, 5, 2, 5]
+
+
+def _dmd():
+    import paper_1612_07875_amd as dmd
+    return dmd
+
+
+def check_eigs(stat, lam, sig, W, m, r):
+    ref = oracle.exact_dmd(oracle.as_fp64(W[:, :m]), oracle.as_fp64(W[:, 1:]), r)
+    assert stat in (0, 1), stat
+    k = lam.size
+    assert k == ref.r_eff, (k, ref.r_eff)
+    err_s = metrics.sigma_relerr(sig, ref.sigma[:k])
+    assert np.all(err_s <= sigma_tol(ref.sigma[:k])), err_s
+    err_l, _ = metrics.eig_relerr(lam, ref.lam)
+    assert err_l.max() < 1e-8, err_l.max()
+
+
+def run_blocks(s, X, frames, blocks, m, r, phi_tol, every_window=True):
+    """Push X (T, n) in blocks; check the Gram after each block, every solved
+    window of each block and the current window's matrices and modes."""
+    dmd = _dmd()
+    t = 0
+    for k in blocks:
+        s.push_block(X[t:t + k])
+        t += k
+        check_gram(s, frames[:, max(0, t - 1 - m):t])
+        if t < m + 1:
+            with pytest.raises(dmd.DMDError) as ei:
+                s.block_eigs()
+            assert ei.value.code == dmd.E_NOT_READY
+            continue
+        wins, rc = s.block_eigs()
+        assert len(wins) == k and rc in (0, 1)
+        for w, (stat, lam, sig) in enumerate(wins):
+            te = t - k + w  # newest frame of window w
+            if te < m:
+                assert stat == dmd.E_NOT_READY
+            elif every_window or w == 0:
+                check_eigs(stat, lam, sig, frames[:, te - m:te + 1], m, r)
+        # the last window is the current one: identical to eigs()
+        lam_c, sig_c, _ = s.eigs()
+        assert np.array_equal(lam_c, wins[-1][1]) and np.array_equal(sig_c, wins[-1][2])
+        check_window(s, frames[:, t - 1 - m:t], m, r, phi_tol=phi_tol)
+
+
+@pytest.mark.parametrize("n", [4133, 1000])
+def test_block_fp64_every_window(n):
+    dmd = _dmd()
+    m, r = 16, 6
+    frames = gen.ModalStream(n=n, noise=1e-3).frames(0, sum(BLOCKS))
+    X = torch.from_numpy(frames.T.copy()).cuda()
+    with dmd.Stream(n, m, r, dtype="f64", max_block=5) as s:
+        run_blocks(s, X, frames, BLOCKS, m, r, phi_tol=1e-8)
+
+
+@pytest.mark.parametrize("aligned", [True, False])
+def test_block_fp32_video_every_window(aligned):
+    """Odd m, ragged n, k up to 16; unaligned columns (odd leading dimension) too."""
+    dmd = _dmd()
+    H, W, m, r = 100, 130, 37, 12
+    n = H * W
+    blocks = [16, 16, 7, 16, 1, 11]
+    frames = gen.BlobVideo(height=H, width=W, blob_sigma=4.0).frames(0, sum(blocks))
+    if aligned:
+        X = torch.from_numpy(frames.T.copy()).cuda()
+    else:
+        buf = torch.zeros((frames.shape[1], n + 1), dtype=torch.float32, device="cuda")
+        buf[:, :n] = torch.from_numpy(frames.T.copy()).cuda()
+        X = buf[:, :n]
+        assert X.stride(0) == n + 1
+    with dmd.Stream(n, m, r, max_block=16) as s:
+        run_blocks(s, X, frames, blocks, m, r, phi_tol=2e-4)
+
+
+def test_block_matches_single_pushes():
+    """Blocks and single pushes of the same frames: same windows, same results
+    up to the summation order of the inner products."""
+    dmd = _dmd()
+    n, m, r, kb = 20000, 64, 20, 16
+    frames = gen.BlobVideo(height=100, width=200, blob_sigma=5.0).frames(0, 8 * kb + 1)
+    X = torch.from_numpy(frames.T.copy()).cuda()
+    T = X.shape[0]
+    with dmd.Stream(n, m, r) as a, dmd.Stream(n, m, r, max_block=kb) as b:
+        singles = {}
+        for t in range(T):
+            a.push(X[t])
+            if t >= m:
+                singles[t] = a.eigs()
+        t = 0
+        while t < T:
+            k = min(kb, T - t)
+            b.push_block(X[t:t + k])
+            t += k
+            if t >= m + 1:
+                wins, _ = b.block_eigs()
+                for w, (stat, lam, sig) in enumerate(wins):
+                    te = t - k + w
+                    if te < m:
+                        continue
+                    lam_a, sig_a, _ = singles[te]
+                    assert lam.size == lam_a.size
+                    assert np.all(np.abs(sig - sig_a) <= sigma_tol(sig_a) * sig_a)
+                    err, _ = metrics.eig_relerr(lam, lam_a)
+                    assert err.max() < 1e-8
+        Ga, Gb = a.gram(), b.gram()
+        d = np.sqrt(np.outer(np.diag(Ga), np.diag(Ga)))
+        assert np.all(np.abs(Ga - Gb) <= 1e-13 * d)
+        # a single push after blocks continues the same window
+        x = torch.from_numpy(gen.BlobVideo(height=100, width=200, blob_sigma=5.0).frame(T)).cuda()
+        a.push(x)
+        b.push(x)
+        with pytest.raises(dmd.DMDError) as ei:
+            b.block_eigs()
+        assert ei.value.code == dmd.E_NOT_READY
+        la, sa, _ = a.eigs()
+        lb, sb, _ = b.eigs()
+        assert metrics.eig_relerr(lb, la)[0].max() < 1e-8
+
+
+def test_block_with_nonfinite_rejected_whole():
+    dmd = _dmd()
+    g = gen.ModalStream(n=2048, noise=1e-3)
+    m, r = 8, 4
+    frames = g.frames(0, 16)
+    X = torch.from_numpy(frames.T.copy()).cuda()
+    with dmd.Stream(2048, m, r, dtype="f64", max_block=4) as s:
+        for t in range(10):
+            s.push(X[t])
+        G0 = s.gram()
+        lam0, sig0, _ = s.eigs()
+        bad = X[10:13].clone()
+        bad[1, 77] = float("inf")
+        s.push_block(bad)
+        with pytest.raises(dmd.DMDError) as ei:
+            s.sync()
+        assert ei.value.code == dmd.E_NONFINITE
+        assert np.array_equal(s.gram(), G0)
+        wins, _ = s.block_eigs()
+        assert [w[0] for w in wins] == [dmd.E_NONFINITE] * 3
+        lam1, sig1, _ = s.eigs()
+        assert np.array_equal(lam0, lam1) and np.array_equal(sig0, sig1)
+        s.push_block(X[10:13])           # the same frames without the bad value
+        wins, _ = s.block_eigs()
+        for w, (stat, lam, sig) in enumerate(wins):
+            te = 10 + w
+            check_eigs(stat, lam, sig, frames[:, te - m:te + 1], m, r)
+        check_window(s, frames[:, 13 - 1 - m:13], m, r, phi_tol=1e-8)
+
+
+def test_block_argument_errors():
+    dmd = _dmd()
+    with dmd.Stream(1000, 8, 4, max_block=3) as s:
+        X = torch.zeros((4, 1000), device="cuda")
+        with pytest.raises(dmd.DMDError) as ei:
+            s.push_block(X)
+        assert ei.value.code == dmd.E_INVAL
+        with pytest.raises(dmd.DMDError) as ei:
+            s.block_eigs()
+        assert ei.value.code == dmd.E_NOT_READY
+    with dmd.Stream(1000, 8, 4, dtype="c64_csr", max_nnz=16) as s:
+        Xc = torch.zeros((1, 1000), dtype=torch.complex64, device="cuda")
+        with pytest.raises(dmd.DMDError) as ei:
+            s.push_block(Xc)
+        assert ei.value.code == dmd.E_UNSUPPORTED
+
+
+def test_block_full_hd_video():
+    """1920 x 1080 FP32 frames, m = 64, r = 20, blocks of 16: the Gram of the
+    window and the first, a middle and the last window of the last block."""
+    dmd = _dmd()
+    H, W, m, r, kb = 1080, 1920, 64, 20, 16
+    n = H * W
+    v = gen.BlobVideo(height=H, width=W)
+    T = 5 * kb
+    frames = v.frames(0, T)
+    X = torch.from_numpy(frames.T.copy()).cuda()
+    with dmd.Stream(n, m, r, max_block=kb) as s:
+        for t in range(0, T, kb):
+            s.push_block(X[t:t + kb])
+        wins, _ = s.block_eigs()
+        check_gram(s, frames[:, T - 1 - m:T])
+        for w in (0, kb // 2, kb - 1):
+            te = T - kb + w
+            stat, lam, sig = wins[w]
+            check_eigs(stat, lam, sig, frames[:, te - m:te + 1], m, r)
