@@ -23,6 +23,9 @@ LAPACK routines as the only library steps:
                             streaming CPU baseline.
 * :mod:`oracle.metrics`  -- error metrics (singular-value relative error,
                             matched eigenvalue error, mode angles).
+* :mod:`oracle.background` -- mode amplitudes b = (W Lambda)^-1 alpha_1 and
+                            the background/foreground split of the newest
+                            snapshot (Sec. 3.3, Algorithm 3).
 
 Readings of the paper that this oracle fixes (where the paper is silent):
 the window holds m+1 snapshots (X = first m, X' = last m); rank truncation
@@ -38,9 +41,10 @@ from .dmd import (
     dmd_from_gram, densify,
 )
 from . import metrics
+from . import background
 
 __all__ = [
     "as_fp64", "gram", "mos_svd", "exact_dmd", "StreamingMoS", "DMDResult",
     "canonical_columns", "sort_eigs", "r_effective", "default_rcond", "pod_modes",
-    "dmd_from_gram", "densify", "metrics",
+    "dmd_from_gram", "densify", "metrics", "background",
 ]
