@@ -5,12 +5,17 @@ Workload: synthetic blob video, 1920 x 1080 greyscale FP32 frames
 (n = 2,073,600), window m = 64, truncation rank r = 20.  Frames are generated
 on the host and copied to HBM before timing.
 
-One step = one window update of the whole hot path, through the C ABI:
-  push   -- ingest of the new frame and its m+1 inner products with the window
-            (FP64 accumulation), Gram update;
-  solve  -- FP64 Jacobi eig of X^* X, sigma, A~, Hessenberg-QR eig of A~,
-            projection coefficients (all on the GPU);
-  modes  -- Phi = X' V Sigma^-1 W (n x r complex64) into a resident buffer.
+Every window update runs the whole hot path through the C ABI:
+  ingest + Gram -- the new frame(s) and their inner products with the window
+                   (FP64 accumulation), Gram update;
+  solve         -- FP64 Jacobi eig of X^* X, sigma, A~, Hessenberg-QR eig of
+                   A~, projection coefficients (all on the GPU);
+  modes         -- Phi = X' V Sigma^-1 W (n x r complex64) into a resident buffer.
+
+--mode block (default): one step = one push of k frames (multi-column update,
+  Sec. 5) whose k windows are all solved (side by side) and projected; the
+  value counts k window updates per step.
+--mode single: one step = one frame.
 
 Prints one JSON line (see the repository's benchmark contract).
 """
@@ -29,14 +34,20 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 H, W, M, R = 1080, 1920, 64, 20
+COPY_BYTES = 1 << 30
 
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--latency-frames", type=int, default=40)
+    ap.add_argument("--mode", choices=("block", "single"), default="block",
+                    help="block: k frames per step (multi-column update, every window solved and projected); "
+                         "single: one frame per step")
+    ap.add_argument("--block", type=int, default=32, help="frames per block in block mode (1..64)")
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 20 blocks / 100 frames)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 2 blocks / 10 frames)")
+    ap.add_argument("--latency-frames", type=int, default=40, help="single-frame pushes timed one by one")
+    ap.add_argument("--latency-blocks", type=int, default=5, help="block mode: blocks timed one by one")
     ap.add_argument("--cpu-windows", type=int, default=4, help="windows in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", action="store_true",
@@ -44,7 +55,42 @@ def parse():
     ap.add_argument("--serve-streams", type=int, default=64)
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="aggregate frames/s")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain device copy of 1 GiB (5 times) and print its bandwidth: the "
+                         "calibration kernel for the HBM byte counters")
     return ap.parse_args()
+
+
+def copy_probe():
+    """A plain copy of COPY_BYTES (read COPY_BYTES, write COPY_BYTES) per launch."""
+    import torch
+    torch.cuda.set_device(0)
+    x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(5):
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    best = min(times)
+    print(json.dumps({"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES, "launches": 6,
+                      "best_us": round(best * 1e6, 1),
+                      "copy_GBps": round(2 * COPY_BYTES / best / 1e9, 1)}), flush=True)
+
+
+def defaults(args):
+    if args.steps is None:
+        args.steps = 20 if args.mode == "block" else 100
+    if args.warmup is None:
+        args.warmup = 2 if args.mode == "block" else 10
+    if not 1 <= args.block <= 64:
+        raise SystemExit("--block must be in [1, 64]")
+    return args
 
 
 def kernel_source_hash(name: str) -> str:
@@ -165,39 +211,91 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
-def main():
-    args = parse()
-    if args.serve and args.gpus == 1:
-        serve_bench(args)
-        return
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(sharding is described in DESIGN.md); use --gpus 1", file=sys.stderr)
-        sys.exit(2)
+def make_frames(T, keep):
+    """T frames of the blob video on the device (generated on the host in
+    parallel, outside any timed region); the first `keep` also kept on the host."""
+    from concurrent.futures import ThreadPoolExecutor
 
-    import numpy as np
     import torch
 
     import gen
-    import paper_1612_07875_amd as dmd
 
-    torch.cuda.set_device(0)
     n = H * W
-    K, Wu, L = args.steps, args.warmup, args.latency_frames
-    T = M + 1 + Wu + K + L
     video = gen.BlobVideo(height=H, width=W)
     frames = torch.empty((T, n), dtype=torch.float32, device="cuda")
     host_keep = []
-    keep = M + 1 + (args.cpu_windows if not args.no_cpu_baseline else 0)
     t_gen = time.perf_counter()
-    for t in range(T):
-        f = video.frame(t)
-        frames[t].copy_(torch.from_numpy(f))
-        if t < keep:
-            host_keep.append(f)
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        for t0 in range(0, T, 64):
+            chunk = list(ex.map(video.frame, range(t0, min(T, t0 + 64))))
+            for i, f in enumerate(chunk):
+                frames[t0 + i].copy_(torch.from_numpy(f))
+                if t0 + i < keep:
+                    host_keep.append(f)
     torch.cuda.synchronize()
-    t_gen = time.perf_counter() - t_gen
-    print(f"[bench] generated {T} frames in {t_gen:.1f} s", file=sys.stderr, flush=True)
+    print(f"[bench] generated {T} frames in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    return frames, host_keep
+
+
+def kernel_table(dmd, names):
+    out = {}
+    for name in names:
+        cnt, ms = dmd.profile_read(name)
+        if cnt:
+            out[name] = {"launches": cnt, "avg_us": 1000.0 * ms / cnt}
+    return out
+
+
+def roofline_of(kernels, bytes_per, source_of):
+    """Roofline of the dominant HBM-streaming kernel (longest average launch)."""
+    dom = max(bytes_per, key=lambda k: kernels.get(k, {}).get("avg_us", 0.0))
+    avg_s = kernels[dom]["avg_us"] * 1e-6
+    achieved = bytes_per[dom] / avg_s / 1e9
+    for k in bytes_per:
+        if k in kernels:
+            kernels[k]["algorithmic_bytes"] = bytes_per[k]
+            kernels[k]["algorithmic_GBps"] = round(bytes_per[k] / (kernels[k]["avg_us"] * 1e-6) / 1e9, 1)
+    return {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(dom, source_of[dom]),
+        "kernel": dom, "algorithmic_bytes_per_launch": bytes_per[dom],
+        "avg_launch_us": round(kernels[dom]["avg_us"], 2),
+    }
+
+
+def single_latency(s, frames, t, L, phi):
+    import numpy as np
+    import torch
+    lat = []
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    for _ in range(L):
+        e0.record()
+        s.push(frames[t])
+        s.modes(phi)
+        e1.record()
+        e1.synchronize()
+        lat.append(e0.elapsed_time(e1))
+        t += 1
+    if not lat:
+        return None, t
+    lat = np.array(lat)
+    return {"p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4),
+            "frames": int(L)}, t
+
+
+def bench_single(args):
+    """One frame per step: push + FP64 solves + modes of that window."""
+    import numpy as np
+    import torch
+
+    import paper_1612_07875_amd as dmd
+
+    n = H * W
+    K, Wu, L = args.steps, args.warmup, args.latency_frames
+    T = M + 1 + Wu + K + L
+    keep = M + 1 + (args.cpu_windows if not args.no_cpu_baseline else 0)
+    frames, host_keep = make_frames(T, keep)
 
     s = dmd.Stream(n, M, R, dtype="f32")
     phi = torch.zeros((R, n), dtype=torch.complex64, device="cuda").T
@@ -209,8 +307,6 @@ def main():
         s.modes(phi)
         t += 1
     torch.cuda.synchronize()
-    lam, sig, rc = s.eigs()
-    r_eff = lam.size
 
     dmd.profile_enable(True)
     dmd.profile_reset()
@@ -223,53 +319,122 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     dmd.profile_enable(False)
-    kernels = {}
-    for name in ("gram_columns", "gram_finalize", "solve_sym", "solve_eig", "project_modes"):
-        cnt, ms = dmd.profile_read(name)
-        if cnt:
-            kernels[name] = {"launches": cnt, "avg_us": 1000.0 * ms / cnt}
+    kernels = kernel_table(dmd, ("gram_columns", "gram_finalize", "solve_sym", "solve_eig", "project_modes"))
     dmd.profile_reset()
     print(f"[bench] timed {K} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
 
-    # per-frame latency: push -> modes complete, one frame at a time
-    lat = []
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    for _ in range(L):
-        e0.record()
-        s.push(frames[t])
-        s.modes(phi)
-        e1.record()
-        e1.synchronize()
-        lat.append(e0.elapsed_time(e1))
-        t += 1
+    latency, t = single_latency(s, frames, t, L, phi)
     lam, sig, rc = s.eigs()
+    r_eff = lam.size
     info = s.info()
     s.close()
-    lat = np.array(lat)
+    roofline = roofline_of(
+        kernels,
+        {"gram_columns": (M + 2) * n * 4,             # read m kept columns + new frame, write the frame
+         "project_modes": M * n * 4 + n * r_eff * 8},  # read X', write Phi (complex64)
+        {"gram_columns": "gram_push.hip", "project_modes": "project.hip"})
+    out = result_line(K / elapsed, K, Wu, elapsed, "f32", {
+        "workload": "blob video 1920x1080 FP32 (n=2073600), m=64, r=20; single-frame mode: "
+                    "step = push of one frame + FP64 solves + modes of its window",
+        "n": n, "m": M, "r": R, "r_eff": int(r_eff), "frames_per_step": 1,
+        "precision": "FP64 Gram accumulation, FP64 solves, FP32 modes"})
+    out.update({"roofline": roofline, "kernels": kernels,
+                "gram_GBps": kernels.get("gram_columns", {}).get("algorithmic_GBps"),
+                "latency_ms": latency, "jacobi_sweeps": int(info.sweeps), "qr_iters": int(info.qr_iters)})
+    return out, host_keep
 
-    # roofline of the dominant kernel (algorithmic bytes per launch)
-    bytes_per = {
-        "gram_columns": (M + 2) * n * 4,           # read m kept columns + new frame, write the frame
-        "project_modes": M * n * 4 + n * r_eff * 8,  # read X', write Phi (complex64)
-    }
-    source_of = {"gram_columns": "gram_push.hip", "project_modes": "project.hip"}
-    dom = max(bytes_per, key=lambda k: kernels.get(k, {}).get("avg_us", 0.0))
-    avg_s = kernels[dom]["avg_us"] * 1e-6
-    achieved = bytes_per[dom] / avg_s / 1e9
-    roofline = {
-        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(dom, source_of[dom]),
-        "kernel": dom, "algorithmic_bytes_per_launch": bytes_per[dom],
-        "avg_launch_us": round(kernels[dom]["avg_us"], 2),
-    }
-    for k in bytes_per:
-        if k in kernels:
-            kernels[k]["algorithmic_GBps"] = round(bytes_per[k] / (kernels[k]["avg_us"] * 1e-6) / 1e9, 1)
 
-    out = {
+def bench_block(args):
+    """k frames per step (multi-column update): one block push, the FP64
+    solves of all k windows side by side, and the modes of all k windows."""
+    import numpy as np
+    import torch
+
+    import paper_1612_07875_amd as dmd
+
+    n = H * W
+    kb = args.block
+    K, Wu, L = args.steps, args.warmup, args.latency_frames
+    LB = args.latency_blocks
+    fill = M + 1
+    T = fill + (Wu + K + LB) * kb + L
+    keep = M + 1 + (args.cpu_windows if not args.no_cpu_baseline else 0)
+    frames, host_keep = make_frames(T, keep)
+
+    s = dmd.Stream(n, M, R, dtype="f32", max_block=kb)
+    phis = torch.zeros((kb, R, n), dtype=torch.complex64, device="cuda")
+    t = 0
+    while t < fill:                      # the window fills with block pushes as well
+        k = min(kb, fill - t)
+        s.push_block(frames[t:t + k])
+        t += k
+    for _ in range(Wu):
+        s.push_block(frames[t:t + kb])
+        s.block_modes(phis)
+        t += kb
+    torch.cuda.synchronize()
+
+    dmd.profile_enable(True)
+    dmd.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        s.push_block(frames[t:t + kb])
+        s.block_modes(phis)
+        t += kb
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    dmd.profile_enable(False)
+    kernels = kernel_table(dmd, ("gram_block", "block_solve", "project_block"))
+    dmd.profile_reset()
+    print(f"[bench] timed {K} blocks of {kb} frames in {elapsed:.3f} s", file=sys.stderr, flush=True)
+    wins, _ = s.block_eigs()
+    bad = [w for w in wins if w[0] not in (0, 1)]
+    if bad:
+        raise RuntimeError(f"a window of the last block was not solved: status {bad[0][0]}")
+    r_eff = min(w[1].size for w in wins)
+
+    # block latency: enqueue of a block -> all k windows' modes written
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    blat = []
+    for _ in range(LB):
+        e0.record()
+        s.push_block(frames[t:t + kb])
+        s.block_modes(phis)
+        e1.record()
+        e1.synchronize()
+        blat.append(e0.elapsed_time(e1))
+        t += kb
+    latency, t = single_latency(s, frames, t, L, phis[0].T)
+    info = s.info()
+    s.close()
+    roofline = roofline_of(
+        kernels,
+        {"gram_block": (M + 1 + kb) * n * 4 + kb * n * 4,           # read window + block, write the block
+         "project_block": (M + kb - 1) * n * 4 + kb * n * r_eff * 8},  # read the union of X', write k Phi
+        {"gram_block": "gram_block.hip", "project_block": "project.hip"})
+    out = result_line(kb * K / elapsed, K, Wu, elapsed, "f32", {
+        "workload": f"blob video 1920x1080 FP32 (n=2073600), m=64, r=20; block mode: step = one push of "
+                    f"{kb} frames (multi-column update) + FP64 solves of all {kb} windows + modes of all {kb} windows",
+        "n": n, "m": M, "r": R, "r_eff": int(r_eff), "frames_per_step": kb,
+        "precision": "FP64 Gram accumulation, FP64 solves, FP32 modes"})
+    blat = np.array(blat) if blat else None
+    out.update({"roofline": roofline, "kernels": kernels,
+                "gram_GBps": kernels.get("gram_block", {}).get("algorithmic_GBps"),
+                "block_latency_ms": ({"p50": round(float(np.percentile(blat, 50)), 3),
+                                      "p99": round(float(np.percentile(blat, 99)), 3), "blocks": int(LB)}
+                                     if blat is not None else None),
+                "latency_ms": latency, "latency_note": "latency_ms: single-frame pushes (push -> modes) on "
+                                                       "the same stream after the timed blocks",
+                "jacobi_sweeps": int(info.sweeps), "qr_iters": int(info.qr_iters)})
+    return out, host_keep
+
+
+def result_line(value, K, Wu, elapsed, dtype, config):
+    return {
         "metric": "DMD window updates/s + Gram HBM GB/s vs roofline; p99 frame latency",
-        "value": round(K / elapsed, 2),
+        "value": round(value, 2),
         "unit": "window updates/s",
         "n_gpus": 1,
         "steps": K,
@@ -278,19 +443,33 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": dtype,
         "data": "synthetic",
-        "config": {
-            "workload": "blob video 1920x1080 FP32 (n=2073600), m=64, r=20; step = push + FP64 solves + modes",
-            "n": n, "m": M, "r": R, "r_eff": int(r_eff), "precision": "FP64 Gram accumulation, FP64 solves, FP32 modes",
-        },
-        "roofline": roofline,
-        "kernels": kernels,
-        "gram_GBps": kernels.get("gram_columns", {}).get("algorithmic_GBps"),
-        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
-                       "p99": round(float(np.percentile(lat, 99)), 4), "frames": int(L)},
-        "jacobi_sweeps": int(info.sweeps), "qr_iters": int(info.qr_iters),
+        "config": config,
     }
+
+
+def main():
+    args = defaults(parse())
+    if args.copy_probe and args.gpus == 1:
+        copy_probe()
+        return
+    if args.serve and args.gpus == 1:
+        serve_bench(args)
+        return
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    torch.cuda.set_device(0)
+    if args.mode == "single":
+        out, host_keep = bench_single(args)
+    else:
+        out, host_keep = bench_block(args)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(np.stack(host_keep), args.cpu_windows)

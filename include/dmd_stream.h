@@ -88,6 +88,14 @@ typedef enum {
     DMD_PREC_FP64    = 3  /* projections in FP64                                  */
 } dmd_precision_t;
 
+typedef enum {
+    DMD_EIG_DEFAULT = 0,  /* DMD_EIG_TRIDIAG, or DMD_EIG_JACOBI when warm_start is on   */
+    DMD_EIG_JACOBI  = 1,  /* cyclic two-sided Jacobi, all m eigenvectors               */
+    DMD_EIG_TRIDIAG = 2   /* Householder tridiagonalization, multisection for all
+                             eigenvalues, twisted factorizations for the r leading
+                             eigenvectors (O(m) dependent steps; no warm start)        */
+} dmd_eig_solver_t;
+
 typedef struct {
     int32_t dtype;       /* dmd_dtype_t (default DMD_F32)                           */
     int32_t precision;   /* dmd_precision_t for the tall-skinny projections; the
@@ -109,7 +117,8 @@ typedef struct {
     int32_t max_block;   /* largest k of dmd_stream_push_block, 1 .. 64 (0 = 1);
                             dense streams only.  The ring keeps max_block spare
                             slots and max_block - 1 extra solve workspaces       */
-    int32_t reserved[6]; /* must be zero                                             */
+    int32_t eig_solver;  /* dmd_eig_solver_t for the symmetric eig of X^* X       */
+    int32_t reserved[5]; /* must be zero                                             */
 } dmd_opts_t;
 
 typedef struct dmd_stream dmd_stream_t;
@@ -197,6 +206,16 @@ int dmd_stream_push_block(dmd_stream_t* h, const void* X_new, int64_t ldx,
 int dmd_stream_block_eigs(dmd_stream_t* h, int32_t* k, double* lam_re, double* lam_im,
                           double* sigma, int64_t ld, int32_t* r_eff, int32_t* status);
 
+/* DMD modes (Eq. Phi) of every window of the latest block push, each as
+ * dmd_stream_modes writes it: window w's Phi (n x r_eff[w] complex, column j
+ * at phi + w * ldw + j * ld complex elements; complex64, or complex128 for
+ * DMD_F64 streams and DMD_PREC_FP64) into the device buffer phi, ld >= n,
+ * ldw >= ld * r.  Windows that were not full, not solved, or belong to a
+ * rejected block are left untouched.  For FP32 data and coefficients one pass
+ * over the ring serves all k windows.  Stream-ordered; does not wait.
+ * DMD_E_NOT_READY if the latest push was not a block push with auto_solve on. */
+int dmd_stream_block_modes(dmd_stream_t* h, void* phi, int64_t ld, int64_t ldw, void* stream);
+
 /* ------------------------------------------------------------ small solves (Alg. 1-2) */
 
 /* Run the FP64 small solves for the current window on `stream` (not needed
@@ -238,6 +257,27 @@ int dmd_stream_modes(dmd_stream_t* h, void* phi, int64_t ld, void* stream);
 /* POD modes U = X V Sigma^-1 (n x r_eff, leading dimension ld >= n; double for
  * DMD_F64 or DMD_PREC_FP64, complex64 for DMD_C64_CSR, else float). */
 int dmd_stream_pod(dmd_stream_t* h, void* U, int64_t ld, void* stream);
+
+/* ------------------------------------------------------------ amplitudes, background (Sec. 3.3, Alg. 3) */
+
+/* Mode amplitudes of the latest solve (waits for it): b = (W Lambda)^-1
+ * alpha_1, alpha_1 = Sigma_r V_r^* e_1 the POD coefficients of the window's
+ * first snapshot x_1 (so that x_1 ~ Phi b, Sec. 3.3), and the background mode
+ * index argmin_i |log lambda_i| (Algorithm 3; lowest index on ties), in
+ * eigenvalue order.  b_re, b_im (host, r_eff values each) and bg_index may be
+ * NULL; *bg_index is -1 when there is no solve.  Status as dmd_stream_eigs. */
+int dmd_stream_amplitudes(dmd_stream_t* h, double* b_re, double* b_im, int32_t* bg_index,
+                          int32_t* r_eff);
+
+/* Background subtraction of the newest snapshot x_{m+1} (Algorithm 3, the
+ * streaming branch): with i the background mode, the background is
+ * l = b_i lambda_i^m phi_i and the foreground s = x_{m+1} - |l| (elementwise
+ * modulus).  Writes s into fg and |l| into bg (device, n values each; either
+ * may be NULL, not both): float for FP32 projections, double for DMD_F64
+ * streams and DMD_PREC_FP64.  One pass over X' (m n elements).  Dense streams
+ * only (DMD_E_UNSUPPORTED otherwise).  Stream-ordered; does not wait; leaves
+ * the outputs untouched while no full window has been solved. */
+int dmd_stream_background(dmd_stream_t* h, void* fg, void* bg, void* stream);
 
 /* ------------------------------------------------------------ bulk Gram (Alg. 1 first step) */
 
@@ -325,9 +365,10 @@ int dmd_batch_info(dmd_batch_t* b, int32_t* nstreams, int64_t* used_bytes,
 /* Process-wide per-kernel timing for diagnostics and roofline measurement.
  * When enabled, every kernel launch of every handle is bracketed by HIP events
  * recorded on its launch stream.  Kernel names: "gram_columns", "gram_finalize", "solve_sym",
- * "solve_eig", "project_modes", "project_pod", "csr_gram", "csr_project",
- * "gram_full", for block pushes "gram_block" (block Gram pass, reduction and
- * commit) and "block_solve" (all windows' solves), and for batch ticks
+ * "solve_eig", "project_modes", "project_pod", "background", "csr_gram",
+ * "csr_project", "gram_full", for block pushes "gram_block" (block Gram pass, reduction and
+ * commit), "block_solve" (all windows' solves) and "project_block" (all
+ * windows' modes), and for batch ticks
  * "batch_gram", "batch_solve", "batch_project".
  * dmd_profile_read waits for the recorded events and returns the number of
  * launches of `kernel` and their summed duration in milliseconds since the

@@ -25,6 +25,7 @@ STATUS_NAMES = {
 
 DTYPES = {"f32": 0, "f64": 1, "c64_csr": 2}
 PRECISIONS = {"default": 0, "fp32": 1, "bf16x3": 2, "fp64": 3}
+EIG_SOLVERS = {"default": 0, "jacobi": 1, "tridiag": 2}
 
 
 class DMDError(RuntimeError):
@@ -38,7 +39,7 @@ class Opts(ctypes.Structure):
         ("dtype", ctypes.c_int32), ("precision", ctypes.c_int32), ("max_nnz", ctypes.c_int32),
         ("max_sweeps", ctypes.c_int32), ("max_qr_iter", ctypes.c_int32), ("auto_solve", ctypes.c_int32),
         ("rcond", ctypes.c_double), ("tol", ctypes.c_double), ("warm_start", ctypes.c_int32),
-        ("max_block", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6),
+        ("max_block", ctypes.c_int32), ("eig_solver", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -72,6 +73,7 @@ SIGNATURES = {
     "dmd_stream_push_csr": [_P, _I32, _P, _P, _P],
     "dmd_stream_push_block": [_P, _P, _I64, _I32, _P],
     "dmd_stream_block_eigs": [_P, _I32P, _DP, _DP, _DP, _I64, _I32P, _I32P],
+    "dmd_stream_block_modes": [_P, _P, _I64, _I64, _P],
     "dmd_stream_solve": [_P, _P],
     "dmd_stream_eigs": [_P, _DP, _DP, _DP, _I32P],
     "dmd_stream_svd": [_P, _DP, _DP, _I64, _I32P],
@@ -79,6 +81,8 @@ SIGNATURES = {
     "dmd_stream_gram": [_P, _DP, _I64, _I32P],
     "dmd_stream_modes": [_P, _P, _I64, _P],
     "dmd_stream_pod": [_P, _P, _I64, _P],
+    "dmd_stream_amplitudes": [_P, _DP, _DP, _I32P, _I32P],
+    "dmd_stream_background": [_P, _P, _P, _P],
     "dmd_stream_load_window": [_P, _P, _I64, _I32, _P],
     "dmd_stream_resync": [_P, _P],
     "dmd_stream_info": [_P, ctypes.POINTER(Info)],
@@ -161,7 +165,7 @@ class Stream:
     def __init__(self, n: int, m: int, r: int, dtype: str = "f32", precision: str = "default",
                  auto_solve: bool = True, rcond: Optional[float] = None, tol: float = 0.0,
                  max_nnz: int = 0, max_sweeps: int = 0, max_qr_iter: int = 0, warm_start: bool = False,
-                 max_block: int = 1):
+                 max_block: int = 1, eig_solver: str = "default"):
         if not torch.cuda.is_available():
             raise RuntimeError("libdmdstream needs a HIP GPU; none is available")
         lib = load()
@@ -177,6 +181,7 @@ class Stream:
         o.tol = float(tol)
         o.warm_start = 1 if warm_start else 0
         o.max_block = int(max_block)
+        o.eig_solver = EIG_SOLVERS[eig_solver]
         h = _P()
         check(lib.dmd_stream_create(int(n), int(m), int(r), ctypes.byref(o), ctypes.byref(h)))
         self._h = h
@@ -258,6 +263,18 @@ class Stream:
             out.append((int(stat[w]), re[w, :q] + 1j * im[w, :q], sg[w, :q].copy()))
         return out, rc
 
+    def block_modes(self, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """Phi of every window of the latest block push: a (max_block, r, n) tensor whose
+        [w].T is window w's n x r modes (first r_eff[w] columns written)."""
+        if out is None:
+            out = torch.zeros((self.max_block, self.r, self.n), dtype=self.mode_dtype, device="cuda")
+        if not (out.is_cuda and out.dtype == self.mode_dtype and out.dim() == 3 and out.shape[2] == self.n
+                and out.shape[1] >= self.r and out.stride(2) == 1):
+            raise ValueError("output must be a (k, >= r, n) CUDA tensor with unit stride along n")
+        check(load().dmd_stream_block_modes(self._h, out.data_ptr(), out.stride(1), out.stride(0),
+                                            _stream_ptr(stream)))
+        return out
+
     def load_window(self, X: torch.Tensor, stream=None) -> int:
         if not (X.is_cuda and X.dtype == self.elem and X.dim() == 2 and X.shape[1] == self.n
                 and X.stride(1) == 1):
@@ -336,6 +353,31 @@ class Stream:
         self._check_out(out, self.pod_dtype)
         check(load().dmd_stream_pod(self._h, out.data_ptr(), out.stride(1), _stream_ptr(stream)))
         return out
+
+    def amplitudes(self):
+        """(b complex128[r_eff], background index, status) of the latest solve."""
+        re = np.zeros(self.r)
+        im = np.zeros(self.r)
+        idx = ctypes.c_int32(-1)
+        k = ctypes.c_int32(0)
+        rc = check(load().dmd_stream_amplitudes(self._h, _dp(re), _dp(im), ctypes.byref(idx), ctypes.byref(k)))
+        k = k.value
+        return re[:k] + 1j * im[:k], idx.value, rc
+
+    def background(self, fg: Optional[torch.Tensor] = None, bg: Optional[torch.Tensor] = None,
+                   want_bg: bool = True, stream=None):
+        """Foreground and background magnitude (n values each, device) of the newest snapshot."""
+        if fg is None:
+            fg = torch.zeros(self.n, dtype=self.pod_dtype, device="cuda")
+        if bg is None and want_bg:
+            bg = torch.zeros(self.n, dtype=self.pod_dtype, device="cuda")
+        for t in (fg, bg):
+            if t is not None and not (t.is_cuda and t.dtype == self.pod_dtype and t.numel() == self.n
+                                      and t.is_contiguous()):
+                raise ValueError(f"outputs must be contiguous {self.pod_dtype} CUDA tensors of n elements")
+        check(load().dmd_stream_background(self._h, fg.data_ptr(), bg.data_ptr() if bg is not None else None,
+                                           _stream_ptr(stream)))
+        return fg, bg
 
     def _check_out(self, out: torch.Tensor, dt):
         if not (out.is_cuda and out.dtype == dt and out.dim() == 2 and out.shape[0] == self.n

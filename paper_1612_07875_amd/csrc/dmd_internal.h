@@ -32,7 +32,7 @@ struct DevState {
     int32_t warm;               // latest solve was warm-started (1: shifted, 2: same window)
     int32_t skipped;            // latest solve found nothing new and kept the previous results
     int32_t block_rejected;     // the latest block push was rejected (non-finite inner products)
-    int32_t pad;
+    int32_t bg_index;           // background mode (argmin |log lambda|) of the latest solve
 };
 static_assert(sizeof(DevState) == 64, "DevState must stay 64 bytes");
 
@@ -40,12 +40,14 @@ static_assert(sizeof(DevState) == 64, "DevState must stay 64 bytes");
 struct ResultsLayout {
     size_t sigma_off;  // m doubles
     size_t lam_off;    // 2 r doubles (interleaved complex)
+    size_t amp_off;    // 2 r doubles: mode amplitudes b (interleaved complex)
     size_t bytes;
     static ResultsLayout make(int m, int r) {
         ResultsLayout L;
         L.sigma_off = sizeof(DevState);
         L.lam_off = L.sigma_off + sizeof(double) * (size_t)m;
-        L.bytes = L.lam_off + sizeof(double) * 2 * (size_t)r;
+        L.amp_off = L.lam_off + sizeof(double) * 2 * (size_t)r;
+        L.bytes = L.amp_off + sizeof(double) * 2 * (size_t)r;
         return L;
     }
 };
@@ -120,24 +122,32 @@ struct SolveArgs {
     int warm_start;        // start Jacobi from the previous solve's eigenvectors
     double* sigma;         // results block: m sigmas
     double* lam;           // results block: 2 r doubles
+    double* amp;           // results block: 2 r doubles, mode amplitudes b
     double* V;             // m x r (complex: interleaved), canonical columns
     double* At;            // r x r (complex: interleaved)
     double* W;             // r x r complex
-    double* work;          // global scratch for m > 64: 3 M (M+1) values (A, V, Q)
+    double* work;          // global scratch: 4 M (M+1) values (A, V, Q or Z, tail scratch)
     double* Vfull;         // m x m eigenvectors of the latest solve, sigma order
     void* Bphi;            // m x 2r coefficients of Phi (row-major, data precision)
     void* Bpod;            // m x r (real) or m x 2r (complex) coefficients of U
+    void* Bbg;             // m complex coefficients of the background (may be null)
     int coef_f64;          // 1: coefficients stored as double, 0: float
     char* res_block;       // device results block (state, sigma, lambda)
     char* res_host;        // device address of its pinned host mirror
     int res_bytes;         // size of the results block
 };
 hipError_t launch_solve_sym(const SolveArgs& a, hipStream_t s);
+// Same outputs by Householder tridiagonalization, multisection and twisted
+// factorizations (no warm start).
+hipError_t launch_solve_trid(const SolveArgs& a, hipStream_t s);
+// Grouped real symmetric solves (one workgroup per item; lds: m <= 64) by
+// Jacobi or by the tridiagonal method, and the grouped eig of A~.
+hipError_t launch_jacobi_grouped(const SolveArgs* items_lds, int n_lds, const SolveArgs* items_glb, int n_glb,
+                                 hipStream_t s);
+hipError_t launch_trid_grouped(const SolveArgs* items_lds, int n_lds, const SolveArgs* items_glb, int n_glb,
+                               hipStream_t s);
+hipError_t launch_eig_grouped(const SolveArgs* items, int n, hipStream_t s);
 hipError_t launch_solve_eig(const SolveArgs& a, hipStream_t s);
-// Grouped solves, one workgroup per stream: Jacobi kernels for real windows
-// with m <= 64 (LDS) and m > 64 (global workspace), then the eig kernel for all.
-hipError_t launch_solve_grouped(const SolveArgs* items_lds, int n_lds, const SolveArgs* items_glb, int n_glb,
-                                const SolveArgs* items_all, int n_all, hipStream_t s);
 
 // Multi-column update (k new snapshots at once): one pass over the window and
 // the k new columns gives the (count+k) x k block of new inner products on the
@@ -182,12 +192,51 @@ struct ProjectArgs {
     int elem_f64;          // ring elements are double (else float)
     int coef_f64;          // coefficients, accumulation and output in double
     int precision;         // DMD_PREC_* used for float data
+    int block_only;        // a window of a block push: skip it if the block was rejected
 };
 hipError_t launch_project(const ProjectArgs& a, hipStream_t s);
 // Grouped FP32 projections of many streams in one launch.
 hipError_t launch_project_grouped(const ProjectArgs* items, const int* blk_start, int nitems, int total_blocks,
                                   hipStream_t s);
 int project_item_blocks(int64_t n);
+
+// Modes of every window of a block push in one pass over the ring (FP32 data
+// and coefficients).  Window w (0 = oldest) of the block ends w - k + 1
+// snapshots before the current window; its X' is the m ring columns starting
+// at logical position w - k + 2 of the current window.  Window w < k-1 has its
+// state and coefficients in set kmax-k+w of the intermediate-window sets;
+// window k-1 uses the stream's own.  Phi of window w goes to out + w * ldw
+// complex elements (column j at + j * ldo); windows without a solve are skipped.
+struct BlockProjectArgs {
+    const void* ring;
+    int64_t ld, n;
+    int m, r, slots, k, kmax;
+    const DevState* st;            // the stream's state (current window)
+    const char* shadow;            // states of the intermediate windows
+    int shadow_stride;
+    const float* Bphi;             // current window's coefficients (m x 2r row-major)
+    const float* Bphi_sets;        // intermediate sets, bphi_stride floats apart
+    int64_t bphi_stride;
+    float2* out;
+    int64_t ldo, ldw;
+};
+hipError_t launch_project_block(const BlockProjectArgs& a, hipStream_t s);
+
+// Background subtraction of the newest snapshot (Sec. 3.3, Algorithm 3): with
+// beta = b_i lambda_i^m C[:, i] (background mode i, written by the eig solve),
+// bg = |X' beta| and fg = x_new - bg, x_new being the last column of X'.
+struct BackgroundArgs {
+    const DevState* st;
+    const void* ring;
+    int64_t ld, n;
+    int m, slots;
+    const void* beta;      // m complex, float or double (elem_f64 / coef_f64)
+    void* fg;              // n values of the data type (may be null)
+    void* bg;              // n values of the data type (may be null)
+    int elem_f64;          // ring elements are double (else float)
+    int coef_f64;          // beta and the accumulation in double
+};
+hipError_t launch_background(const BackgroundArgs& a, hipStream_t s);
 
 // Sparse projection: out = X_sub * B (complex) into a dense n x r_eff
 // complex64 output (zero outside the window's support).

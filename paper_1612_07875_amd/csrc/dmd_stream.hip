@@ -99,6 +99,7 @@ struct dmd_stream {
     int elem_bytes = 4;     // dense ring element size
     bool cplx = false;      // sparse complex path
     bool coef_f64 = false;  // projection coefficients and accumulation in double
+    bool use_trid = true;   // symmetric eig by the tridiagonal method (else Jacobi)
 
     void* ring = nullptr;       // dense: slots x ld elements
     int32_t* ring_idx = nullptr;  // sparse: slots x max_nnz indices
@@ -123,6 +124,7 @@ struct dmd_stream {
     double* gfull = nullptr;      // per-split tiles of the whole-window Gram
     void* Bphi = nullptr;
     void* Bpod = nullptr;
+    void* Bbg = nullptr;          // background coefficients (m complex)
 
     // block pushes: up to kmax snapshots at once (ring has kmax spare slots)
     int kmax = 1;
@@ -187,7 +189,7 @@ int dev_alloc(dmd_stream* h, P** p, size_t bytes) {
 void free_all(dmd_stream* h) {
     void* bufs[] = {h->ring, h->ring_idx, h->ring_val, h->ring_nnz, h->scatter, h->flag, h->G, h->partials,
                     h->res_dev, h->V, h->At, h->W, h->work, h->Vfull, h->gfull, h->Bphi, h->Bpod,
-                    h->bpartial, h->gblock, h->bflag, h->sh_dev, h->sh_V, h->sh_At, h->sh_W, h->sh_work,
+                    h->Bbg, h->bpartial, h->gblock, h->bflag, h->sh_dev, h->sh_V, h->sh_At, h->sh_W, h->sh_work,
                     h->sh_Vfull, h->sh_Bphi, h->sh_Bpod, h->solve_tbl};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -214,7 +216,7 @@ SetSizes set_sizes(const dmd_stream* h) {
     const size_t cw = h->cplx ? 2 : 1, m = h->m, r = h->r;
     const size_t M = m + (m & 1);
     const size_t coef = h->coef_f64 ? 8 : 4;
-    return SetSizes{cw * m * r, cw * r * r, 2 * r * r, cw * 3 * M * (M + 1), cw * m * m, coef * 2 * m * r,
+    return SetSizes{cw * m * r, cw * r * r, 2 * r * r, cw * 4 * M * (M + 1), cw * m * m, coef * 2 * m * r,
                     coef * cw * m * r};
 }
 
@@ -236,6 +238,7 @@ void fill_solve_args(const dmd_stream* h, dmd::SolveArgs& a) {
     a.warm_start = h->opts.warm_start;
     a.sigma = reinterpret_cast<double*>(h->res_dev + h->L.sigma_off);
     a.lam = reinterpret_cast<double*>(h->res_dev + h->L.lam_off);
+    a.amp = reinterpret_cast<double*>(h->res_dev + h->L.amp_off);
     a.V = h->V;
     a.At = h->At;
     a.W = h->W;
@@ -243,6 +246,7 @@ void fill_solve_args(const dmd_stream* h, dmd::SolveArgs& a) {
     a.Vfull = h->Vfull;
     a.Bphi = h->Bphi;
     a.Bpod = h->Bpod;
+    a.Bbg = h->Bbg;
     a.coef_f64 = h->coef_f64 ? 1 : 0;
     a.res_block = h->res_dev;
     a.res_host = h->res_host_dev;
@@ -257,6 +261,8 @@ void fill_shadow_args(const dmd_stream* h, dmd::SolveArgs& a, int e) {
     a.warm_start = 0;
     a.sigma = reinterpret_cast<double*>(res + h->L.sigma_off);
     a.lam = reinterpret_cast<double*>(res + h->L.lam_off);
+    a.amp = reinterpret_cast<double*>(res + h->L.amp_off);
+    a.Bbg = nullptr;  // the background split is provided for the current window
     a.V = h->sh_V + e * z.V;
     a.At = h->sh_At + e * z.At;
     a.W = h->sh_W + e * z.W;
@@ -291,7 +297,9 @@ int enqueue_solve(dmd_stream* h, hipStream_t s) {
     h->last_block_k = 0;
     dmd::SolveArgs a;
     fill_solve_args(h, a);
-    HIP_TRY(timed("solve_sym", s, [&] { return dmd::launch_solve_sym(a, s); }));
+    HIP_TRY(timed("solve_sym", s, [&] {
+        return h->use_trid ? dmd::launch_solve_trid(a, s) : dmd::launch_solve_sym(a, s);
+    }));
     HIP_TRY(timed("solve_eig", s, [&] { return dmd::launch_solve_eig(a, s); }));
     HIP_TRY(hipEventRecord(h->ev_solved, s));
     h->solve_enqueued = true;
@@ -358,7 +366,7 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
     dmd_opts_init(&o);
     if (opts) {
         o = *opts;
-        for (int i = 0; i < 6; ++i)
+        for (int i = 0; i < 5; ++i)
             if (o.reserved[i] != 0) return fail(DMD_E_INVAL, "opts.reserved must be zero");
         if (o.max_sweeps == 0) o.max_sweeps = 40;
         if (o.max_qr_iter == 0) o.max_qr_iter = 60;
@@ -375,6 +383,10 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
     if (o.max_sweeps < 1 || o.max_qr_iter < 1) return fail(DMD_E_INVAL, "iteration limits must be positive");
     if (o.auto_solve != 0 && o.auto_solve != 1) return fail(DMD_E_INVAL, "auto_solve must be 0 or 1");
     if (o.warm_start != 0 && o.warm_start != 1) return fail(DMD_E_INVAL, "warm_start must be 0 or 1");
+    if (o.eig_solver < DMD_EIG_DEFAULT || o.eig_solver > DMD_EIG_TRIDIAG)
+        return fail(DMD_E_INVAL, "unknown eig_solver %d", o.eig_solver);
+    if (o.eig_solver == DMD_EIG_TRIDIAG && o.warm_start)
+        return fail(DMD_E_INVAL, "warm_start needs the Jacobi eigensolver");
     if (o.max_block == 0) o.max_block = 1;
     if (o.max_block < 1 || o.max_block > 64) return fail(DMD_E_INVAL, "max_block must be in [1, 64] (got %d)", o.max_block);
     if (o.dtype == DMD_C64_CSR && o.max_block != 1) return fail(DMD_E_UNSUPPORTED, "block pushes are for dense streams");
@@ -399,6 +411,7 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
     h->cplx = (o.dtype == DMD_C64_CSR);
     h->elem_bytes = (o.dtype == DMD_F64) ? 8 : 4;
     h->coef_f64 = (o.dtype == DMD_F64) || (o.precision == DMD_PREC_FP64);
+    h->use_trid = o.eig_solver == DMD_EIG_TRIDIAG || (o.eig_solver == DMD_EIG_DEFAULT && !o.warm_start);
     h->ld = (n + 63) / 64 * 64;
     h->L = ResultsLayout::make(m, r);
     if (hipGetDevice(&h->device) != hipSuccess) {
@@ -435,10 +448,11 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
     ALLOC(h->V, sizeof(double) * cw * (size_t)m * r);
     ALLOC(h->At, sizeof(double) * cw * (size_t)r * r);
     ALLOC(h->W, sizeof(double) * 2 * (size_t)r * r);
-    ALLOC(h->work, sizeof(double) * cw * 3 * (size_t)M * (M + 1));
+    ALLOC(h->work, sizeof(double) * cw * 4 * (size_t)M * (M + 1));
     ALLOC(h->Vfull, sizeof(double) * cw * (size_t)m * m);
     ALLOC(h->Bphi, coef * 2 * (size_t)m * r);
     ALLOC(h->Bpod, coef * cw * (size_t)m * r);
+    ALLOC(h->Bbg, coef * 2 * (size_t)m);
     h->sh_stride = (h->L.bytes + 255) / 256 * 256;
     if (h->kmax > 1) {
         const SetSizes z = set_sizes(h);
@@ -639,8 +653,11 @@ DMD_API int dmd_stream_push_block(dmd_stream_t* h, const void* X_new, int64_t ld
     if (h->opts.auto_solve) {
         const dmd::SolveArgs* t = h->solve_tbl + (h->kmax - k);
         const bool lds = h->m + (h->m & 1) <= 64;
-        HIP_TRY(timed("block_solve", s,
-                      [&] { return dmd::launch_solve_grouped(t, lds ? k : 0, t, lds ? 0 : k, t, k, s); }));
+        HIP_TRY(timed("block_solve", s, [&] {
+            hipError_t e = h->use_trid ? dmd::launch_trid_grouped(t, lds ? k : 0, t, lds ? 0 : k, s)
+                                       : dmd::launch_jacobi_grouped(t, lds ? k : 0, t, lds ? 0 : k, s);
+            return e != hipSuccess ? e : dmd::launch_eig_grouped(t, k, s);
+        }));
         HIP_TRY(hipEventRecord(h->ev_solved, s));
         h->solve_enqueued = true;
         h->last_block_k = k;
@@ -678,6 +695,56 @@ DMD_API int dmd_stream_block_eigs(dmd_stream_t* h, int32_t* k, double* lam_re, d
         }
     }
     return solve_status(h);
+}
+
+DMD_API int dmd_stream_block_modes(dmd_stream_t* h, void* phi, int64_t ld, int64_t ldw, void* stream) {
+    if (int rc = check_handle(h)) return rc;
+    if (!phi) return fail(DMD_E_INVAL, "null output");
+    if (ld < h->n) return fail(DMD_E_INVAL, "ld < n");
+    if (ldw < ld * h->r) return fail(DMD_E_INVAL, "ldw < ld * r");
+    if (h->last_block_k == 0) return fail(DMD_E_NOT_READY, "the latest push was not a solved block push");
+    DeviceGuard g(h->device);
+    hipStream_t s = as_stream(stream);
+    HIP_TRY(begin(h, s));
+    const int k = h->last_block_k;
+    const size_t celem = h->coef_f64 ? 16 : 8;  // complex128 or complex64
+    if (h->elem_bytes == 4 && !h->coef_f64) {
+        dmd::BlockProjectArgs a{};
+        a.ring = h->ring;
+        a.ld = h->ld;
+        a.n = h->n;
+        a.m = h->m;
+        a.r = h->r;
+        a.slots = h->slots;
+        a.k = k;
+        a.kmax = h->kmax;
+        a.st = reinterpret_cast<const DevState*>(h->res_dev);
+        a.shadow = h->sh_dev;
+        a.shadow_stride = (int)h->sh_stride;
+        a.Bphi = static_cast<const float*>(h->Bphi);
+        a.Bphi_sets = static_cast<const float*>(h->sh_Bphi);
+        a.bphi_stride = (int64_t)set_sizes(h).Bphi / sizeof(float);
+        a.out = static_cast<float2*>(phi);
+        a.ldo = ld;
+        a.ldw = ldw;
+        HIP_TRY(timed("project_block", s, [&] { return dmd::launch_project_block(a, s); }));
+    } else {
+        // FP64 data or coefficients: one projection per window, each from its own state
+        for (int w = 0; w < k; ++w) {
+            dmd::ProjectArgs a;
+            char* out = static_cast<char*>(phi) + (size_t)w * ldw * celem;
+            fill_project_args(h, a, out, ld, true);
+            if (w < k - 1) {
+                const int set = h->kmax - k + w;
+                a.st = reinterpret_cast<const DevState*>(h->sh_dev + (size_t)set * h->sh_stride);
+                a.B = static_cast<char*>(h->sh_Bphi) + (size_t)set * set_sizes(h).Bphi;
+            }
+            a.block_only = 1;
+            HIP_TRY(timed("project_block", s, [&] { return dmd::launch_project(a, s); }));
+        }
+    }
+    HIP_TRY(end(h, s));
+    return DMD_OK;
 }
 
 DMD_API int dmd_stream_solve(dmd_stream_t* h, void* stream) {
@@ -802,6 +869,48 @@ DMD_API int dmd_stream_pod(dmd_stream_t* h, void* U, int64_t ld, void* stream) {
     return project(h, U, ld, stream, false);
 }
 
+DMD_API int dmd_stream_amplitudes(dmd_stream_t* h, double* b_re, double* b_im, int32_t* bg_index,
+                                  int32_t* r_eff) {
+    if (int rc = check_handle(h)) return rc;
+    DeviceGuard g(h->device);
+    if (int rc = wait_solved(h)) return rc;
+    const DevState& st = host_state(h);
+    const int k = st.solve_status == dmd::ST_E_NOT_READY ? 0 : st.r_eff;
+    if (r_eff) *r_eff = k;
+    if (bg_index) *bg_index = k > 0 ? st.bg_index : -1;
+    const double* b = reinterpret_cast<const double*>(h->res_host + h->L.amp_off);
+    for (int i = 0; i < k; ++i) {
+        if (b_re) b_re[i] = b[2 * i];
+        if (b_im) b_im[i] = b[2 * i + 1];
+    }
+    return solve_status(h);
+}
+
+DMD_API int dmd_stream_background(dmd_stream_t* h, void* fg, void* bg, void* stream) {
+    if (int rc = check_handle(h)) return rc;
+    if (h->cplx) return fail(DMD_E_UNSUPPORTED, "background subtraction is for dense streams");
+    if (!fg && !bg) return fail(DMD_E_INVAL, "fg and bg are both null");
+    if (!h->solve_enqueued) return fail(DMD_E_NOT_READY, "no solve has been enqueued");
+    DeviceGuard g(h->device);
+    hipStream_t s = as_stream(stream);
+    HIP_TRY(begin(h, s));
+    dmd::BackgroundArgs a{};
+    a.st = reinterpret_cast<const DevState*>(h->res_dev);
+    a.ring = h->ring;
+    a.ld = h->ld;
+    a.n = h->n;
+    a.m = h->m;
+    a.slots = h->slots;
+    a.beta = h->Bbg;
+    a.fg = fg;
+    a.bg = bg;
+    a.elem_f64 = h->elem_bytes == 8;
+    a.coef_f64 = h->coef_f64;
+    HIP_TRY(timed("background", s, [&] { return dmd::launch_background(a, s); }));
+    HIP_TRY(end(h, s));
+    return DMD_OK;
+}
+
 DMD_API int dmd_stream_load_window(dmd_stream_t* h, const void* X, int64_t ldx, int32_t ncols, void* stream) {
     if (int rc = check_handle(h)) return rc;
     if (h->cplx) return fail(DMD_E_UNSUPPORTED, "bulk window load is for dense streams");
@@ -907,7 +1016,7 @@ namespace {
 // copied to the device before the grouped launches (two copies alternate so
 // that the host never overwrites a table a tick in flight still reads).
 struct TickLayout {
-    size_t gram, gblk, lds, glb, all, proj, pblk, bytes;
+    size_t gram, gblk, lds, glb, tlds, tglb, all, proj, pblk, bytes;
     static TickLayout make(int cap) {
         TickLayout L;
         auto al = [](size_t x) { return (x + 255) / 256 * 256; };
@@ -915,7 +1024,9 @@ struct TickLayout {
         L.gblk = al(L.gram + sizeof(dmd::GramItem) * cap);
         L.lds = al(L.gblk + sizeof(int) * (cap + 1));
         L.glb = al(L.lds + sizeof(dmd::SolveArgs) * cap);
-        L.all = al(L.glb + sizeof(dmd::SolveArgs) * cap);
+        L.tlds = al(L.glb + sizeof(dmd::SolveArgs) * cap);
+        L.tglb = al(L.tlds + sizeof(dmd::SolveArgs) * cap);
+        L.all = al(L.tglb + sizeof(dmd::SolveArgs) * cap);
         L.proj = al(L.all + sizeof(dmd::SolveArgs) * cap);
         L.pblk = al(L.proj + sizeof(dmd::ProjectArgs) * cap);
         L.bytes = al(L.pblk + sizeof(int) * (cap + 1));
@@ -1079,10 +1190,12 @@ DMD_API int dmd_batch_tick(dmd_batch_t* b, int32_t count, dmd_stream_t* const* s
     int* gblk = reinterpret_cast<int*>(H + b->L.gblk);
     auto* sl = reinterpret_cast<dmd::SolveArgs*>(H + b->L.lds);
     auto* sg = reinterpret_cast<dmd::SolveArgs*>(H + b->L.glb);
+    auto* tl = reinterpret_cast<dmd::SolveArgs*>(H + b->L.tlds);
+    auto* tg = reinterpret_cast<dmd::SolveArgs*>(H + b->L.tglb);
     auto* sa = reinterpret_cast<dmd::SolveArgs*>(H + b->L.all);
     auto* pa = reinterpret_cast<dmd::ProjectArgs*>(H + b->L.proj);
     int* pblk = reinterpret_cast<int*>(H + b->L.pblk);
-    int nl = 0, ng = 0, np = 0, gtot = 0, ptot = 0;
+    int nl = 0, ng = 0, ntl = 0, ntg = 0, np = 0, gtot = 0, ptot = 0;
     for (int i = 0; i < count; ++i) {
         dmd_stream* h = streams[i];
         dmd::GramItem& it = gi[i];
@@ -1103,8 +1216,14 @@ DMD_API int dmd_batch_tick(dmd_batch_t* b, int32_t count, dmd_stream_t* const* s
         dmd::SolveArgs a;
         fill_solve_args(h, a);
         sa[i] = a;
-        if (h->m + (h->m & 1) <= 64) sl[nl++] = a;
-        else sg[ng++] = a;
+        const bool small = h->m + (h->m & 1) <= 64;
+        if (h->use_trid) {
+            if (small) tl[ntl++] = a;
+            else tg[ntg++] = a;
+        } else {
+            if (small) sl[nl++] = a;
+            else sg[ng++] = a;
+        }
         if (modes && modes[i]) {
             fill_project_args(h, pa[np], modes[i], ld_modes[i], true);
             pblk[np] = ptot;
@@ -1122,9 +1241,14 @@ DMD_API int dmd_batch_tick(dmd_batch_t* b, int32_t count, dmd_stream_t* const* s
     auto* dgblk = reinterpret_cast<const int*>(D + b->L.gblk);
     HIP_TRY(timed("batch_gram", s, [&] { return dmd::launch_gram_grouped(dgi, dgblk, count, gtot, s); }));
     HIP_TRY(timed("batch_solve", s, [&] {
-        return dmd::launch_solve_grouped(reinterpret_cast<const dmd::SolveArgs*>(D + b->L.lds), nl,
-                                         reinterpret_cast<const dmd::SolveArgs*>(D + b->L.glb), ng,
-                                         reinterpret_cast<const dmd::SolveArgs*>(D + b->L.all), count, s);
+        hipError_t e = dmd::launch_jacobi_grouped(reinterpret_cast<const dmd::SolveArgs*>(D + b->L.lds), nl,
+                                                  reinterpret_cast<const dmd::SolveArgs*>(D + b->L.glb), ng, s);
+        if (e == hipSuccess)
+            e = dmd::launch_trid_grouped(reinterpret_cast<const dmd::SolveArgs*>(D + b->L.tlds), ntl,
+                                         reinterpret_cast<const dmd::SolveArgs*>(D + b->L.tglb), ntg, s);
+        if (e == hipSuccess)
+            e = dmd::launch_eig_grouped(reinterpret_cast<const dmd::SolveArgs*>(D + b->L.all), count, s);
+        return e;
     }));
     if (np > 0)
         HIP_TRY(timed("batch_project", s, [&] {

@@ -58,6 +58,7 @@ __device__ void project_body(const ProjectArgs& a, int blk) {
     __shared__ T stage[kThreads / 64][64 * OLD];
     const DevState* st = a.st;
     if (st->solve_status == ST_E_NOT_READY) return;
+    if (a.block_only && st->block_rejected) return;
     const int k_eff = st->r_eff;
     const int kcols = a.cplx_out ? 2 * k_eff : k_eff;
     if (kcols == 0) return;
@@ -193,7 +194,131 @@ hipError_t launch_tiles(const ProjectArgs& a, hipStream_t s, int kc_max) {
     return launch_nt<TX, T, 4>(a, s);
 }
 
+// ---------------------------------------------------------------------------
+// Modes of every window of a block push (multi-column update, Sec. 5, with
+// Eq. Phi per window).  The k windows' X' are m consecutive ring columns each,
+// shifted by one column per window, so together they span m+k-1 columns.  A
+// workgroup stages 64 rows of those columns in LDS once (16-byte loads; ring
+// rows between n and the padded length are zero) and each wavefront
+// multiplies them by the coefficient matrices of windows wave, wave+4, ...:
+// the ring is read once for all k windows instead of k times.  Requires k <= 64.
+constexpr int kBlkRows = 64;
+constexpr int kBlkLDR = kBlkRows + 16;  // column stride: the four k-slots of a fragment hit distinct banks
+constexpr int kBlkOLD = 17;             // padded row length of the output stage
+
+template <int NT>
+__global__ __launch_bounds__(kThreads, 3)
+void k_project_block(BlockProjectArgs a) {
+    extern __shared__ float dynp[];
+    const DevState* stf = a.st;
+    if (stf->count < a.m + 1 || stf->block_rejected) return;
+    const int m = a.m, k = a.k;
+    const int ncols = m + k - 1;
+    float* U = dynp;
+    float* stage = dynp + (size_t)ncols * kBlkLDR;
+    const int64_t row0 = (int64_t)blockIdx.x * kBlkRows;
+    const int base = stf->oldest + 2 - k + a.slots;  // slot of staged column 0, before the wrap
+    const float* ring = static_cast<const float*>(a.ring);
+    for (int t = threadIdx.x; t < ncols * (kBlkRows / 4); t += kThreads) {
+        const int c = t / (kBlkRows / 4), q = t % (kBlkRows / 4);
+        const float* src = ring + (int64_t)((base + c) % a.slots) * a.ld + row0 + 4 * q;
+        *reinterpret_cast<float4*>(&U[c * kBlkLDR + 4 * q]) = *reinterpret_cast<const float4*>(src);
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    float* sw = stage + wave * 64 * kBlkOLD;
+    const int rs = 2 * a.r;
+    for (int w = wave; w < k; w += kThreads / 64) {
+        const int set = a.kmax - k + w;
+        const DevState* st =
+            w == k - 1 ? stf : reinterpret_cast<const DevState*>(a.shadow + (size_t)set * a.shadow_stride);
+        if (st->solve_status != ST_OK && st->solve_status != ST_W_RANK) continue;
+        const int kc = 2 * st->r_eff;
+        if (kc == 0) continue;
+        const float* B = w == k - 1 ? a.Bphi : a.Bphi_sets + (int64_t)set * a.bphi_stride;
+        v4f acc[4][NT];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = v4f{0, 0, 0, 0};
+        // coefficients of 8 k-steps (32 window columns) are loaded together
+        // before their MFMAs, so the L2 latency is paid once per chunk
+        for (int cb = 0; cb < m; cb += 32) {
+            float bv[8][NT];
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks) {
+                const int col = cb + 4 * ks + lk;
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const int c = 16 * nt + li;
+                    bv[ks][nt] = (col < m && c < kc) ? B[(int64_t)col * rs + c] : 0.0f;
+                }
+            }
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks) {
+                const int col = cb + 4 * ks + lk;
+                const bool cin = col < m;
+                const float* ucol = U + (w + (cin ? col : 0)) * kBlkLDR;
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt) {
+                    const float av = cin ? ucol[16 * rt + li] : 0.0f;
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+                        acc[rt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[ks][nt], acc[rt][nt], 0, 0, 0);
+                }
+            }
+        }
+        float2* out = a.out + (int64_t)w * a.ldw;
+        const int64_t row = row0 + lane;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            if (16 * nt >= kc) break;
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) sw[(16 * rt + 4 * lk + v) * kBlkOLD + li] = acc[rt][nt][v];
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (row < a.n) {
+#pragma unroll
+                for (int cc = 0; cc < 16; cc += 2) {
+                    const int c = 16 * nt + cc;
+                    if (c < kc)
+                        out[row + (int64_t)(c >> 1) * a.ldo] = float2{sw[lane * kBlkOLD + cc], sw[lane * kBlkOLD + cc + 1]};
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+}
+
+template <int NT>
+hipError_t launch_block_nt(const BlockProjectArgs& a, hipStream_t s) {
+    const size_t lds = sizeof(float) * ((size_t)(a.m + a.k - 1) * kBlkLDR + (kThreads / 64) * 64 * kBlkOLD);
+    auto kern = k_project_block<NT>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const unsigned gx = (unsigned)((a.n + kBlkRows - 1) / kBlkRows);
+    hipLaunchKernelGGL(kern, dim3(gx), dim3(kThreads), lds, s, a);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_project_block(const BlockProjectArgs& a, hipStream_t s) {
+    const int kc_max = 2 * a.r;
+    if (kc_max > 64 || a.k < 1 || a.k > a.kmax || a.ld % kBlkRows) return hipErrorInvalidValue;
+    if (kc_max <= 16) return launch_block_nt<1>(a, s);
+    if (kc_max <= 32) return launch_block_nt<2>(a, s);
+    if (kc_max <= 48) return launch_block_nt<3>(a, s);
+    return launch_block_nt<4>(a, s);
+}
 
 int project_item_blocks(int64_t n) { return (int)((n + kRowsPerBlock - 1) / kRowsPerBlock); }
 

@@ -16,7 +16,10 @@
 //     A~ = Z T Z^*, eigenvectors of T by back substitution, W = Z Y;
 //   * eigenpairs sorted (|lambda| descending, arg ascending), W's columns
 //     scaled to unit norm with the largest-modulus entry real positive;
-//   * DMD coefficients C = V Sigma^-1 W for the projection Phi = X' C (Eq. Phi).
+//   * mode amplitudes b = (W Lambda)^-1 alpha_1 (Sec. 3.3) and the background
+//     mode argmin |log lambda| (Algorithm 3);
+//   * DMD coefficients C = V Sigma^-1 W for the projection Phi = X' C (Eq. Phi)
+//     and the background coefficients C[:, bg] b_bg lambda_bg^m.
 #include <cfloat>
 
 #include "cplx.h"
@@ -157,6 +160,132 @@ template <typename S> __device__ __forceinline__ S load_s(const double* p, int64
 template <> __device__ __forceinline__ double load_s<double>(const double* p, int64_t i) { return p[i]; }
 template <> __device__ __forceinline__ cplx load_s<cplx>(const double* p, int64_t i) { return cplx{p[2 * i], p[2 * i + 1]}; }
 
+// Common end of the symmetric solves: sigma sorted descending (stable in the
+// index) with V permuted alike (Algorithm 1), the rank r_eff, canonical V_r,
+// A~ = Sigma^-1 V_r^* xty V_r Sigma^-1 (Eq. Atilde, Algorithm 2), the POD
+// coefficients V_r Sigma^-1 and the status.
+// s_sig[i]: sigma of eigenvector i (i < m); Vc: eigenvectors by column
+// (leading dimension ld), the first nvec of them valid (nvec >= r_eff);
+// spare1, spare2: M x ld scratch.
+template <typename S, int NT>
+__device__ void sym_tail(const SolveArgs& a, int ld, S* Vc, S* spare1, S* spare2, double* s_sig, int* s_perm,
+                         int nvec, int sweeps, bool converged, int warm) {
+    using SC = Scal<S>;
+    const int tid = threadIdx.x;
+    const int m = a.m;
+    const int slots = a.slots;
+    DevState* st = a.st;
+    const int oldest = st->oldest;
+    const int nw = NT / 64, lane = tid & 63, wv = tid >> 6;
+    __shared__ int s_reff;
+    // sigma = sqrt(|d|), sorted descending (stable in the index)
+    for (int i = tid; i < m; i += NT) {
+        const double si = s_sig[i];
+        int rank = 0;
+        for (int j = 0; j < m; ++j) {
+            const double sj = s_sig[j];
+            rank += (sj > si) || (sj == si && j < i);
+        }
+        s_perm[rank] = i;
+        a.sigma[rank] = si;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const double s0 = s_sig[s_perm[0]];
+        int k = 0;
+        if (s0 > 0.0) {
+            const double thr = a.rcond * s0;
+            const int lim = a.r < m ? a.r : m;
+            while (k < lim && s_sig[s_perm[k]] > thr) ++k;
+        }
+        s_reff = k;
+    }
+    // the eigenvectors in sigma order, kept for the next solve's warm start
+    // (only when all m are known)
+    if (nvec >= m) {
+        for (int idx = tid; idx < m * m; idx += NT) {
+            const int i = idx % m, k = idx / m;
+            store_s<S>(a.Vfull, i + (int64_t)k * m, Vc[i + (size_t)s_perm[k] * ld]);
+        }
+    }
+    __syncthreads();
+    const int k_eff = s_reff;
+
+    // canonical V_r: column perm[k] of V, phase so that its largest-modulus
+    // entry (lowest index on ties) is real positive
+    S* Vr = spare1;  // m x k_eff, leading dimension ld
+    for (int k = wv; k < k_eff; k += nw) {
+        const int col = s_perm[k];
+        double best = -1.0;
+        int bi = 0;
+        for (int i = lane; i < m; i += 64) {
+            const double v = SC::absv(Vc[i + (size_t)col * ld]);
+            if (v > best) { best = v; bi = i; }
+        }
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double ob = __shfl_xor(best, off, 64);
+            const int oi = __shfl_xor(bi, off, 64);
+            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        const S ph = SC::cj(SC::phase(Vc[bi + (size_t)col * ld]));
+        for (int i = lane; i < m; i += 64) {
+            const S v = mulr(Vc[i + (size_t)col * ld], ph);
+            Vr[i + (size_t)k * ld] = v;
+            store_s<S>(a.V, i + (int64_t)k * m, v);
+        }
+    }
+    __syncthreads();
+
+    // T = xty V_r (m x k_eff) with xty[i][j] = <x_i, x_{j+1}>
+    S* T = spare2;
+    for (int idx = tid; idx < m * k_eff; idx += NT) {
+        const int i = idx % m, b = idx / m;
+        const int si = slot_of(oldest, i, slots);
+        S acc = SC::zero();
+        for (int j = 0; j < m; ++j)
+            acc = acc + mulr(gram_at<S>(a.G, si, slot_of(oldest, j + 1, slots), slots), Vr[j + (size_t)b * ld]);
+        T[i + (size_t)b * ld] = acc;
+    }
+    __syncthreads();
+
+    // A~[p][q] = (V_r^* T)[p][q] / (sigma_p sigma_q)
+    for (int idx = tid; idx < k_eff * k_eff; idx += NT) {
+        const int p = idx % k_eff, q = idx / k_eff;
+        S acc = SC::zero();
+        for (int i = 0; i < m; ++i) acc = acc + mulr(SC::cj(Vr[i + (size_t)p * ld]), T[i + (size_t)q * ld]);
+        const double sp = s_sig[s_perm[p]], sq = s_sig[s_perm[q]];
+        store_s<S>(a.At, p + (int64_t)q * k_eff, acc * (1.0 / (sp * sq)));
+    }
+    // POD coefficients V_r Sigma^-1 (row-major m x r, real or interleaved complex)
+    const int cw = (sizeof(S) == sizeof(cplx)) ? 2 : 1;
+    for (int idx = tid; idx < m * k_eff; idx += NT) {
+        const int i = idx / k_eff, q = idx % k_eff;
+        const S v = Vr[i + (size_t)q * ld] * (1.0 / s_sig[s_perm[q]]);
+        const cplx cv = SC::toc(v);
+        const int64_t o = (int64_t)i * cw * a.r + (int64_t)cw * q;
+        if (a.coef_f64) {
+            double* B = reinterpret_cast<double*>(a.Bpod);
+            B[o] = cv.re;
+            if (cw == 2) B[o + 1] = cv.im;
+        } else {
+            float* B = reinterpret_cast<float*>(a.Bpod);
+            B[o] = (float)cv.re;
+            if (cw == 2) B[o + 1] = (float)cv.im;
+        }
+    }
+    if (tid == 0) {
+        const int lim = a.r < m ? a.r : m;
+        st->skipped = 0;
+        st->r_eff = k_eff;
+        st->sweeps = sweeps;
+        st->solve_status = converged ? (k_eff < lim ? ST_W_RANK : ST_OK) : ST_E_CONVERGENCE;
+        if (k_eff == 0) st->solve_status = ST_W_RANK;
+        st->vprev_valid = (converged && nvec >= m) ? 1 : 0;
+        st->vprev_push = st->pushes;
+        st->warm = warm;
+    }
+}
+
 // LDS: matrices in dynamic LDS (real, M <= 64); else in the global workspace.
 // PMAX: largest number of rotation pairs per round (M / 2).
 template <typename S, int NT, bool LDS, int PMAX>
@@ -194,7 +323,7 @@ __device__ void solve_sym_body(const SolveArgs& a, int M) {
     __shared__ double s_c[PMAX], s_s[PMAX];
     __shared__ S s_e[PMAX];
     __shared__ int s_p[PMAX], s_q[PMAX];
-    __shared__ int s_rot, s_reff, s_warm;
+    __shared__ int s_rot, s_warm;
     __shared__ double s_red[NT / 64];
     __shared__ double s_sig[2 * PMAX];
     __shared__ int s_perm[2 * PMAX];
@@ -388,109 +517,7 @@ __device__ void solve_sym_body(const SolveArgs& a, int M) {
         spare1 = bufA;
         spare2 = bufQ;
     }
-    // sigma = sqrt(|d|), sorted descending (stable in the index)
-    for (int i = tid; i < m; i += NT) {
-        const double si = s_sig[i];
-        int rank = 0;
-        for (int j = 0; j < m; ++j) {
-            const double sj = s_sig[j];
-            rank += (sj > si) || (sj == si && j < i);
-        }
-        s_perm[rank] = i;
-        a.sigma[rank] = si;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        const double s0 = s_sig[s_perm[0]];
-        int k = 0;
-        if (s0 > 0.0) {
-            const double thr = a.rcond * s0;
-            const int lim = a.r < m ? a.r : m;
-            while (k < lim && s_sig[s_perm[k]] > thr) ++k;
-        }
-        s_reff = k;
-    }
-    // all m eigenvectors in sigma order, kept for the next solve's warm start
-    for (int idx = tid; idx < m * m; idx += NT) {
-        const int i = idx % m, k = idx / m;
-        store_s<S>(a.Vfull, i + (int64_t)k * m, Vc[i + (size_t)s_perm[k] * ld]);
-    }
-    __syncthreads();
-    const int k_eff = s_reff;
-
-    // canonical V_r: column perm[k] of V, phase so that its largest-modulus
-    // entry (lowest index on ties) is real positive
-    S* Vr = spare1;  // m x k_eff, leading dimension ld
-    for (int k = wv; k < k_eff; k += nw) {
-        const int col = s_perm[k];
-        double best = -1.0;
-        int bi = 0;
-        for (int i = lane; i < m; i += 64) {
-            const double v = SC::absv(Vc[i + (size_t)col * ld]);
-            if (v > best) { best = v; bi = i; }
-        }
-        for (int off = 32; off >= 1; off >>= 1) {
-            const double ob = __shfl_xor(best, off, 64);
-            const int oi = __shfl_xor(bi, off, 64);
-            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-        }
-        const S ph = SC::cj(SC::phase(Vc[bi + (size_t)col * ld]));
-        for (int i = lane; i < m; i += 64) {
-            const S v = mulr(Vc[i + (size_t)col * ld], ph);
-            Vr[i + (size_t)k * ld] = v;
-            store_s<S>(a.V, i + (int64_t)k * m, v);
-        }
-    }
-    __syncthreads();
-
-    // T = xty V_r (m x k_eff) with xty[i][j] = <x_i, x_{j+1}>
-    S* T = spare2;
-    for (int idx = tid; idx < m * k_eff; idx += NT) {
-        const int i = idx % m, b = idx / m;
-        const int si = slot_of(oldest, i, slots);
-        S acc = SC::zero();
-        for (int j = 0; j < m; ++j)
-            acc = acc + mulr(gram_at<S>(a.G, si, slot_of(oldest, j + 1, slots), slots), Vr[j + (size_t)b * ld]);
-        T[i + (size_t)b * ld] = acc;
-    }
-    __syncthreads();
-
-    // A~[p][q] = (V_r^* T)[p][q] / (sigma_p sigma_q)
-    for (int idx = tid; idx < k_eff * k_eff; idx += NT) {
-        const int p = idx % k_eff, q = idx / k_eff;
-        S acc = SC::zero();
-        for (int i = 0; i < m; ++i) acc = acc + mulr(SC::cj(Vr[i + (size_t)p * ld]), T[i + (size_t)q * ld]);
-        const double sp = s_sig[s_perm[p]], sq = s_sig[s_perm[q]];
-        store_s<S>(a.At, p + (int64_t)q * k_eff, acc * (1.0 / (sp * sq)));
-    }
-    // POD coefficients V_r Sigma^-1 (row-major m x r, real or interleaved complex)
-    const int cw = (sizeof(S) == sizeof(cplx)) ? 2 : 1;
-    for (int idx = tid; idx < m * k_eff; idx += NT) {
-        const int i = idx / k_eff, q = idx % k_eff;
-        const S v = Vr[i + (size_t)q * ld] * (1.0 / s_sig[s_perm[q]]);
-        const cplx cv = SC::toc(v);
-        const int64_t o = (int64_t)i * cw * a.r + (int64_t)cw * q;
-        if (a.coef_f64) {
-            double* B = reinterpret_cast<double*>(a.Bpod);
-            B[o] = cv.re;
-            if (cw == 2) B[o + 1] = cv.im;
-        } else {
-            float* B = reinterpret_cast<float*>(a.Bpod);
-            B[o] = (float)cv.re;
-            if (cw == 2) B[o + 1] = (float)cv.im;
-        }
-    }
-    if (tid == 0) {
-        const int lim = a.r < m ? a.r : m;
-        st->skipped = 0;
-        st->r_eff = k_eff;
-        st->sweeps = sweep + (converged ? 1 : 0);
-        st->solve_status = converged ? (k_eff < lim ? ST_W_RANK : ST_OK) : ST_E_CONVERGENCE;
-        if (k_eff == 0) st->solve_status = ST_W_RANK;
-        st->vprev_valid = converged ? 1 : 0;
-        st->vprev_push = st->pushes;
-        st->warm = warm;
-    }
+    sym_tail<S, NT>(a, ld, Vc, spare1, spare2, s_sig, s_perm, m, sweep + (converged ? 1 : 0), converged, warm);
 }
 
 template <typename S, int NT, bool LDS, int PMAX>
@@ -795,6 +822,7 @@ __device__ void solve_eig_body(const SolveArgs& a) {
         __syncthreads();
     }
     __shared__ double s_mod[kRMax], s_arg[kRMax];
+    __shared__ cplx s_ls[kRMax];  // eigenvalues in sorted order
     if (lane < k) {
         s_mod[lane] = cabs(lam_q);
         s_arg[lane] = atan2(lam_q.im, lam_q.re);
@@ -820,6 +848,7 @@ __device__ void solve_eig_body(const SolveArgs& a) {
             rank += (mp > mq) || (mp == mq && app < aq) || (mp == mq && app == aq && p < q);
         }
         s_rank[q] = rank;
+        s_ls[rank] = lam_q;
         a.lam[2 * rank] = lam_q.re;
         a.lam[2 * rank + 1] = lam_q.im;
         for (int i = 0; i < k; ++i) {
@@ -830,6 +859,96 @@ __device__ void solve_eig_body(const SolveArgs& a) {
         }
     }
     __syncthreads();
+
+    // ---- mode amplitudes b = (W Lambda)^-1 alpha_1 (Sec. 3.3), alpha_1 = the
+    // POD coefficients of the first snapshot = Sigma_r V_r^* e_1 (first row
+    // of V_r); Gaussian elimination with partial pivoting on W Lambda (in H,
+    // free now), lanes over rows.  Then the background mode argmin |log
+    // lambda| (Algorithm 3) and its factor b_i lambda_i^m for the newest
+    // snapshot.
+    __shared__ cplx s_rhs[kRMax];
+    __shared__ cplx s_fbg;
+    __shared__ int s_bg;
+    for (int idx = lane; idx < k * k; idx += 64) {
+        const int i = idx % k, q = idx / k;
+        H[i + q * LDH] = Y[i + q * LDH] * s_ls[q];
+    }
+    if (lane < k) {
+        const cplx v0 = a.cplx ? cplx{a.V[2 * ((int64_t)lane * m)], a.V[2 * ((int64_t)lane * m) + 1]}
+                               : mkc(a.V[(int64_t)lane * m]);
+        s_rhs[lane] = s_sig[lane] * conj(v0);
+    }
+    __syncthreads();
+    for (int c = 0; c < k; ++c) {
+        double best = -1.0;
+        int bi = c;
+        if (lane >= c && lane < k) {
+            best = abs2(H[lane + c * LDH]);
+            bi = lane;
+        }
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double ob = __shfl_xor(best, off, 64);
+            const int oi = __shfl_xor(bi, off, 64);
+            if (ob > best || (ob == best && oi < bi)) {
+                best = ob;
+                bi = oi;
+            }
+        }
+        if (bi != c) {
+            for (int j = lane; j < k; j += 64) {
+                const cplx t = H[c + j * LDH];
+                H[c + j * LDH] = H[bi + j * LDH];
+                H[bi + j * LDH] = t;
+            }
+            if (lane == 0) {
+                const cplx t = s_rhs[c];
+                s_rhs[c] = s_rhs[bi];
+                s_rhs[bi] = t;
+            }
+        }
+        __syncthreads();
+        const cplx piv = H[c + c * LDH];
+        if (lane > c && lane < k) {
+            const cplx f = cdiv(H[lane + c * LDH], piv);
+            for (int j = c + 1; j < k; ++j) H[lane + j * LDH] = H[lane + j * LDH] - f * H[c + j * LDH];
+            s_rhs[lane] = s_rhs[lane] - f * s_rhs[c];
+        }
+        __syncthreads();
+    }
+    for (int c = k - 1; c >= 0; --c) {
+        if (lane == 0) s_rhs[c] = cdiv(s_rhs[c], H[c + c * LDH]);
+        __syncthreads();
+        if (lane < c) s_rhs[lane] = s_rhs[lane] - H[lane + c * LDH] * s_rhs[c];
+        __syncthreads();
+    }
+    if (lane < k) {
+        a.amp[2 * lane] = s_rhs[lane].re;
+        a.amp[2 * lane + 1] = s_rhs[lane].im;
+    }
+    if (lane == 0) {
+        double best = 0.0;
+        int bi = -1;
+        for (int q = 0; q < k; ++q) {
+            const cplx lq = s_ls[q];
+            const double mod = cabs(lq);
+            if (!(mod > 0.0)) continue;
+            const double d = hypot(log(mod), atan2(lq.im, lq.re));
+            if (bi < 0 || d < best) {
+                best = d;
+                bi = q;
+            }
+        }
+        if (bi < 0) bi = 0;
+        s_bg = bi;
+        st->bg_index = bi;
+        // lambda^m = |lambda|^m e^{i m arg lambda}
+        const cplx lb = s_ls[bi];
+        const double pm = pow(cabs(lb), (double)m), th = (double)m * atan2(lb.im, lb.re);
+        s_fbg = s_rhs[bi] * cplx{pm * cos(th), pm * sin(th)};
+    }
+    __syncthreads();
+    const int bgq = s_bg;
+    const cplx fbg = s_fbg;
 
     // ---- C = V_r Sigma^-1 W (m x k complex), row-major with row stride 2 r;
     // lane i keeps row i of V_r Sigma^-1 in registers, W (sorted) is in LDS
@@ -853,6 +972,17 @@ __device__ void solve_eig_body(const SolveArgs& a) {
                 if (p + 1 < k) acc1 = acc1 + vrow[p + 1] * Y[p + 1 + q * LDH];
             }
             const cplx acc = acc0 + acc1;
+            if (q == bgq && a.Bbg) {
+                // background coefficients beta_i = C[i][bg] b_bg lambda_bg^m
+                const cplx bt = acc * fbg;
+                if (a.coef_f64) {
+                    reinterpret_cast<double*>(a.Bbg)[2 * i] = bt.re;
+                    reinterpret_cast<double*>(a.Bbg)[2 * i + 1] = bt.im;
+                } else {
+                    reinterpret_cast<float*>(a.Bbg)[2 * i] = (float)bt.re;
+                    reinterpret_cast<float*>(a.Bbg)[2 * i + 1] = (float)bt.im;
+                }
+            }
             const int64_t o = (int64_t)i * 2 * a.r + 2 * q;
             if (a.coef_f64) {
                 double* B = reinterpret_cast<double*>(a.Bphi);
@@ -884,6 +1014,355 @@ void k_solve_eig_grouped(const SolveArgs* __restrict__ items) {
     solve_eig_body(a);
 }
 
+// --------------------------------------------------------------------------
+// k_solve_trid: the symmetric solve of k_solve_sym by a method with O(m)
+// dependent steps instead of O(m) per Jacobi sweep, for large windows:
+//   1. Householder reduction of xtx to a real symmetric tridiagonal T
+//      (Hermitian input: complex reflectors, T still real);
+//   2. all eigenvalues of T by multisection: NT / m lanes per eigenvalue
+//      evaluate Sturm counts at equally spaced points of its bracket;
+//   3. eigenvectors of T for the r largest |eigenvalues| by twisted
+//      factorizations (forward L D L^T and backward U D U^T of T - lambda I,
+//      twist where |gamma_k| is smallest, then the two one-term recurrences),
+//      re-orthogonalized where two eigenvalues nearly coincide;
+//   4. back-transformation by the reflectors, one half-wavefront per vector.
+// The result feeds the same tail as the Jacobi solve.
+// --------------------------------------------------------------------------
+
+// Eigenvalues of the tridiagonal (d, e2 = e^2), scaled so that every Gershgorin
+// radius is at most 1, below x: sign changes of the leading principal minors
+// p_k = (d_k - x) p_{k-1} - e_{k-1}^2 p_{k-2} (an exact zero counts as a sign
+// change), rescaled by powers of two to stay in range.
+__device__ __forceinline__ int sturm_count(const double* __restrict__ d, const double* __restrict__ e2, int n,
+                                           double x) {
+    double a = 1.0, b = d[0] - x;
+    if (b == 0.0) b = -0x1p-900;
+    int cnt = b < 0.0;
+    for (int k = 1; k < n; ++k) {
+        double c = fma(d[k] - x, b, -e2[k - 1] * a);
+        a = b;
+        if (c == 0.0) c = -copysign(0x1p-900, a);
+        const double ac = fabs(c);
+        if (ac > 0x1p500 || ac < 0x1p-500) {
+            const double sc = ac > 1.0 ? 0x1p-500 : 0x1p500;
+            a *= sc;
+            c *= sc;
+        }
+        cnt += (c < 0.0) != (a < 0.0);
+        b = c;
+    }
+    return cnt;
+}
+
+template <typename S, int NT, bool LDS>
+__device__ void solve_trid_body(const SolveArgs& a) {
+    using SC = Scal<S>;
+    extern __shared__ double dyn[];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int m = a.m, n = m;
+    const int slots = a.slots;
+    DevState* st = a.st;
+    if (st->count < m + 1) {
+        if (tid == 0) {
+            st->solve_status = ST_E_NOT_READY;
+            st->r_eff = 0;
+        }
+        return;
+    }
+    if (st->vprev_valid && st->pushes == st->vprev_push) {
+        if (tid == 0) st->skipped = 1;
+        return;
+    }
+    const int oldest = st->oldest;
+    const int ld = n + 1;
+    const int nv = a.r < n ? a.r : n;  // eigenvectors computed: the r largest |eigenvalues|
+
+    __shared__ double s_d[kMaxM], s_e[kMaxM], s_e2[kMaxM], s_lam[kMaxM];
+    __shared__ S s_tau[kMaxM], s_v[kMaxM], s_p[kMaxM];
+    __shared__ double s_sig[kMaxM];
+    __shared__ int s_perm[kMaxM], s_sel[kRMax], s_twist[kRMax];
+    __shared__ double s_scale;
+
+    // storage: A (n x ld) in LDS for small windows, else in the workspace;
+    // the multipliers of the twisted factorizations (2 n nv doubles) in LDS;
+    // Z (n x nv) and the tail's scratch after A in the workspace
+    S* A = LDS ? reinterpret_cast<S*>(dyn) : reinterpret_cast<S*>(a.work);
+    double* LU = LDS ? dyn + (size_t)n * ld * (sizeof(S) / sizeof(double)) : dyn;
+    S* Z = reinterpret_cast<S*>(a.work) + (size_t)n * ld;
+    S* spare1 = Z + (size_t)n * ld;
+    S* spare2 = spare1 + (size_t)n * ld;
+
+    for (int idx = tid; idx < n * n; idx += NT) {
+        const int i = idx % n, j = idx / n;
+        A[i + (size_t)j * ld] = gram_at<S>(a.G, slot_of(oldest, i, slots), slot_of(oldest, j, slots), slots);
+    }
+    __syncthreads();
+
+    // ---- 1. Householder tridiagonalization: T = Q^* xtx Q, Q = H_0 ... H_{n-2},
+    // H_j = I - tau_j v_j v_j^*, v_j = (1, A[j+2.., j]) acting on rows j+1..
+    for (int j = 0; j + 1 < n; ++j) {
+        const int L = n - j - 1;
+        S* col = A + (size_t)j * ld + (j + 1);  // x = A[j+1.., j]
+        if (wv == 0) {
+            double xn2 = 0.0;
+            for (int i = 1 + lane; i < L; i += 64) xn2 += SC::absv(col[i]) * SC::absv(col[i]);
+            for (int off = 32; off >= 1; off >>= 1) xn2 += __shfl_xor(xn2, off, 64);
+            const cplx alpha = SC::toc(col[0]);
+            cplx tau = mkc(0.0), scal = mkc(0.0);
+            double beta = alpha.re;
+            if (!(xn2 == 0.0 && alpha.im == 0.0)) {
+                beta = -copysign(sqrt(alpha.re * alpha.re + alpha.im * alpha.im + xn2), alpha.re);
+                tau = cplx{(beta - alpha.re) / beta, -alpha.im / beta};
+                scal = cdiv(mkc(1.0), alpha - mkc(beta));
+            }
+            for (int i = 1 + lane; i < L; i += 64) {
+                const S v = SC::fromc(SC::toc(col[i]) * scal);
+                col[i] = v;
+                s_v[i] = v;
+            }
+            if (lane == 0) {
+                s_v[0] = SC::one();
+                s_tau[j] = SC::fromc(tau);
+                s_e[j] = beta;
+                s_d[j] = SC::re(A[j + (size_t)j * ld]);
+            }
+        }
+        __syncthreads();
+        // (tau = 0 leaves A22 unchanged: p = 0, c = 0)
+        const cplx tau = SC::toc(s_tau[j]);
+        S* A22 = A + (size_t)(j + 1) * ld + (j + 1);
+        // p = tau A22 v: group of G lanes per column i (A22 Hermitian: row i = conj(column i))
+        {
+            int G = 64;
+            while (G > 1 && G * L > NT) G >>= 1;
+            const int gi = tid / G, gl = tid % G;
+            for (int i = gi; i < L; i += NT / G) {
+                cplx acc = mkc(0.0);
+                const S* ci = A22 + (size_t)i * ld;
+                for (int k = gl; k < L; k += G) acc = acc + conj(SC::toc(ci[k])) * SC::toc(s_v[k]);
+                for (int off = G >> 1; off >= 1; off >>= 1) {
+                    acc.re += __shfl_xor(acc.re, off, 64);
+                    acc.im += __shfl_xor(acc.im, off, 64);
+                }
+                if (gl == 0) s_p[i] = SC::fromc(tau * acc);
+            }
+        }
+        __syncthreads();
+        // c = -tau/2 (p^* v) (every wavefront reduces it itself), w = p + c v,
+        // A22 <- A22 - v w^* - w v^*
+        cplx pv = mkc(0.0);
+        for (int k = lane; k < L; k += 64) pv = pv + conj(SC::toc(s_p[k])) * SC::toc(s_v[k]);
+        for (int off = 32; off >= 1; off >>= 1) {
+            pv.re += __shfl_xor(pv.re, off, 64);
+            pv.im += __shfl_xor(pv.im, off, 64);
+        }
+        const cplx c = -0.5 * (tau * pv);
+        for (int idx = tid; idx < L * L; idx += NT) {
+            const int k = idx % L, i = idx / L;
+            const cplx vk = SC::toc(s_v[k]), vi = SC::toc(s_v[i]);
+            const cplx wk = SC::toc(s_p[k]) + c * vk, wi = SC::toc(s_p[i]) + c * vi;
+            const cplx upd = vk * conj(wi) + wk * conj(vi);
+            S& ak = A22[k + (size_t)i * ld];
+            ak = SC::fromc(SC::toc(ak) - upd);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        s_d[n - 1] = SC::re(A[(n - 1) + (size_t)(n - 1) * ld]);
+        s_e[n - 1] = 0.0;
+        double g = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const double r = fabs(s_d[i]) + (i > 0 ? fabs(s_e[i - 1]) : 0.0) + fabs(s_e[i]);
+            g = r > g ? r : g;
+        }
+        s_scale = g;
+    }
+    __syncthreads();
+    const double scale = s_scale;
+    const double inv = scale > 0.0 ? 1.0 / scale : 0.0;
+    for (int i = tid; i < n; i += NT) {
+        s_d[i] *= inv;
+        s_e[i] *= inv;
+        s_e2[i] = s_e[i] * s_e[i];
+    }
+    __syncthreads();
+
+    // ---- 2. eigenvalues: G lanes per eigenvalue, bracket [-1, 1] split into
+    // G+1 parts per iteration until its width is 4 eps (absolute, ||T|| <= 1)
+    {
+        int np2 = 1;
+        while (np2 < n) np2 <<= 1;
+        int G = NT / np2;
+        G = G > 64 ? 64 : (G < 1 ? 1 : G);
+        const int gi = tid / G, gl = tid % G;
+        const int gshift = (tid & 63) / G * G;  // first lane of the group inside the wavefront
+        int iters = 1;
+        {
+            double w = 2.0;
+            while (w > 4.0 * kEps) {
+                w /= (double)(G + 1);
+                ++iters;
+            }
+        }
+        double lo = -1.0 - 4.0 * kEps, hi = 1.0 + 4.0 * kEps;
+        for (int it = 0; it < iters; ++it) {
+            const double x = lo + (hi - lo) * (double)(gl + 1) / (double)(G + 1);
+            const bool above = gi < n ? sturm_count(s_d, s_e2, n, x) > gi : true;
+            const uint64_t mask = __ballot(above);
+            const uint64_t grp = (G == 64) ? mask : ((mask >> gshift) & ((1ull << G) - 1));
+            if (grp == 0) {
+                lo = lo + (hi - lo) * (double)G / (double)(G + 1);
+            } else {
+                const int f = __builtin_ctzll(grp);  // first point above the eigenvalue
+                const double nlo = f == 0 ? lo : lo + (hi - lo) * (double)f / (double)(G + 1);
+                hi = lo + (hi - lo) * (double)(f + 1) / (double)(G + 1);
+                lo = nlo;
+            }
+        }
+        if (gi < n && gl == 0) s_lam[gi] = 0.5 * (lo + hi);
+    }
+    __syncthreads();
+
+    // order by |lambda| descending (ties: larger lambda first); sigma = sqrt(|lambda|)
+    for (int i = tid; i < n; i += NT) {
+        const double li = s_lam[i], ai = fabs(li);
+        int rank = 0;
+        for (int j2 = 0; j2 < n; ++j2) {
+            const double aj = fabs(s_lam[j2]);
+            rank += (aj > ai) || (aj == ai && j2 > i);
+        }
+        s_perm[rank] = i;
+        s_sig[rank] = sqrt(ai * scale);
+        if (rank < nv) s_sel[rank] = i;
+    }
+    __syncthreads();
+
+    // ---- 3. eigenvectors of T by twisted factorizations, one lane per vector
+    if (tid < nv) {
+        const int v = tid;
+        const double lam = s_lam[s_sel[v]];
+        double* Lm = LU;            // Lm[i * nv + v], i < n-1
+        double* Um = LU + (size_t)n * nv;  // Um[i * nv + v], 1 <= i < n
+        const double tiny = 0x1p-900;
+        double Dp = s_d[0] - lam;
+        for (int i = 0; i + 1 < n; ++i) {
+            if (Dp == 0.0) Dp = tiny;
+            const double l = s_e[i] * rcp_fast(Dp);
+            Lm[(size_t)i * nv + v] = l;
+            Dp = s_d[i + 1] - lam - l * s_e[i];
+        }
+        double Dm = s_d[n - 1] - lam;
+        for (int i = n - 1; i >= 1; --i) {
+            if (Dm == 0.0) Dm = tiny;
+            const double u = s_e[i - 1] * rcp_fast(Dm);
+            Um[(size_t)i * nv + v] = u;
+            Dm = s_d[i - 1] - lam - u * s_e[i - 1];
+        }
+        // twist index: argmin |gamma_k|, gamma_k = (d_k - lam) - L_{k-1} e_{k-1} - U_{k+1} e_k
+        double best = 1e308;
+        int tw = 0;
+        for (int k = 0; k < n; ++k) {
+            double g = s_d[k] - lam;
+            if (k > 0) g -= Lm[(size_t)(k - 1) * nv + v] * s_e[k - 1];
+            if (k + 1 < n) g -= Um[(size_t)(k + 1) * nv + v] * s_e[k];
+            if (fabs(g) < best) {
+                best = fabs(g);
+                tw = k;
+            }
+        }
+        s_twist[v] = tw;
+        // z_tw = 1, z_i = -L_i z_{i+1} (i < tw), z_{i+1} = -U_{i+1} z_i (i >= tw); written to Z
+        S* zc = Z + (size_t)v * ld;
+        double z = 1.0, nrm2 = 1.0;
+        zc[tw] = SC::fromc(mkc(1.0));
+        for (int i = tw - 1; i >= 0; --i) {
+            z = -Lm[(size_t)i * nv + v] * z;
+            nrm2 += z * z;
+            zc[i] = SC::fromc(mkc(z));
+        }
+        z = 1.0;
+        for (int i = tw; i + 1 < n; ++i) {
+            z = -Um[(size_t)(i + 1) * nv + v] * z;
+            nrm2 += z * z;
+            zc[i + 1] = SC::fromc(mkc(z));
+        }
+        const double sc = rsqrt_acc(nrm2);
+        for (int i = 0; i < n; ++i) zc[i] = SC::fromc(SC::toc(zc[i]) * sc);
+    }
+    __syncthreads();
+    // nearly coincident eigenvalues: Gram-Schmidt in selection order (one wavefront)
+    if (wv == 0) {
+        for (int q = 1; q < nv; ++q) {
+            for (int p = 0; p < q; ++p) {
+                if (fabs(s_lam[s_sel[q]] - s_lam[s_sel[p]]) > 1e-8) continue;
+                S* zq = Z + (size_t)q * ld;
+                const S* zp = Z + (size_t)p * ld;
+                double dot = 0.0;
+                for (int i = lane; i < n; i += 64) dot += SC::re(zp[i]) * SC::re(zq[i]);
+                for (int off = 32; off >= 1; off >>= 1) dot += __shfl_xor(dot, off, 64);
+                double nn = 0.0;
+                for (int i = lane; i < n; i += 64) {
+                    const double zi = SC::re(zq[i]) - dot * SC::re(zp[i]);
+                    zq[i] = SC::fromc(mkc(zi));
+                    nn += zi * zi;
+                }
+                for (int off = 32; off >= 1; off >>= 1) nn += __shfl_xor(nn, off, 64);
+                const double sc = nn > 0.0 ? rsqrt_acc(nn) : 0.0;
+                for (int i = lane; i < n; i += 64) zq[i] = SC::fromc(SC::toc(zq[i]) * sc);
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- 4. back-transformation Z <- H_0 ... H_{n-2} Z, one half-wavefront per
+    // vector (columns are independent: no barrier between reflectors)
+    {
+        const int hw = tid >> 5, hl = tid & 31;
+        for (int v = hw; v < nv; v += NT / 32) {
+            S* zc = Z + (size_t)v * ld;
+            for (int j = n - 2; j >= 0; --j) {
+                const cplx tau = SC::toc(s_tau[j]);
+                if (tau.re == 0.0 && tau.im == 0.0) continue;
+                const int L = n - j - 1;
+                const S* vj = A + (size_t)j * ld + (j + 1);  // v_0 = 1 is implicit
+                cplx w = mkc(0.0);
+                for (int i = hl; i < L; i += 32) {
+                    const cplx vi = i == 0 ? mkc(1.0) : SC::toc(vj[i]);
+                    w = w + conj(vi) * SC::toc(zc[j + 1 + i]);
+                }
+                for (int off = 16; off >= 1; off >>= 1) {
+                    w.re += __shfl_xor(w.re, off, 32);
+                    w.im += __shfl_xor(w.im, off, 32);
+                }
+                const cplx f = tau * w;
+                for (int i = hl; i < L; i += 32) {
+                    const cplx vi = i == 0 ? mkc(1.0) : SC::toc(vj[i]);
+                    zc[j + 1 + i] = SC::fromc(SC::toc(zc[j + 1 + i]) - vi * f);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // eigenvector index k of the tail = selection rank k (columns of Z)
+    for (int i = tid; i < n; i += NT) s_perm[i] = i;
+    __syncthreads();
+    sym_tail<S, NT>(a, ld, Z, spare1, spare2, s_sig, s_perm, nv, 0, true, 0);
+}
+
+template <typename S, int NT, bool LDS>
+__global__ __launch_bounds__(NT)
+void k_solve_trid(SolveArgs a) {
+    solve_trid_body<S, NT, LDS>(a);
+}
+
+template <typename S, int NT, bool LDS>
+__global__ __launch_bounds__(NT)
+void k_solve_trid_grouped(const SolveArgs* __restrict__ items) {
+    const SolveArgs a = items[blockIdx.x];
+    solve_trid_body<S, NT, LDS>(a);
+}
+
 }  // namespace
 
 hipError_t launch_solve_sym(const SolveArgs& a, hipStream_t s) {
@@ -904,6 +1383,25 @@ hipError_t launch_solve_sym(const SolveArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename S, bool LDS>
+static hipError_t launch_trid_one(const SolveArgs& a, hipStream_t s) {
+    const int n = a.m, nv = a.r < n ? a.r : n;
+    size_t lds = sizeof(double) * 2 * (size_t)n * nv;
+    if (LDS) lds += sizeof(S) * (size_t)n * (n + 1);
+    auto kern = k_solve_trid<S, 1024, LDS>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(1), dim3(1024), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_trid(const SolveArgs& a, hipStream_t s) {
+    if (a.r > kRMax || a.m > kMaxM) return hipErrorInvalidValue;
+    if (a.cplx) return a.m <= 32 ? launch_trid_one<cplx, true>(a, s) : launch_trid_one<cplx, false>(a, s);
+    return a.m <= 64 ? launch_trid_one<double, true>(a, s) : launch_trid_one<double, false>(a, s);
+}
+
 hipError_t launch_solve_eig(const SolveArgs& a, hipStream_t s) {
     if (a.r > kRMax) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_solve_eig, dim3(1), dim3(64), 0, s, a);
@@ -914,8 +1412,38 @@ hipError_t launch_solve_eig(const SolveArgs& a, hipStream_t s) {
 
 namespace dmd {
 
-hipError_t launch_solve_grouped(const SolveArgs* items_lds, int n_lds, const SolveArgs* items_glb, int n_glb,
-                                const SolveArgs* items_all, int n_all, hipStream_t s) {
+hipError_t launch_trid_grouped(const SolveArgs* items_lds, int n_lds, const SolveArgs* items_glb, int n_glb,
+                               hipStream_t s) {
+    // real windows; items_lds: m <= 64, items_glb: m > 64 (dynamic LDS sized for the largest)
+    if (n_lds > 0) {
+        const size_t lds = sizeof(double) * (2 * 64 * kRMax + 64 * 65);
+        auto kern = k_solve_trid_grouped<double, 1024, true>;
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(n_lds), dim3(1024), lds, s, items_lds);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (n_glb > 0) {
+        const size_t lds = sizeof(double) * 2 * kMaxM * kRMax;
+        auto kern = k_solve_trid_grouped<double, 1024, false>;
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(n_glb), dim3(1024), lds, s, items_glb);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_eig_grouped(const SolveArgs* items, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_solve_eig_grouped, dim3(n), dim3(64), 0, s, items);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi_grouped(const SolveArgs* items_lds, int n_lds, const SolveArgs* items_glb, int n_glb,
+                                 hipStream_t s) {
     if (n_lds > 0) {
         const size_t lds = 3 * sizeof(double) * 64 * 65;  // sized for M <= 64
         auto kern = k_solve_sym_grouped<double, 1024, true, 32>;
@@ -931,8 +1459,8 @@ hipError_t launch_solve_grouped(const SolveArgs* items_lds, int n_lds, const Sol
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_solve_eig_grouped, dim3(n_all), dim3(64), 0, s, items_all);
-    return hipGetLastError();
+    return hipSuccess;
 }
+
 
 }  // namespace dmd

@@ -103,3 +103,15 @@ def test_create_rejects_bad_block_options_without_gpu(dtype, max_block, code, ms
     rc = lib.dmd_stream_create(1000, 8, 4, ctypes.byref(o), ctypes.byref(h))
     assert rc == code
     assert msg in dmd.last_error()
+
+
+@pytest.mark.parametrize("solver,warm,msg", [(3, 0, "unknown eig_solver"), (2, 1, "warm_start needs")])
+def test_create_rejects_bad_solver_options_without_gpu(solver, warm, msg):
+    lib = dmd.load()
+    o = binding.Opts()
+    lib.dmd_opts_init(ctypes.byref(o))
+    o.eig_solver = solver
+    o.warm_start = warm
+    h = ctypes.c_void_p()
+    assert lib.dmd_stream_create(1000, 8, 4, ctypes.byref(o), ctypes.byref(h)) == dmd.E_INVAL
+    assert msg in dmd.last_error()

@@ -37,8 +37,15 @@ def check_eigs(stat, lam, sig, W, m, r):
     assert k == ref.r_eff, (k, ref.r_eff)
     err_s = metrics.sigma_relerr(sig, ref.sigma[:k])
     assert np.all(err_s <= sigma_tol(ref.sigma[:k])), err_s
-    err_l, _ = metrics.eig_relerr(lam, ref.lam)
+    err_l, perm = metrics.eig_relerr(lam, ref.lam)
     assert err_l.max() < 1e-8, err_l.max()
+    return ref, perm
+
+
+def check_phi(phi, ref, perm, k, tol):
+    for i in range(k):
+        e = metrics.phase_aligned_relerr(phi[:, i], ref.Phi[:, perm[i]])
+        assert e < tol, (i, e)
 
 
 def run_blocks(s, X, frames, blocks, m, r, phi_tol, every_window=True):
@@ -57,15 +64,25 @@ def run_blocks(s, X, frames, blocks, m, r, phi_tol, every_window=True):
             continue
         wins, rc = s.block_eigs()
         assert len(wins) == k and rc in (0, 1)
+        sentinel = 7.0 + 7.0j
+        phis = s.block_modes(torch.full((s.max_block, r, s.n), sentinel, dtype=s.mode_dtype, device="cuda"))
+        phis = phis.cpu().numpy()
         for w, (stat, lam, sig) in enumerate(wins):
             te = t - k + w  # newest frame of window w
             if te < m:
                 assert stat == dmd.E_NOT_READY
+                assert np.all(phis[w] == sentinel)       # unsolved windows are left untouched
             elif every_window or w == 0:
-                check_eigs(stat, lam, sig, frames[:, te - m:te + 1], m, r)
-        # the last window is the current one: identical to eigs()
+                ref, perm = check_eigs(stat, lam, sig, frames[:, te - m:te + 1], m, r)
+                check_phi(phis[w].T, ref, perm, lam.size, phi_tol)
+                assert np.all(phis[w][lam.size:] == sentinel)
+        # the last window is the current one: identical to eigs() and modes()
         lam_c, sig_c, _ = s.eigs()
         assert np.array_equal(lam_c, wins[-1][1]) and np.array_equal(sig_c, wins[-1][2])
+        phi_c = s.modes().cpu().numpy()
+        kc = lam_c.size
+        np.testing.assert_allclose(phis[k - 1].T[:, :kc], phi_c[:, :kc], rtol=0,
+                                   atol=1e-6 * np.abs(phi_c[:, :kc]).max())
         check_window(s, frames[:, t - 1 - m:t], m, r, phi_tol=phi_tol)
 
 
@@ -163,6 +180,8 @@ def test_block_with_nonfinite_rejected_whole():
         assert np.array_equal(s.gram(), G0)
         wins, _ = s.block_eigs()
         assert [w[0] for w in wins] == [dmd.E_NONFINITE] * 3
+        out = s.block_modes(torch.full((4, r, 2048), 3.0, dtype=s.mode_dtype, device="cuda"))
+        assert torch.all(out == 3.0).item()
         lam1, sig1, _ = s.eigs()
         assert np.array_equal(lam0, lam1) and np.array_equal(sig0, sig1)
         s.push_block(X[10:13])           # the same frames without the bad value
@@ -182,6 +201,9 @@ def test_block_argument_errors():
         assert ei.value.code == dmd.E_INVAL
         with pytest.raises(dmd.DMDError) as ei:
             s.block_eigs()
+        assert ei.value.code == dmd.E_NOT_READY
+        with pytest.raises(dmd.DMDError) as ei:
+            s.block_modes()
         assert ei.value.code == dmd.E_NOT_READY
     with dmd.Stream(1000, 8, 4, dtype="c64_csr", max_nnz=16) as s:
         Xc = torch.zeros((1, 1000), dtype=torch.complex64, device="cuda")
@@ -205,7 +227,9 @@ def test_block_full_hd_video():
             s.push_block(X[t:t + kb])
         wins, _ = s.block_eigs()
         check_gram(s, frames[:, T - 1 - m:T])
+        phis = s.block_modes()
         for w in (0, kb // 2, kb - 1):
             te = T - kb + w
             stat, lam, sig = wins[w]
-            check_eigs(stat, lam, sig, frames[:, te - m:te + 1], m, r)
+            ref, perm = check_eigs(stat, lam, sig, frames[:, te - m:te + 1], m, r)
+            check_phi(phis[w].cpu().numpy().T, ref, perm, lam.size, 2e-4)

@@ -4,7 +4,7 @@ Every case pushes seeded synthetic frames through the C ABI and compares, per
 window, the streamed Gram, sigma, V, A~, lambda, W, Phi and U with the oracle
 computed from the same frames (widened exactly to FP64).
 
-Tolerances (derived in DESIGN.md):
+Tolerances:
 * Gram: products of FP32/FP64 data summed in FP64 in a different order than
   the oracle: |dG_ij| <= 1e-12 sqrt(G_ii G_jj).
 * sigma_k: the method of snapshots squares the condition number, so FP64
