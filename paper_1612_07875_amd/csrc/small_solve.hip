@@ -1032,26 +1032,88 @@ void k_solve_eig_grouped(const SolveArgs* __restrict__ items) {
 // Eigenvalues of the tridiagonal (d, e2 = e^2), scaled so that every Gershgorin
 // radius is at most 1, below x: sign changes of the leading principal minors
 // p_k = (d_k - x) p_{k-1} - e_{k-1}^2 p_{k-2} (an exact zero counts as a sign
-// change), rescaled by powers of two to stay in range.
+// change), rescaled by powers of two to stay in range.  |p_k| grows at most
+// threefold per step, so the range is checked every fourth step.
 __device__ __forceinline__ int sturm_count(const double* __restrict__ d, const double* __restrict__ e2, int n,
                                            double x) {
     double a = 1.0, b = d[0] - x;
     if (b == 0.0) b = -0x1p-900;
     int cnt = b < 0.0;
-    for (int k = 1; k < n; ++k) {
+    auto step = [&](int k) {
         double c = fma(d[k] - x, b, -e2[k - 1] * a);
+        if (c == 0.0) c = -copysign(0x1p-900, b);
+        cnt += (int)(((unsigned long long)__double_as_longlong(c) ^ (unsigned long long)__double_as_longlong(b)) >> 63);
         a = b;
-        if (c == 0.0) c = -copysign(0x1p-900, a);
-        const double ac = fabs(c);
-        if (ac > 0x1p500 || ac < 0x1p-500) {
-            const double sc = ac > 1.0 ? 0x1p-500 : 0x1p500;
-            a *= sc;
-            c *= sc;
-        }
-        cnt += (c < 0.0) != (a < 0.0);
         b = c;
+    };
+    auto rescale = [&]() {
+        const double ab = fabs(b);
+        if (ab > 0x1p500 || ab < 0x1p-500) {
+            const double sc = ab > 1.0 ? 0x1p-500 : 0x1p500;
+            a *= sc;
+            b *= sc;
+        }
+    };
+    int k = 1;
+    for (; k + 3 < n; k += 4) {
+        step(k);
+        step(k + 1);
+        step(k + 2);
+        step(k + 3);
+        rescale();
+    }
+    for (; k < n; ++k) {
+        step(k);
+        rescale();
     }
     return cnt;
+}
+
+template <typename S> __device__ __forceinline__ S shfl_xor_s(S v, int off, int width);
+template <> __device__ __forceinline__ double shfl_xor_s<double>(double v, int off, int width) {
+    return __shfl_xor(v, off, width);
+}
+template <> __device__ __forceinline__ cplx shfl_xor_s<cplx>(cplx v, int off, int width) {
+    return cplx{__shfl_xor(v.re, off, width), __shfl_xor(v.im, off, width)};
+}
+__device__ __forceinline__ double div_s(double a, double b) { return a / b; }
+__device__ __forceinline__ cplx div_s(cplx a, cplx b) { return cdiv(a, b); }
+
+// Householder reflector of column j (one wavefront): H = I - tau v v^* maps
+// x = A[j+1.., j] to (beta, 0, ..); v = (1, x[1..] / (alpha - beta)) is stored
+// over x[1..] and into vbuf, with tau, beta = e_j and d_j = A[j][j].
+template <typename S>
+__device__ void householder_col(S* A, int ld, int n, int j, S* vbuf, S* s_tau, double* s_e, double* s_d) {
+    using SC = Scal<S>;
+    const int lane = threadIdx.x & 63;
+    const int L = n - j - 1;
+    S* col = A + (size_t)j * ld + (j + 1);
+    double xn2 = 0.0;
+    for (int i = 1 + lane; i < L; i += 64) {
+        const double ax = SC::absv(col[i]);
+        xn2 += ax * ax;
+    }
+    for (int off = 32; off >= 1; off >>= 1) xn2 += __shfl_xor(xn2, off, 64);
+    const S alpha = col[0];
+    const double ar = SC::re(alpha), aa = SC::absv(alpha);
+    S tau = SC::zero(), scal = SC::zero();
+    double beta = ar;
+    if (!(xn2 == 0.0 && aa == ar)) {
+        beta = -copysign(sqrt(aa * aa + xn2), ar);
+        tau = (SC::fromc(mkc(beta)) - alpha) * (1.0 / beta);
+        scal = div_s(SC::one(), alpha - SC::fromc(mkc(beta)));
+    }
+    for (int i = 1 + lane; i < L; i += 64) {
+        const S v = mulr(col[i], scal);
+        col[i] = v;
+        vbuf[i] = v;
+    }
+    if (lane == 0) {
+        vbuf[0] = SC::one();
+        s_tau[j] = tau;
+        s_e[j] = beta;
+        s_d[j] = SC::re(A[j + (size_t)j * ld]);
+    }
 }
 
 template <typename S, int NT, bool LDS>
@@ -1079,14 +1141,15 @@ __device__ void solve_trid_body(const SolveArgs& a) {
     const int nv = a.r < n ? a.r : n;  // eigenvectors computed: the r largest |eigenvalues|
 
     __shared__ double s_d[kMaxM], s_e[kMaxM], s_e2[kMaxM], s_lam[kMaxM];
-    __shared__ S s_tau[kMaxM], s_v[kMaxM], s_p[kMaxM];
+    __shared__ S s_tau[kMaxM], s_v0[kMaxM], s_v1[kMaxM], s_p[kMaxM];
     __shared__ double s_sig[kMaxM];
-    __shared__ int s_perm[kMaxM], s_sel[kRMax], s_twist[kRMax];
+    __shared__ int s_perm[kMaxM], s_sel[kRMax];
     __shared__ double s_scale;
 
     // storage: A (n x ld) in LDS for small windows, else in the workspace;
-    // the multipliers of the twisted factorizations (2 n nv doubles) in LDS;
-    // Z (n x nv) and the tail's scratch after A in the workspace
+    // the multipliers of the twisted factorizations (2 n nv doubles) in LDS,
+    // later the eigenvectors during the back-transformation; Z (n x nv) and
+    // the tail's scratch after A in the workspace
     S* A = LDS ? reinterpret_cast<S*>(dyn) : reinterpret_cast<S*>(a.work);
     double* LU = LDS ? dyn + (size_t)n * ld * (sizeof(S) / sizeof(double)) : dyn;
     S* Z = reinterpret_cast<S*>(a.work) + (size_t)n * ld;
@@ -1101,70 +1164,54 @@ __device__ void solve_trid_body(const SolveArgs& a) {
 
     // ---- 1. Householder tridiagonalization: T = Q^* xtx Q, Q = H_0 ... H_{n-2},
     // H_j = I - tau_j v_j v_j^*, v_j = (1, A[j+2.., j]) acting on rows j+1..
+    // Per column: p = tau A22 v, then A22 -= v w^* + w v^* with w = p + c v,
+    // c = -tau (p^* v) / 2.  Wavefront 0 updates the next column first and
+    // builds its reflector while the others update the rest (two barriers
+    // per column).  Row j+1 of A22 is never used again and is not updated.
+    if (wv == 0) householder_col<S>(A, ld, n, 0, s_v0, s_tau, s_e, s_d);
+    __syncthreads();
     for (int j = 0; j + 1 < n; ++j) {
         const int L = n - j - 1;
-        S* col = A + (size_t)j * ld + (j + 1);  // x = A[j+1.., j]
-        if (wv == 0) {
-            double xn2 = 0.0;
-            for (int i = 1 + lane; i < L; i += 64) xn2 += SC::absv(col[i]) * SC::absv(col[i]);
-            for (int off = 32; off >= 1; off >>= 1) xn2 += __shfl_xor(xn2, off, 64);
-            const cplx alpha = SC::toc(col[0]);
-            cplx tau = mkc(0.0), scal = mkc(0.0);
-            double beta = alpha.re;
-            if (!(xn2 == 0.0 && alpha.im == 0.0)) {
-                beta = -copysign(sqrt(alpha.re * alpha.re + alpha.im * alpha.im + xn2), alpha.re);
-                tau = cplx{(beta - alpha.re) / beta, -alpha.im / beta};
-                scal = cdiv(mkc(1.0), alpha - mkc(beta));
-            }
-            for (int i = 1 + lane; i < L; i += 64) {
-                const S v = SC::fromc(SC::toc(col[i]) * scal);
-                col[i] = v;
-                s_v[i] = v;
-            }
-            if (lane == 0) {
-                s_v[0] = SC::one();
-                s_tau[j] = SC::fromc(tau);
-                s_e[j] = beta;
-                s_d[j] = SC::re(A[j + (size_t)j * ld]);
-            }
-        }
-        __syncthreads();
-        // (tau = 0 leaves A22 unchanged: p = 0, c = 0)
-        const cplx tau = SC::toc(s_tau[j]);
+        const S* v = (j & 1) ? s_v1 : s_v0;
+        S* vnext = (j & 1) ? s_v0 : s_v1;
+        const S tau = s_tau[j];
         S* A22 = A + (size_t)(j + 1) * ld + (j + 1);
-        // p = tau A22 v: group of G lanes per column i (A22 Hermitian: row i = conj(column i))
         {
             int G = 64;
             while (G > 1 && G * L > NT) G >>= 1;
             const int gi = tid / G, gl = tid % G;
             for (int i = gi; i < L; i += NT / G) {
-                cplx acc = mkc(0.0);
+                S acc = SC::zero();
                 const S* ci = A22 + (size_t)i * ld;
-                for (int k = gl; k < L; k += G) acc = acc + conj(SC::toc(ci[k])) * SC::toc(s_v[k]);
-                for (int off = G >> 1; off >= 1; off >>= 1) {
-                    acc.re += __shfl_xor(acc.re, off, 64);
-                    acc.im += __shfl_xor(acc.im, off, 64);
-                }
-                if (gl == 0) s_p[i] = SC::fromc(tau * acc);
+                for (int k = gl; k < L; k += G) acc = acc + mulr(SC::cj(ci[k]), v[k]);
+                for (int off = G >> 1; off >= 1; off >>= 1) acc = acc + shfl_xor_s<S>(acc, off, 64);
+                if (gl == 0) s_p[i] = mulr(tau, acc);
             }
         }
         __syncthreads();
-        // c = -tau/2 (p^* v) (every wavefront reduces it itself), w = p + c v,
-        // A22 <- A22 - v w^* - w v^*
-        cplx pv = mkc(0.0);
-        for (int k = lane; k < L; k += 64) pv = pv + conj(SC::toc(s_p[k])) * SC::toc(s_v[k]);
-        for (int off = 32; off >= 1; off >>= 1) {
-            pv.re += __shfl_xor(pv.re, off, 64);
-            pv.im += __shfl_xor(pv.im, off, 64);
-        }
-        const cplx c = -0.5 * (tau * pv);
-        for (int idx = tid; idx < L * L; idx += NT) {
-            const int k = idx % L, i = idx / L;
-            const cplx vk = SC::toc(s_v[k]), vi = SC::toc(s_v[i]);
-            const cplx wk = SC::toc(s_p[k]) + c * vk, wi = SC::toc(s_p[i]) + c * vi;
-            const cplx upd = vk * conj(wi) + wk * conj(vi);
-            S& ak = A22[k + (size_t)i * ld];
-            ak = SC::fromc(SC::toc(ak) - upd);
+        S pv = SC::zero();
+        for (int k = lane; k < L; k += 64) pv = pv + mulr(SC::cj(s_p[k]), v[k]);
+        for (int off = 32; off >= 1; off >>= 1) pv = pv + shfl_xor_s<S>(pv, off, 64);
+        const S c = mulr(tau, pv) * (-0.5);
+        if (wv == 0) {
+            const S v0 = v[0], w0 = s_p[0] + mulr(c, v0);
+            for (int k = lane; k < L; k += 64) {
+                const S vk = v[k], wk = s_p[k] + mulr(c, vk);
+                A22[k] = A22[k] - (mulr(vk, SC::cj(w0)) + mulr(wk, SC::cj(v0)));
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (j + 2 < n) householder_col<S>(A, ld, n, j + 1, vnext, s_tau, s_e, s_d);
+        } else {
+            const int L1 = L - 1;
+            for (int idx = tid - 64; idx < L1 * L1; idx += NT - 64) {
+                const int k = 1 + idx % L1, i = 1 + idx / L1;
+                const S vk = v[k], vi = v[i];
+                const S wk = s_p[k] + mulr(c, vk), wi = s_p[i] + mulr(c, vi);
+                S& ak = A22[k + (size_t)i * ld];
+                ak = ak - (mulr(vk, SC::cj(wi)) + mulr(wk, SC::cj(vi)));
+            }
         }
         __syncthreads();
     }
@@ -1242,7 +1289,7 @@ __device__ void solve_trid_body(const SolveArgs& a) {
     if (tid < nv) {
         const int v = tid;
         const double lam = s_lam[s_sel[v]];
-        double* Lm = LU;            // Lm[i * nv + v], i < n-1
+        double* Lm = LU;                   // Lm[i * nv + v], i < n-1
         double* Um = LU + (size_t)n * nv;  // Um[i * nv + v], 1 <= i < n
         const double tiny = 0x1p-900;
         double Dp = s_d[0] - lam;
@@ -1271,11 +1318,10 @@ __device__ void solve_trid_body(const SolveArgs& a) {
                 tw = k;
             }
         }
-        s_twist[v] = tw;
-        // z_tw = 1, z_i = -L_i z_{i+1} (i < tw), z_{i+1} = -U_{i+1} z_i (i >= tw); written to Z
+        // z_tw = 1, z_i = -L_i z_{i+1} (i < tw), z_{i+1} = -U_{i+1} z_i (i >= tw); into Z, normalized
         S* zc = Z + (size_t)v * ld;
         double z = 1.0, nrm2 = 1.0;
-        zc[tw] = SC::fromc(mkc(1.0));
+        zc[tw] = SC::one();
         for (int i = tw - 1; i >= 0; --i) {
             z = -Lm[(size_t)i * nv + v] * z;
             nrm2 += z * z;
@@ -1288,7 +1334,14 @@ __device__ void solve_trid_body(const SolveArgs& a) {
             zc[i + 1] = SC::fromc(mkc(z));
         }
         const double sc = rsqrt_acc(nrm2);
-        for (int i = 0; i < n; ++i) zc[i] = SC::fromc(SC::toc(zc[i]) * sc);
+        for (int i = 0; i < n; ++i) zc[i] = zc[i] * sc;
+    }
+    __syncthreads();
+    // the eigenvectors move into LDS (over the multipliers) for the rest of the work
+    S* Zs = reinterpret_cast<S*>(LU);  // Zs[i + v n]
+    for (int idx = tid; idx < n * nv; idx += NT) {
+        const int i = idx % n, v = idx / n;
+        Zs[i + (size_t)v * n] = Z[i + (size_t)v * ld];
     }
     __syncthreads();
     // nearly coincident eigenvalues: Gram-Schmidt in selection order (one wavefront)
@@ -1296,8 +1349,8 @@ __device__ void solve_trid_body(const SolveArgs& a) {
         for (int q = 1; q < nv; ++q) {
             for (int p = 0; p < q; ++p) {
                 if (fabs(s_lam[s_sel[q]] - s_lam[s_sel[p]]) > 1e-8) continue;
-                S* zq = Z + (size_t)q * ld;
-                const S* zp = Z + (size_t)p * ld;
+                S* zq = Zs + (size_t)q * n;
+                const S* zp = Zs + (size_t)p * n;
                 double dot = 0.0;
                 for (int i = lane; i < n; i += 64) dot += SC::re(zp[i]) * SC::re(zq[i]);
                 for (int off = 32; off >= 1; off >>= 1) dot += __shfl_xor(dot, off, 64);
@@ -1309,7 +1362,7 @@ __device__ void solve_trid_body(const SolveArgs& a) {
                 }
                 for (int off = 32; off >= 1; off >>= 1) nn += __shfl_xor(nn, off, 64);
                 const double sc = nn > 0.0 ? rsqrt_acc(nn) : 0.0;
-                for (int i = lane; i < n; i += 64) zq[i] = SC::fromc(SC::toc(zq[i]) * sc);
+                for (int i = lane; i < n; i += 64) zq[i] = zq[i] * sc;
             }
         }
     }
@@ -1320,30 +1373,30 @@ __device__ void solve_trid_body(const SolveArgs& a) {
     {
         const int hw = tid >> 5, hl = tid & 31;
         for (int v = hw; v < nv; v += NT / 32) {
-            S* zc = Z + (size_t)v * ld;
+            S* zc = Zs + (size_t)v * n;
             for (int j = n - 2; j >= 0; --j) {
-                const cplx tau = SC::toc(s_tau[j]);
-                if (tau.re == 0.0 && tau.im == 0.0) continue;
+                const S tau = s_tau[j];
                 const int L = n - j - 1;
                 const S* vj = A + (size_t)j * ld + (j + 1);  // v_0 = 1 is implicit
-                cplx w = mkc(0.0);
+                S w = SC::zero();
                 for (int i = hl; i < L; i += 32) {
-                    const cplx vi = i == 0 ? mkc(1.0) : SC::toc(vj[i]);
-                    w = w + conj(vi) * SC::toc(zc[j + 1 + i]);
+                    const S vi = i == 0 ? SC::one() : vj[i];
+                    w = w + mulr(SC::cj(vi), zc[j + 1 + i]);
                 }
-                for (int off = 16; off >= 1; off >>= 1) {
-                    w.re += __shfl_xor(w.re, off, 32);
-                    w.im += __shfl_xor(w.im, off, 32);
-                }
-                const cplx f = tau * w;
+                for (int off = 16; off >= 1; off >>= 1) w = w + shfl_xor_s<S>(w, off, 32);
+                const S f = mulr(tau, w);
                 for (int i = hl; i < L; i += 32) {
-                    const cplx vi = i == 0 ? mkc(1.0) : SC::toc(vj[i]);
-                    zc[j + 1 + i] = SC::fromc(SC::toc(zc[j + 1 + i]) - vi * f);
+                    const S vi = i == 0 ? SC::one() : vj[i];
+                    zc[j + 1 + i] = zc[j + 1 + i] - mulr(vi, f);
                 }
             }
         }
     }
     __syncthreads();
+    for (int idx = tid; idx < n * nv; idx += NT) {
+        const int i = idx % n, v = idx / n;
+        Z[i + (size_t)v * ld] = Zs[i + (size_t)v * n];
+    }
     // eigenvector index k of the tail = selection rank k (columns of Z)
     for (int i = tid; i < n; i += NT) s_perm[i] = i;
     __syncthreads();
