@@ -44,6 +44,9 @@ def parse():
                     help="block: k frames per step (multi-column update, every window solved and projected); "
                          "single: one frame per step")
     ap.add_argument("--block", type=int, default=32, help="frames per block in block mode (1..64)")
+    ap.add_argument("--precision", choices=("fp32", "bf16x3"), default="fp32",
+                    help="arithmetic of the mode projections: FP32 MFMA, or three BF16 MFMA products "
+                         "(hi*hi + hi*lo + lo*hi) with FP32 accumulation")
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default 20 blocks / 100 frames)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 2 blocks / 10 frames)")
     ap.add_argument("--latency-frames", type=int, default=40, help="single-frame pushes timed one by one")
@@ -297,7 +300,7 @@ def bench_single(args):
     keep = M + 1 + (args.cpu_windows if not args.no_cpu_baseline else 0)
     frames, host_keep = make_frames(T, keep)
 
-    s = dmd.Stream(n, M, R, dtype="f32")
+    s = dmd.Stream(n, M, R, dtype="f32", precision=args.precision)
     phi = torch.zeros((R, n), dtype=torch.complex64, device="cuda").T
     for t in range(M + 1):
         s.push(frames[t])
@@ -337,7 +340,7 @@ def bench_single(args):
         "workload": "blob video 1920x1080 FP32 (n=2073600), m=64, r=20; single-frame mode: "
                     "step = push of one frame + FP64 solves + modes of its window",
         "n": n, "m": M, "r": R, "r_eff": int(r_eff), "frames_per_step": 1,
-        "precision": "FP64 Gram accumulation, FP64 solves, FP32 modes"})
+        "precision": precision_note(args)})
     out.update({"roofline": roofline, "kernels": kernels,
                 "gram_GBps": kernels.get("gram_columns", {}).get("algorithmic_GBps"),
                 "latency_ms": latency, "jacobi_sweeps": int(info.sweeps), "qr_iters": int(info.qr_iters)})
@@ -361,7 +364,7 @@ def bench_block(args):
     keep = M + 1 + (args.cpu_windows if not args.no_cpu_baseline else 0)
     frames, host_keep = make_frames(T, keep)
 
-    s = dmd.Stream(n, M, R, dtype="f32", max_block=kb)
+    s = dmd.Stream(n, M, R, dtype="f32", max_block=kb, precision=args.precision)
     phis = torch.zeros((kb, R, n), dtype=torch.complex64, device="cuda")
     t = 0
     while t < fill:                      # the window fills with block pushes as well
@@ -418,7 +421,7 @@ def bench_block(args):
         "workload": f"blob video 1920x1080 FP32 (n=2073600), m=64, r=20; block mode: step = one push of "
                     f"{kb} frames (multi-column update) + FP64 solves of all {kb} windows + modes of all {kb} windows",
         "n": n, "m": M, "r": R, "r_eff": int(r_eff), "frames_per_step": kb,
-        "precision": "FP64 Gram accumulation, FP64 solves, FP32 modes"})
+        "precision": precision_note(args)})
     blat = np.array(blat) if blat else None
     out.update({"roofline": roofline, "kernels": kernels,
                 "gram_GBps": kernels.get("gram_block", {}).get("algorithmic_GBps"),
@@ -429,6 +432,11 @@ def bench_block(args):
                                                        "the same stream after the timed blocks",
                 "jacobi_sweeps": int(info.sweeps), "qr_iters": int(info.qr_iters)})
     return out, host_keep
+
+
+def precision_note(args):
+    modes = "FP32 modes" if args.precision == "fp32" else "BF16x3 modes (FP32 accumulation)"
+    return "FP64 Gram accumulation, FP64 solves, " + modes
 
 
 def result_line(value, K, Wu, elapsed, dtype, config):

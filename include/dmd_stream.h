@@ -82,10 +82,15 @@ typedef enum {
 
 typedef enum {
     DMD_PREC_DEFAULT = 0, /* FP64 for F64 data, FP32 for F32 / C64 data          */
-    DMD_PREC_FP32    = 1, /* projections in FP32 (MFMA), FP32 accumulation       */
-    DMD_PREC_BF16X3  = 2, /* projections as three BF16 MFMA products (hi*hi +
-                             hi*lo + lo*hi), FP32 accumulation                    */
-    DMD_PREC_FP64    = 3  /* projections in FP64                                  */
+    DMD_PREC_FP32    = 1, /* dense contractions in FP32 (MFMA), FP32 accumulation */
+    DMD_PREC_BF16X3  = 2, /* F32 data only: dense contractions as three BF16 MFMA
+                             products (hi*hi + hi*lo + lo*hi), FP32 accumulation:
+                             the projections (modes, POD modes, the modes of a
+                             block push, grouped batch projections) and the
+                             whole-window Gram (dmd_stream_load_window,
+                             dmd_stream_resync)                                   */
+    DMD_PREC_FP64    = 3  /* F32 data: coefficients, projections and the
+                             whole-window Gram in FP64                            */
 } dmd_precision_t;
 
 typedef enum {
@@ -98,9 +103,11 @@ typedef enum {
 
 typedef struct {
     int32_t dtype;       /* dmd_dtype_t (default DMD_F32)                           */
-    int32_t precision;   /* dmd_precision_t for the tall-skinny projections; the
-                            per-frame inner products always accumulate in FP64 and
-                            the small solves always run in FP64                     */
+    int32_t precision;   /* dmd_precision_t for the dense contractions (the
+                            tall-skinny projections and the whole-window Gram);
+                            the per-frame inner products and the block Gram of a
+                            block push always accumulate in FP64, and the small
+                            solves always run in FP64                               */
     int32_t max_nnz;     /* DMD_C64_CSR: capacity per snapshot (0 = n)              */
     int32_t max_sweeps;  /* Jacobi sweep limit (0 = 40)                              */
     int32_t max_qr_iter; /* Hessenberg-QR iterations per eigenvalue (0 = 60)         */

@@ -219,8 +219,11 @@ struct BlockProjectArgs {
     int64_t bphi_stride;
     float2* out;
     int64_t ldo, ldw;
+    int bf16x3;                    // products as three BF16 MFMAs (DMD_PREC_BF16X3), else FP32
 };
 hipError_t launch_project_block(const BlockProjectArgs& a, hipStream_t s);
+// Whether the one-pass block projection's LDS tiles fit for these sizes.
+bool project_block_fits(int m, int k, int r);
 
 // Background subtraction of the newest snapshot (Sec. 3.3, Algorithm 3): with
 // beta = b_i lambda_i^m C[:, i] (background mode i, written by the eig solve),

@@ -708,7 +708,7 @@ DMD_API int dmd_stream_block_modes(dmd_stream_t* h, void* phi, int64_t ld, int64
     HIP_TRY(begin(h, s));
     const int k = h->last_block_k;
     const size_t celem = h->coef_f64 ? 16 : 8;  // complex128 or complex64
-    if (h->elem_bytes == 4 && !h->coef_f64) {
+    if (h->elem_bytes == 4 && !h->coef_f64 && dmd::project_block_fits(h->m, k, h->r)) {
         dmd::BlockProjectArgs a{};
         a.ring = h->ring;
         a.ld = h->ld;
@@ -727,9 +727,10 @@ DMD_API int dmd_stream_block_modes(dmd_stream_t* h, void* phi, int64_t ld, int64
         a.out = static_cast<float2*>(phi);
         a.ldo = ld;
         a.ldw = ldw;
+        a.bf16x3 = h->opts.precision == DMD_PREC_BF16X3;
         HIP_TRY(timed("project_block", s, [&] { return dmd::launch_project_block(a, s); }));
     } else {
-        // FP64 data or coefficients: one projection per window, each from its own state
+        // FP64 data or coefficients, or tiles beyond the LDS: one projection per window from its own state
         for (int w = 0; w < k; ++w) {
             dmd::ProjectArgs a;
             char* out = static_cast<char*>(phi) + (size_t)w * ldw * celem;

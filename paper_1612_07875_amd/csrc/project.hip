@@ -28,6 +28,20 @@ constexpr int kRowsPerBlock = kThreads / 64 * kRowsPerWave;
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// x = hi + lo with hi = bf16(x), lo = bf16(x - hi): the BF16x3 split.
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+    hi = (__bf16)x;
+    lo = (__bf16)(x - (float)hi);
+}
+// acc += a b in three BF16 products (hi*hi + hi*lo + lo*hi), FP32 accumulation;
+// the small terms first.
+__device__ __forceinline__ v4f mma_bf16x3(const v8bf& ahi, const v8bf& alo, const v8bf& bhi, const v8bf& blo, v4f acc) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo, acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi, acc, 0, 0, 0);
+}
 
 template <typename T> struct Acc;
 template <> struct Acc<float> {
@@ -50,12 +64,14 @@ template <> struct Acc<double> {
 // The A and B fragments of the next group of four k-steps are loaded while
 // the current group's MFMAs run; output tiles go through LDS so that every
 // store instruction writes 64 consecutive rows of one output column.
+constexpr int kOLD = 17;  // padded row length of the output stage
+constexpr int kStage = kThreads / 64 * 64 * kOLD;
+
 template <typename TX, typename T, int NT>
-__device__ void project_body(const ProjectArgs& a, int blk) {
+__device__ void project_body(const ProjectArgs& a, int blk, T* stage) {
     using AccT = typename Acc<T>::type;
     constexpr int KG = sizeof(T) == 8 ? 2 : 4;  // k-steps (of 4 columns) per group
-    constexpr int OLD = 17;                // padded row length of the output stage
-    __shared__ T stage[kThreads / 64][64 * OLD];
+    constexpr int OLD = kOLD;
     const DevState* st = a.st;
     if (st->solve_status == ST_E_NOT_READY) return;
     if (a.block_only && st->block_rejected) return;
@@ -120,7 +136,7 @@ __device__ void project_body(const ProjectArgs& a, int blk) {
     }
 
     T* out = reinterpret_cast<T*>(a.out);
-    T* sw = stage[wave];
+    T* sw = stage + wave * 64 * OLD;
     const int64_t row = row0 + lane;  // the row this lane stores
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
@@ -157,14 +173,123 @@ __device__ void project_body(const ProjectArgs& a, int blk) {
     }
 }
 
+// BF16x3 form (FP32 ring and coefficients, DMD_PREC_BF16X3): per chunk of 32
+// window columns each lane holds 8 consecutive columns of one row (A) and 8
+// consecutive rows of one coefficient column (B) of the 16x16x32 fragments
+// (A[l%16][8(l/16)+e], B[8(l/16)+e][l%16]; D as the f32 16x16x4 layout).
+template <int NT>
+__device__ void project_body_bf3(const ProjectArgs& a, int blk, float* stage) {
+    constexpr int OLD = kOLD;
+    const DevState* st = a.st;
+    if (st->solve_status == ST_E_NOT_READY) return;
+    if (a.block_only && st->block_rejected) return;
+    const int k_eff = st->r_eff;
+    const int kcols = a.cplx_out ? 2 * k_eff : k_eff;
+    if (kcols == 0) return;
+    const int m = a.m;
+    const int rowstride = a.cplx_out ? 2 * a.kmax : a.kmax;
+    const float* B = reinterpret_cast<const float*>(a.B);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lq = lane >> 4;
+    const int64_t row0 = (int64_t)blk * kRowsPerBlock + wave * kRowsPerWave;
+    const int oldest = st->oldest;
+    const float* ring = reinterpret_cast<const float*>(a.ring);
+
+    v4f acc[4][NT];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = v4f{0, 0, 0, 0};
+    for (int c0 = 0; c0 < m; c0 += 32) {
+        v8bf ahi[4], alo[4];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int col = c0 + 8 * lq + e;
+            const bool cin = col < m;
+            const float* cp = ring + (int64_t)slot_of(oldest, a.first + (cin ? col : 0), a.slots) * a.ld;
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
+                const int64_t r = row0 + 16 * rt + li;
+                const float x = (cin && r < a.n) ? cp[r] : 0.0f;
+                __bf16 h, l;
+                split_bf16(x, h, l);
+                ahi[rt][e] = h;
+                alo[rt][e] = l;
+            }
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            v8bf bhi, blo;
+            const int c = 16 * nt + li;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int col = c0 + 8 * lq + e;
+                const float y = (col < m && c < kcols) ? B[(int64_t)col * rowstride + c] : 0.0f;
+                __bf16 h, l;
+                split_bf16(y, h, l);
+                bhi[e] = h;
+                blo[e] = l;
+            }
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) acc[rt][nt] = mma_bf16x3(ahi[rt], alo[rt], bhi, blo, acc[rt][nt]);
+        }
+    }
+
+    float* out = reinterpret_cast<float*>(a.out);
+    float* sw = stage + wave * 64 * OLD;
+    const int64_t row = row0 + lane;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        if (16 * nt >= kcols) break;
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sw[(16 * rt + 4 * lq + v) * OLD + li] = acc[rt][nt][v];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (row < a.n) {
+            if (a.cplx_out) {
+#pragma unroll
+                for (int cc = 0; cc < 16; cc += 2) {
+                    const int c = 16 * nt + cc;
+                    if (c < kcols) {
+                        const int64_t o = 2 * (row + (int64_t)(c >> 1) * a.ldo);
+                        out[o] = sw[lane * OLD + cc];
+                        out[o + 1] = sw[lane * OLD + cc + 1];
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int cc = 0; cc < 16; ++cc) {
+                    const int c = 16 * nt + cc;
+                    if (c < kcols) out[row + (int64_t)c * a.ldo] = sw[lane * OLD + cc];
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
 template <typename TX, typename T, int NT>
 __global__ __launch_bounds__(kThreads)
 void k_project_mfma(ProjectArgs a) {
-    project_body<TX, T, NT>(a, blockIdx.x);
+    __shared__ T stage[kStage];
+    project_body<TX, T, NT>(a, blockIdx.x, stage);
 }
 
-// Grouped form over many streams (FP32 ring and coefficients): block b
-// belongs to item i with blk_start[i] <= b < blk_start[i+1].
+template <int NT>
+__global__ __launch_bounds__(kThreads)
+void k_project_bf3(ProjectArgs a) {
+    __shared__ float stage[kStage];
+    project_body_bf3<NT>(a, blockIdx.x, stage);
+}
+
+// Grouped form over many streams (FP32 ring and coefficients; each item in
+// FP32 or BF16x3 by its precision): block b belongs to item i with
+// blk_start[i] <= b < blk_start[i+1].
 template <int NT>
 __global__ __launch_bounds__(kThreads)
 void k_project_grouped(const ProjectArgs* __restrict__ items, const int* __restrict__ blk_start, int nitems) {
@@ -176,13 +301,22 @@ void k_project_grouped(const ProjectArgs* __restrict__ items, const int* __restr
         else hi = mid - 1;
     }
     const ProjectArgs a = items[lo];
-    project_body<float, float, NT>(a, b - blk_start[lo]);
+    __shared__ float stage[kStage];
+    if (a.precision == 2 /* DMD_PREC_BF16X3 */) project_body_bf3<NT>(a, b - blk_start[lo], stage);
+    else project_body<float, float, NT>(a, b - blk_start[lo], stage);
 }
 
 template <typename TX, typename T, int NT>
 hipError_t launch_nt(const ProjectArgs& a, hipStream_t s) {
     const unsigned gx = (unsigned)((a.n + kRowsPerBlock - 1) / kRowsPerBlock);
     hipLaunchKernelGGL((k_project_mfma<TX, T, NT>), dim3(gx), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int NT>
+hipError_t launch_bf3_nt(const ProjectArgs& a, hipStream_t s) {
+    const unsigned gx = (unsigned)((a.n + kRowsPerBlock - 1) / kRowsPerBlock);
+    hipLaunchKernelGGL(k_project_bf3<NT>, dim3(gx), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -202,11 +336,17 @@ hipError_t launch_tiles(const ProjectArgs& a, hipStream_t s, int kc_max) {
 // rows between n and the padded length are zero) and each wavefront
 // multiplies them by the coefficient matrices of windows wave, wave+4, ...:
 // the ring is read once for all k windows instead of k times.  Requires k <= 64.
+// BF3: each chunk of 32 window columns as three BF16 16x16x32 products
+// (hi*hi + hi*lo + lo*hi) instead of eight FP32 16x16x4 steps; element e of
+// a lane's 8-wide fragment is window column 4e + lane/16 of the chunk, the
+// same columns the FP32 form's k-step e reads, so both stage reads hit the
+// same banks.
 constexpr int kBlkRows = 64;
 constexpr int kBlkLDR = kBlkRows + 16;  // column stride: the four k-slots of a fragment hit distinct banks
+constexpr size_t kBlockLdsMax = 150 * 1024;  // dynamic LDS of the one-pass block projection
 constexpr int kBlkOLD = 17;             // padded row length of the output stage
 
-template <int NT>
+template <int NT, bool BF3>
 __global__ __launch_bounds__(kThreads, 3)
 void k_project_block(BlockProjectArgs a) {
     extern __shared__ float dynp[];
@@ -246,27 +386,59 @@ void k_project_block(BlockProjectArgs a) {
         // coefficients of 8 k-steps (32 window columns) are loaded together
         // before their MFMAs, so the L2 latency is paid once per chunk
         for (int cb = 0; cb < m; cb += 32) {
-            float bv[8][NT];
+            if constexpr (BF3) {
+                v8bf bhi[NT], blo[NT];
 #pragma unroll
-            for (int ks = 0; ks < 8; ++ks) {
-                const int col = cb + 4 * ks + lk;
+                for (int ks = 0; ks < 8; ++ks) {
+                    const int col = cb + 4 * ks + lk;
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) {
-                    const int c = 16 * nt + li;
-                    bv[ks][nt] = (col < m && c < kc) ? B[(int64_t)col * rs + c] : 0.0f;
+                    for (int nt = 0; nt < NT; ++nt) {
+                        const int c = 16 * nt + li;
+                        __bf16 h, l;
+                        split_bf16((col < m && c < kc) ? B[(int64_t)col * rs + c] : 0.0f, h, l);
+                        bhi[nt][ks] = h;
+                        blo[nt][ks] = l;
+                    }
                 }
-            }
-#pragma unroll
-            for (int ks = 0; ks < 8; ++ks) {
-                const int col = cb + 4 * ks + lk;
-                const bool cin = col < m;
-                const float* ucol = U + (w + (cin ? col : 0)) * kBlkLDR;
 #pragma unroll
                 for (int rt = 0; rt < 4; ++rt) {
-                    const float av = cin ? ucol[16 * rt + li] : 0.0f;
+                    v8bf ahi, alo;
 #pragma unroll
-                    for (int nt = 0; nt < NT; ++nt)
-                        acc[rt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[ks][nt], acc[rt][nt], 0, 0, 0);
+                    for (int ks = 0; ks < 8; ++ks) {
+                        const int col = cb + 4 * ks + lk;
+                        const bool cin = col < m;
+                        const float av = cin ? U[(w + col) * kBlkLDR + 16 * rt + li] : 0.0f;
+                        __bf16 h, l;
+                        split_bf16(av, h, l);
+                        ahi[ks] = h;
+                        alo[ks] = l;
+                    }
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = mma_bf16x3(ahi, alo, bhi[nt], blo[nt], acc[rt][nt]);
+                }
+            } else {
+                float bv[8][NT];
+#pragma unroll
+                for (int ks = 0; ks < 8; ++ks) {
+                    const int col = cb + 4 * ks + lk;
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) {
+                        const int c = 16 * nt + li;
+                        bv[ks][nt] = (col < m && c < kc) ? B[(int64_t)col * rs + c] : 0.0f;
+                    }
+                }
+#pragma unroll
+                for (int ks = 0; ks < 8; ++ks) {
+                    const int col = cb + 4 * ks + lk;
+                    const bool cin = col < m;
+                    const float* ucol = U + (w + (cin ? col : 0)) * kBlkLDR;
+#pragma unroll
+                    for (int rt = 0; rt < 4; ++rt) {
+                        const float av = cin ? ucol[16 * rt + li] : 0.0f;
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt)
+                            acc[rt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[ks][nt], acc[rt][nt], 0, 0, 0);
+                    }
                 }
             }
         }
@@ -297,10 +469,15 @@ void k_project_block(BlockProjectArgs a) {
     }
 }
 
+size_t block_lds(int m, int k) {
+    return sizeof(float) * ((size_t)(m + k - 1) * kBlkLDR + (kThreads / 64) * 64 * kBlkOLD);
+}
+
 template <int NT>
 hipError_t launch_block_nt(const BlockProjectArgs& a, hipStream_t s) {
-    const size_t lds = sizeof(float) * ((size_t)(a.m + a.k - 1) * kBlkLDR + (kThreads / 64) * 64 * kBlkOLD);
-    auto kern = k_project_block<NT>;
+    const size_t lds = block_lds(a.m, a.k);
+    if (lds > kBlockLdsMax) return hipErrorInvalidValue;
+    auto kern = a.bf16x3 ? k_project_block<NT, true> : k_project_block<NT, false>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -310,6 +487,8 @@ hipError_t launch_block_nt(const BlockProjectArgs& a, hipStream_t s) {
 }
 
 }  // namespace
+
+bool project_block_fits(int m, int k, int r) { return 2 * r <= 64 && k <= 64 && block_lds(m, k) <= kBlockLdsMax; }
 
 hipError_t launch_project_block(const BlockProjectArgs& a, hipStream_t s) {
     const int kc_max = 2 * a.r;
@@ -334,6 +513,12 @@ hipError_t launch_project(const ProjectArgs& a, hipStream_t s) {
     if (kc_max > 64) return hipErrorInvalidValue;
     if (a.elem_f64) return launch_tiles<double, double>(a, s, kc_max);
     if (a.coef_f64) return launch_tiles<float, double>(a, s, kc_max);
+    if (a.precision == 2 /* DMD_PREC_BF16X3 */) {
+        if (kc_max <= 16) return launch_bf3_nt<1>(a, s);
+        if (kc_max <= 32) return launch_bf3_nt<2>(a, s);
+        if (kc_max <= 48) return launch_bf3_nt<3>(a, s);
+        return launch_bf3_nt<4>(a, s);
+    }
     return launch_tiles<float, float>(a, s, kc_max);
 }
 

@@ -233,3 +233,30 @@ def test_block_full_hd_video():
             stat, lam, sig = wins[w]
             ref, perm = check_eigs(stat, lam, sig, frames[:, te - m:te + 1], m, r)
             check_phi(phis[w].cpu().numpy().T, ref, perm, lam.size, 2e-4)
+
+
+@pytest.mark.parametrize("m,r,kb", [(160, 24, 32), (200, 32, 48)])
+def test_block_modes_large_windows(m, r, kb):
+    """Windows beyond the default shapes (m > 64, k up to 48): every window's
+    modes from the one-pass block projection must match the oracle."""
+    dmd = _dmd()
+    H, W = 100, 130
+    n = H * W
+    T = m + 1 + kb
+    frames = gen.BlobVideo(height=H, width=W, blob_sigma=4.0).frames(0, T)
+    X = torch.from_numpy(frames.T.copy()).cuda()
+    with dmd.Stream(n, m, r, max_block=kb) as s:
+        t = 0
+        while t < m + 1:
+            k = min(kb, m + 1 - t)
+            s.push_block(X[t:t + k])
+            t += k
+        s.push_block(X[t:t + kb])
+        t += kb
+        wins, _ = s.block_eigs()
+        phis = s.block_modes().cpu().numpy()
+        for w in (0, kb // 2, kb - 1):
+            te = t - kb + w
+            stat, lam, sig = wins[w]
+            ref, perm = check_eigs(stat, lam, sig, frames[:, te - m:te + 1], m, r)
+            check_phi(phis[w].T, ref, perm, lam.size, 2e-4)
