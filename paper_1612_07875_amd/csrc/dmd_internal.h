@@ -220,10 +220,14 @@ struct BlockProjectArgs {
     float2* out;
     int64_t ldo, ldw;
     int bf16x3;                    // products as three BF16 MFMAs (DMD_PREC_BF16X3), else FP32
+    int out16;                     // out, ldo and ldw allow 16-byte stores of two rows
+    uint4* cfrag;                  // project_block_frag_bytes(m, kmax) of scratch for the
+                                   // packed coefficients
 };
 hipError_t launch_project_block(const BlockProjectArgs& a, hipStream_t s);
 // Whether the one-pass block projection's LDS tiles fit for these sizes.
 bool project_block_fits(int m, int k, int r);
+size_t project_block_frag_bytes(int m, int kmax);
 
 // Background subtraction of the newest snapshot (Sec. 3.3, Algorithm 3): with
 // beta = b_i lambda_i^m C[:, i] (background mode i, written by the eig solve),

@@ -144,6 +144,7 @@ struct dmd_stream {
     double* sh_Vfull = nullptr;
     void* sh_Bphi = nullptr;
     void* sh_Bpod = nullptr;
+    uint4* cfrag = nullptr;       // block pushes: packed coefficients of the k windows
     dmd::SolveArgs* solve_tbl = nullptr;  // device: sets 0 .. kmax-2, then the current window
     int32_t last_block_k = 0;     // k of the latest push if it was a solved block push, else 0
 
@@ -190,7 +191,7 @@ void free_all(dmd_stream* h) {
     void* bufs[] = {h->ring, h->ring_idx, h->ring_val, h->ring_nnz, h->scatter, h->flag, h->G, h->partials,
                     h->res_dev, h->V, h->At, h->W, h->work, h->Vfull, h->gfull, h->Bphi, h->Bpod,
                     h->Bbg, h->bpartial, h->gblock, h->bflag, h->sh_dev, h->sh_V, h->sh_At, h->sh_W, h->sh_work,
-                    h->sh_Vfull, h->sh_Bphi, h->sh_Bpod, h->solve_tbl};
+                    h->sh_Vfull, h->sh_Bphi, h->sh_Bpod, h->cfrag, h->solve_tbl};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (h->res_host) (void)hipHostFree(h->res_host);
@@ -465,6 +466,7 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
         ALLOC(h->sh_Vfull, sizeof(double) * ns * z.Vfull);
         ALLOC(h->sh_Bphi, ns * z.Bphi);
         ALLOC(h->sh_Bpod, ns * z.Bpod);
+        ALLOC(h->cfrag, dmd::project_block_frag_bytes(m, h->kmax));
         if (rc == DMD_OK) {
             hipError_t e = hipHostMalloc((void**)&h->sh_host, ns * h->sh_stride,
                                          hipHostMallocMapped | hipHostMallocCoherent);
@@ -728,6 +730,8 @@ DMD_API int dmd_stream_block_modes(dmd_stream_t* h, void* phi, int64_t ld, int64
         a.ldo = ld;
         a.ldw = ldw;
         a.bf16x3 = h->opts.precision == DMD_PREC_BF16X3;
+        a.cfrag = h->cfrag;
+        a.out16 = (reinterpret_cast<uintptr_t>(phi) % 16 == 0) && ld % 2 == 0 && ldw % 2 == 0;
         HIP_TRY(timed("project_block", s, [&] { return dmd::launch_project_block(a, s); }));
     } else {
         // FP64 data or coefficients, or tiles beyond the LDS: one projection per window from its own state

@@ -17,6 +17,8 @@
 //   A: lane l holds A[l % 16][l / 16];  B: lane l holds B[l / 16][l % 16];
 //   D (f32): lane l holds D[4 (l / 16) + v][l % 16], v = 0..3;
 //   D (f64): lane l holds D[(l / 16) + 4 v][l % 16], v = 0..3.
+#include <type_traits>
+
 #include "dmd_internal.h"
 
 namespace dmd {
@@ -29,11 +31,24 @@ constexpr int kRowsPerBlock = kThreads / 64 * kRowsPerWave;
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+struct Frag {  // one lane's 8 coefficient values of a B fragment (k_pack_coef)
+    uint4 x, y;
+};
 
 // x = hi + lo with hi = bf16(x), lo = bf16(x - hi): the BF16x3 split.
 __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
     hi = (__bf16)x;
     lo = (__bf16)(x - (float)hi);
+}
+// The value of the neighbouring lane (lane ^ 1): DPP quad permutation 1,0,3,2.
+__device__ __forceinline__ float swap_pair(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, false));
+}
+// The split as one word: hi in the low half, lo in the high half.
+__device__ __forceinline__ unsigned split_word(float x) {
+    __bf16 h, l;
+    split_bf16(x, h, l);
+    return (unsigned)__builtin_bit_cast(unsigned short, h) | ((unsigned)__builtin_bit_cast(unsigned short, l) << 16);
 }
 // acc += a b in three BF16 products (hi*hi + hi*lo + lo*hi), FP32 accumulation;
 // the small terms first.
@@ -340,14 +355,18 @@ hipError_t launch_tiles(const ProjectArgs& a, hipStream_t s, int kc_max) {
 // (hi*hi + hi*lo + lo*hi) instead of eight FP32 16x16x4 steps; element e of
 // a lane's 8-wide fragment is window column 4e + lane/16 of the chunk, the
 // same columns the FP32 form's k-step e reads, so both stage reads hit the
-// same banks.
+// same banks.  The staged columns are split once, as (hi, lo) pairs in one
+// 32-bit word, and a fragment is put together from 8 words with 8 byte
+// permutes.  The coefficients of all k windows come packed in fragment order
+// (k_pack_coef: FP32, or BF16 hi and lo), two 16-byte loads per fragment.
 constexpr int kBlkRows = 64;
 constexpr int kBlkLDR = kBlkRows + 16;  // column stride: the four k-slots of a fragment hit distinct banks
 constexpr size_t kBlockLdsMax = 150 * 1024;  // dynamic LDS of the one-pass block projection
-constexpr int kBlkOLD = 17;             // padded row length of the output stage
 
+// Three waves per SIMD, two for the BF16x3 form with three or more column
+// tiles (whose A-fragment assembly needs the registers to prefetch two chunks).
 template <int NT, bool BF3>
-__global__ __launch_bounds__(kThreads, 3)
+__global__ __launch_bounds__(kThreads, (BF3 && NT >= 3) ? 2 : 3)
 void k_project_block(BlockProjectArgs a) {
     extern __shared__ float dynp[];
     const DevState* stf = a.st;
@@ -355,130 +374,225 @@ void k_project_block(BlockProjectArgs a) {
     const int m = a.m, k = a.k;
     const int ncols = m + k - 1;
     float* U = dynp;
-    float* stage = dynp + (size_t)ncols * kBlkLDR;
     const int64_t row0 = (int64_t)blockIdx.x * kBlkRows;
     const int base = stf->oldest + 2 - k + a.slots;  // slot of staged column 0, before the wrap
     const float* ring = static_cast<const float*>(a.ring);
     for (int t = threadIdx.x; t < ncols * (kBlkRows / 4); t += kThreads) {
         const int c = t / (kBlkRows / 4), q = t % (kBlkRows / 4);
         const float* src = ring + (int64_t)((base + c) % a.slots) * a.ld + row0 + 4 * q;
-        *reinterpret_cast<float4*>(&U[c * kBlkLDR + 4 * q]) = *reinterpret_cast<const float4*>(src);
+        const float4 x = *reinterpret_cast<const float4*>(src);
+        if constexpr (BF3) {
+            *reinterpret_cast<uint4*>(&U[c * kBlkLDR + 4 * q]) =
+                uint4{split_word(x.x), split_word(x.y), split_word(x.z), split_word(x.w)};
+        } else {
+            *reinterpret_cast<float4*>(&U[c * kBlkLDR + 4 * q]) = x;
+        }
     }
     __syncthreads();
+    const unsigned* U32 = reinterpret_cast<const unsigned*>(U);
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    float* sw = stage + wave * 64 * kBlkOLD;
-    const int rs = 2 * a.r;
+    const int nq = (m + 31) / 32;
+
+    // The coefficient fragments of a window's first PF chunks (as many as the
+    // registers allow: two, one or none) are loaded before the previous
+    // window's output stores: vector-memory completions are counted in issue
+    // order, so a load issued after those stores could not be waited for
+    // without waiting for the stores as well.
+    constexpr int PF = (NT <= 3 || BF3) ? 2 : 1;
+    auto load_frag = [&](int w, int q, Frag (&f)[NT]) {
+        const uint4* fb = a.cfrag + ((size_t)(w * nq + q) * NT * 64 + lane) * 2;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            f[nt].x = fb[nt * 128];
+            f[nt].y = fb[nt * 128 + 1];
+        }
+    };
+    // acc += (window w's columns cb .. cb+31) x (their coefficient fragments)
+    auto chunk = [&](int w, int cb, const Frag (&f)[NT], v4f (&acc)[4][NT]) {
+        const bool full = cb + 32 <= m;  // a whole chunk (the common case) needs no masks
+        if constexpr (BF3) {
+            v8bf bhi[NT], blo[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                bhi[nt] = __builtin_bit_cast(v8bf, f[nt].x);
+                blo[nt] = __builtin_bit_cast(v8bf, f[nt].y);
+            }
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
+                unsigned d[8];
+#pragma unroll
+                for (int ks = 0; ks < 8; ++ks) {
+                    const int col = cb + 4 * ks + lk;
+                    const bool cin = full || col < m;
+                    const unsigned v = U32[(w + (cin ? col : 0)) * kBlkLDR + 16 * rt + li];
+                    d[ks] = cin ? v : 0u;
+                }
+                uint4 h, l;
+                h.x = __builtin_amdgcn_perm(d[1], d[0], 0x05040100u);
+                h.y = __builtin_amdgcn_perm(d[3], d[2], 0x05040100u);
+                h.z = __builtin_amdgcn_perm(d[5], d[4], 0x05040100u);
+                h.w = __builtin_amdgcn_perm(d[7], d[6], 0x05040100u);
+                l.x = __builtin_amdgcn_perm(d[1], d[0], 0x07060302u);
+                l.y = __builtin_amdgcn_perm(d[3], d[2], 0x07060302u);
+                l.z = __builtin_amdgcn_perm(d[5], d[4], 0x07060302u);
+                l.w = __builtin_amdgcn_perm(d[7], d[6], 0x07060302u);
+                const v8bf ahi = __builtin_bit_cast(v8bf, h), alo = __builtin_bit_cast(v8bf, l);
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = mma_bf16x3(ahi, alo, bhi[nt], blo[nt], acc[rt][nt]);
+            }
+        } else {
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks) {
+                const int col = cb + 4 * ks + lk;
+                const bool cin = full || col < m;
+                const float* ucol = U + (w + (cin ? col : 0)) * kBlkLDR;
+                float bv[NT];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const uint4& u = ks < 4 ? f[nt].x : f[nt].y;
+                    const unsigned e = (ks & 3) == 0 ? u.x : (ks & 3) == 1 ? u.y : (ks & 3) == 2 ? u.z : u.w;
+                    bv[nt] = __builtin_bit_cast(float, e);
+                }
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt) {
+                    const float av = cin ? ucol[16 * rt + li] : 0.0f;
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+                        acc[rt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[nt], acc[rt][nt], 0, 0, 0);
+                }
+            }
+        }
+    };
+
+    Frag f0[PF >= 1 ? NT : 1], f1[PF == 2 ? NT : 1];
+    if (wave < k) {
+        if constexpr (PF >= 1) load_frag(wave, 0, f0);
+        if constexpr (PF == 2)
+            if (nq > 1) load_frag(wave, 1, f1);
+    }
     for (int w = wave; w < k; w += kThreads / 64) {
         const int set = a.kmax - k + w;
         const DevState* st =
             w == k - 1 ? stf : reinterpret_cast<const DevState*>(a.shadow + (size_t)set * a.shadow_stride);
-        if (st->solve_status != ST_OK && st->solve_status != ST_W_RANK) continue;
-        const int kc = 2 * st->r_eff;
-        if (kc == 0) continue;
-        const float* B = w == k - 1 ? a.Bphi : a.Bphi_sets + (int64_t)set * a.bphi_stride;
+        const int kc = (st->solve_status == ST_OK || st->solve_status == ST_W_RANK) ? 2 * st->r_eff : 0;
         v4f acc[4][NT];
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = v4f{0, 0, 0, 0};
-        // coefficients of 8 k-steps (32 window columns) are loaded together
-        // before their MFMAs, so the L2 latency is paid once per chunk
-        for (int cb = 0; cb < m; cb += 32) {
-            if constexpr (BF3) {
-                v8bf bhi[NT], blo[NT];
+        if (kc > 0) {
+            if constexpr (PF >= 1) chunk(w, 0, f0, acc);
+            if constexpr (PF == 2)
+                if (nq > 1) chunk(w, 32, f1, acc);
+            for (int q = PF; q < nq; ++q) {
+                Frag g[NT];
+                load_frag(w, q, g);
+                chunk(w, 32 * q, g, acc);
+            }
+        }
+        if (w + kThreads / 64 < k) {
+            if constexpr (PF >= 1) load_frag(w + kThreads / 64, 0, f0);
+            if constexpr (PF == 2)
+                if (nq > 1) load_frag(w + kThreads / 64, 1, f1);
+        }
+        if (kc == 0) continue;  // unsolved window: its output is left untouched
+        // Output straight from the accumulators: lane (li, lq) of tile (rt, nt)
+        // holds rows 16 rt + 4 lq + v (v = 0..3) of real column 16 nt + li,
+        // i.e. the real (li even) or imaginary (li odd) part of complex column
+        // 8 nt + li/2.  One swap with the neighbouring lane gives the even lane
+        // rows v = 0, 1 and the odd lane rows v = 2, 3 as whole complex values:
+        // two consecutive rows, one 16-byte store.
+        float2* out = a.out + (int64_t)w * a.ldw;
+        const bool odd = li & 1;
+        const int r_eff = kc >> 1;
+        // 16-byte stores where the layout allows and all 64 rows exist (uniform)
+        auto store = [&](auto fast) {
 #pragma unroll
-                for (int ks = 0; ks < 8; ++ks) {
-                    const int col = cb + 4 * ks + lk;
-#pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) {
-                        const int c = 16 * nt + li;
-                        __bf16 h, l;
-                        split_bf16((col < m && c < kc) ? B[(int64_t)col * rs + c] : 0.0f, h, l);
-                        bhi[nt][ks] = h;
-                        blo[nt][ks] = l;
-                    }
-                }
+            for (int nt = 0; nt < NT; ++nt) {
+                const int j = 8 * nt + (li >> 1);
 #pragma unroll
                 for (int rt = 0; rt < 4; ++rt) {
-                    v8bf ahi, alo;
-#pragma unroll
-                    for (int ks = 0; ks < 8; ++ks) {
-                        const int col = cb + 4 * ks + lk;
-                        const bool cin = col < m;
-                        const float av = cin ? U[(w + col) * kBlkLDR + 16 * rt + li] : 0.0f;
-                        __bf16 h, l;
-                        split_bf16(av, h, l);
-                        ahi[ks] = h;
-                        alo[ks] = l;
-                    }
-#pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = mma_bf16x3(ahi, alo, bhi[nt], blo[nt], acc[rt][nt]);
-                }
-            } else {
-                float bv[8][NT];
-#pragma unroll
-                for (int ks = 0; ks < 8; ++ks) {
-                    const int col = cb + 4 * ks + lk;
-#pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) {
-                        const int c = 16 * nt + li;
-                        bv[ks][nt] = (col < m && c < kc) ? B[(int64_t)col * rs + c] : 0.0f;
-                    }
-                }
-#pragma unroll
-                for (int ks = 0; ks < 8; ++ks) {
-                    const int col = cb + 4 * ks + lk;
-                    const bool cin = col < m;
-                    const float* ucol = U + (w + (cin ? col : 0)) * kBlkLDR;
-#pragma unroll
-                    for (int rt = 0; rt < 4; ++rt) {
-                        const float av = cin ? ucol[16 * rt + li] : 0.0f;
-#pragma unroll
-                        for (int nt = 0; nt < NT; ++nt)
-                            acc[rt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[ks][nt], acc[rt][nt], 0, 0, 0);
+                    const v4f d = acc[rt][nt];
+                    const float x = odd ? d[0] : d[2], y = odd ? d[1] : d[3];
+                    const float xs = swap_pair(x), ys = swap_pair(y);
+                    const float4 val = odd ? float4{xs, d[2], ys, d[3]} : float4{d[0], xs, d[1], ys};
+                    const int64_t row = row0 + 16 * rt + 4 * lk + (odd ? 2 : 0);
+                    float2* o = out + row + (int64_t)j * a.ldo;
+                    if constexpr (decltype(fast)::value) {
+                        if (j < r_eff) *reinterpret_cast<float4*>(o) = val;
+                    } else if (j < r_eff && row < a.n) {
+                        o[0] = float2{val.x, val.y};
+                        if (row + 1 < a.n) o[1] = float2{val.z, val.w};
                     }
                 }
             }
-        }
-        float2* out = a.out + (int64_t)w * a.ldw;
-        const int64_t row = row0 + lane;
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            if (16 * nt >= kc) break;
-#pragma unroll
-            for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) sw[(16 * rt + 4 * lk + v) * kBlkOLD + li] = acc[rt][nt][v];
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (row < a.n) {
-#pragma unroll
-                for (int cc = 0; cc < 16; cc += 2) {
-                    const int c = 16 * nt + cc;
-                    if (c < kc)
-                        out[row + (int64_t)(c >> 1) * a.ldo] = float2{sw[lane * kBlkOLD + cc], sw[lane * kBlkOLD + cc + 1]};
-                }
-            }
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        }
+        };
+        if (a.out16 && row0 + kBlkRows <= a.n) store(std::true_type{});
+        else store(std::false_type{});
     }
 }
 
-size_t block_lds(int m, int k) {
-    return sizeof(float) * ((size_t)(m + k - 1) * kBlkLDR + (kThreads / 64) * 64 * kBlkOLD);
+// Coefficients of the k windows of a block push in the B-fragment order of
+// k_project_block: entry ((w nq + q) NT + nt) 64 + lane holds the 8 values
+// C[32 q + 4 e + lane/16][16 nt + lane%16], e = 0..7, of window w (zero
+// outside m x 2 r_eff and for unsolved windows), as 8 floats, or for BF3 as
+// their 8 BF16 hi parts followed by their 8 BF16 lo parts.
+template <int NT, bool BF3>
+__global__ __launch_bounds__(64)
+void k_pack_coef(BlockProjectArgs a) {
+    const int lane = threadIdx.x;
+    const int nt = blockIdx.x % NT, q = blockIdx.x / NT, w = blockIdx.y;
+    const int nq = (a.m + 31) / 32;
+    const int k = a.k;
+    const int set = a.kmax - k + w;
+    const DevState* st =
+        w == k - 1 ? a.st : reinterpret_cast<const DevState*>(a.shadow + (size_t)set * a.shadow_stride);
+    const int kc = (st->solve_status == ST_OK || st->solve_status == ST_W_RANK) ? 2 * st->r_eff : 0;
+    const float* B = w == k - 1 ? a.Bphi : a.Bphi_sets + (int64_t)set * a.bphi_stride;
+    const int li = lane & 15, lk = lane >> 4;
+    const int c = 16 * nt + li;
+    float y[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int col = 32 * q + 4 * e + lk;
+        y[e] = (col < a.m && c < kc) ? B[(int64_t)col * (2 * a.r) + c] : 0.0f;
+    }
+    uint4* out = a.cfrag + ((size_t)(w * nq + q) * NT * 64 + nt * 64 + lane) * 2;
+    if constexpr (BF3) {
+        v8bf hi, lo;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            __bf16 h, l;
+            split_bf16(y[e], h, l);
+            hi[e] = h;
+            lo[e] = l;
+        }
+        out[0] = __builtin_bit_cast(uint4, hi);
+        out[1] = __builtin_bit_cast(uint4, lo);
+    } else {
+        out[0] = uint4{__builtin_bit_cast(unsigned, y[0]), __builtin_bit_cast(unsigned, y[1]),
+                       __builtin_bit_cast(unsigned, y[2]), __builtin_bit_cast(unsigned, y[3])};
+        out[1] = uint4{__builtin_bit_cast(unsigned, y[4]), __builtin_bit_cast(unsigned, y[5]),
+                       __builtin_bit_cast(unsigned, y[6]), __builtin_bit_cast(unsigned, y[7])};
+    }
 }
+
+size_t block_lds(int m, int k) { return sizeof(float) * (size_t)(m + k - 1) * kBlkLDR; }
 
 template <int NT>
 hipError_t launch_block_nt(const BlockProjectArgs& a, hipStream_t s) {
     const size_t lds = block_lds(a.m, a.k);
     if (lds > kBlockLdsMax) return hipErrorInvalidValue;
+    if (!a.cfrag) return hipErrorInvalidValue;
+    const dim3 pgrid((unsigned)(((a.m + 31) / 32) * NT), (unsigned)a.k);
+    if (a.bf16x3) hipLaunchKernelGGL((k_pack_coef<NT, true>), pgrid, dim3(64), 0, s, a);
+    else hipLaunchKernelGGL((k_pack_coef<NT, false>), pgrid, dim3(64), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     auto kern = a.bf16x3 ? k_project_block<NT, true> : k_project_block<NT, false>;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const unsigned gx = (unsigned)((a.n + kBlkRows - 1) / kBlkRows);
@@ -487,6 +601,8 @@ hipError_t launch_block_nt(const BlockProjectArgs& a, hipStream_t s) {
 }
 
 }  // namespace
+
+size_t project_block_frag_bytes(int m, int kmax) { return (size_t)kmax * ((m + 31) / 32) * 4 * 64 * 32; }
 
 bool project_block_fits(int m, int k, int r) { return 2 * r <= 64 && k <= 64 && block_lds(m, k) <= kBlockLdsMax; }
 
