@@ -366,14 +366,19 @@ def bench_block(args):
 
     s = dmd.Stream(n, M, R, dtype="f32", max_block=kb, precision=args.precision)
     phis = torch.zeros((kb, R, n), dtype=torch.complex64, device="cuda")
+    # pushes (Gram update + solves) on one stream, projections on another: the
+    # projection of block b overlaps the Gram update and solves of block b + 1
+    sp, sm = torch.cuda.Stream(), torch.cuda.Stream()
+    sp.wait_stream(torch.cuda.current_stream())
+    sm.wait_stream(torch.cuda.current_stream())
     t = 0
     while t < fill:                      # the window fills with block pushes as well
         k = min(kb, fill - t)
-        s.push_block(frames[t:t + k])
+        s.push_block(frames[t:t + k], stream=sp)
         t += k
     for _ in range(Wu):
-        s.push_block(frames[t:t + kb])
-        s.block_modes(phis)
+        s.push_block(frames[t:t + kb], stream=sp)
+        s.block_modes(phis, stream=sm)
         t += kb
     torch.cuda.synchronize()
 
@@ -382,13 +387,13 @@ def bench_block(args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(K):
-        s.push_block(frames[t:t + kb])
-        s.block_modes(phis)
+        s.push_block(frames[t:t + kb], stream=sp)
+        s.block_modes(phis, stream=sm)
         t += kb
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     dmd.profile_enable(False)
-    kernels = kernel_table(dmd, ("gram_block", "block_solve", "project_block"))
+    kernels = kernel_table(dmd, ("gram_block", "block_solve", "pack_block", "project_block"))
     dmd.profile_reset()
     print(f"[bench] timed {K} blocks of {kb} frames in {elapsed:.3f} s", file=sys.stderr, flush=True)
     wins, _ = s.block_eigs()

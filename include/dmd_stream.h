@@ -122,8 +122,9 @@ typedef struct {
                             (consecutive solves then depend on each other); 0
                             (default): start from the identity                      */
     int32_t max_block;   /* largest k of dmd_stream_push_block, 1 .. 64 (0 = 1);
-                            dense streams only.  The ring keeps max_block spare
-                            slots and max_block - 1 extra solve workspaces       */
+                            dense streams only.  For max_block > 1 the ring keeps
+                            2 max_block spare slots, and there are max_block - 1
+                            extra solve workspaces                               */
     int32_t eig_solver;  /* dmd_eig_solver_t for the symmetric eig of X^* X       */
     int32_t reserved[5]; /* must be zero                                             */
 } dmd_opts_t;
@@ -139,8 +140,9 @@ int dmd_opts_init(dmd_opts_t* opts);
  * window holds m+1 snapshots) and truncation rank r on the current HIP device.
  * Requires n >= 1, 2 <= m <= 256, 1 <= r <= min(m, 32); for DMD_C64_CSR also
  * 1 <= max_nnz <= n.  opts may be NULL (defaults).  Allocates the ring of
- * snapshots (m+1+B slots of n elements, B = opts->max_block: the window plus
- * the slots being filled), the FP64 Gram over those slots and the solve
+ * snapshots (m+2 slots of n elements, or m+1+2B slots for block streams,
+ * B = opts->max_block: the window, the slots being filled and the columns of
+ * the previous block's windows), the FP64 Gram over those slots and the solve
  * workspaces, all zeroed.
  * Errors: DMD_E_INVAL, DMD_E_NOMEM, DMD_E_DEVICE.  *out is NULL on error. */
 int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t* opts,
@@ -193,7 +195,12 @@ int dmd_stream_push_csr(dmd_stream_t* h, int32_t nnz, const int32_t* idx,
  * dmd_stream_block_eigs returns every window's eigenvalues.
  * Unlike k single pushes, a non-finite inner product anywhere in the block
  * rejects the whole block (window, Gram and results unchanged; DMD_E_NONFINITE
- * at the next synchronising call).  Asynchronous.
+ * at the next synchronising call).  With FP32 data and coefficients the
+ * inputs of dmd_stream_block_modes (coefficients in the projection kernel's
+ * fragment order, ring position, ranks) are packed right after the solves, in
+ * one of two buffers used in turn.  Ordered after all earlier calls on the
+ * handle except the dmd_stream_block_modes of the previous block push, which
+ * reads nothing this push writes.  Asynchronous.
  * Errors: DMD_E_INVAL (NULL, k out of range, ldx < n, misaligned),
  * DMD_E_UNSUPPORTED (sparse stream), DMD_E_DEVICE. */
 int dmd_stream_push_block(dmd_stream_t* h, const void* X_new, int64_t ldx,
@@ -219,7 +226,11 @@ int dmd_stream_block_eigs(dmd_stream_t* h, int32_t* k, double* lam_re, double* l
  * DMD_F64 streams and DMD_PREC_FP64) into the device buffer phi, ld >= n,
  * ldw >= ld * r.  Windows that were not full, not solved, or belong to a
  * rejected block are left untouched.  For FP32 data and coefficients one pass
- * over the ring serves all k windows.  Stream-ordered; does not wait.
+ * over the ring serves all k windows, reading only the ring columns of the
+ * block's windows and the inputs packed by the push, so that on another
+ * stream than the pushes it runs beside the next block push (whose Gram
+ * update and solves then overlap it); the block push after that, and every
+ * other later call, is ordered after it.  Stream-ordered; does not wait.
  * DMD_E_NOT_READY if the latest push was not a block push with auto_solve on. */
 int dmd_stream_block_modes(dmd_stream_t* h, void* phi, int64_t ld, int64_t ldw, void* stream);
 
@@ -374,8 +385,8 @@ int dmd_batch_info(dmd_batch_t* b, int32_t* nstreams, int64_t* used_bytes,
  * recorded on its launch stream.  Kernel names: "gram_columns", "gram_finalize", "solve_sym",
  * "solve_eig", "project_modes", "project_pod", "background", "csr_gram",
  * "csr_project", "gram_full", for block pushes "gram_block" (block Gram pass, reduction and
- * commit), "block_solve" (all windows' solves) and "project_block" (all
- * windows' modes), and for batch ticks
+ * commit), "block_solve" (all windows' solves), "pack_block" (packing the
+ * projection inputs) and "project_block" (all windows' modes), and for batch ticks
  * "batch_gram", "batch_solve", "batch_project".
  * dmd_profile_read waits for the recorded events and returns the number of
  * launches of `kernel` and their summed duration in milliseconds since the

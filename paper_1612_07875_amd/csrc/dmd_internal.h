@@ -207,6 +207,17 @@ int project_item_blocks(int64_t n);
 // state and coefficients in set kmax-k+w of the intermediate-window sets;
 // window k-1 uses the stream's own.  Phi of window w goes to out + w * ldw
 // complex elements (column j at + j * ldo); windows without a solve are skipped.
+//
+// The block's inputs are packed right after its solves (launch_pack_block):
+// the coefficients in fragment order (cfrag) and a BlockDesc with the ring
+// position and the windows' ranks, so that the projection reads nothing that
+// the next block push modifies (the ring keeps 2 max_block spare slots).
+struct BlockDesc {
+    int valid;        // the window is full and the block was accepted
+    int base;         // ring slot of the union's first column (before the wrap)
+    int pad[2];
+    int kc[64];       // 2 r_eff of window w, 0 if it has no solve
+};
 struct BlockProjectArgs {
     const void* ring;
     int64_t ld, n;
@@ -221,9 +232,12 @@ struct BlockProjectArgs {
     int64_t ldo, ldw;
     int bf16x3;                    // products as three BF16 MFMAs (DMD_PREC_BF16X3), else FP32
     int out16;                     // out, ldo and ldw allow 16-byte stores of two rows
-    uint4* cfrag;                  // project_block_frag_bytes(m, kmax) of scratch for the
-                                   // packed coefficients
+    uint4* cfrag;                  // project_block_frag_bytes(m, kmax): packed coefficients
+    BlockDesc* desc;               // packed ring position and ranks
 };
+// Pack (after the block's solves; reads st, shadow, Bphi, Bphi_sets) and
+// project (reads ring, cfrag and desc only).
+hipError_t launch_pack_block(const BlockProjectArgs& a, hipStream_t s);
 hipError_t launch_project_block(const BlockProjectArgs& a, hipStream_t s);
 // Whether the one-pass block projection's LDS tiles fit for these sizes.
 bool project_block_fits(int m, int k, int r);

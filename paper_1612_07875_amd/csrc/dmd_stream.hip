@@ -144,7 +144,19 @@ struct dmd_stream {
     double* sh_Vfull = nullptr;
     void* sh_Bphi = nullptr;
     void* sh_Bpod = nullptr;
-    uint4* cfrag = nullptr;       // block pushes: packed coefficients of the k windows
+    // Block pushes: the projection inputs of the latest two blocks, packed
+    // after their solves (parity = block number & 1), and the events of the
+    // projections that read them.  A block push waits only for the
+    // projection of the block two back (same parity), so that the projection
+    // of block b can run beside the Gram update and solves of block b + 1.
+    uint4* cfrag = nullptr;       // 2 x cfrag_elems packed coefficients
+    size_t cfrag_elems = 0;
+    dmd::BlockDesc* bdesc = nullptr;  // 2 descriptors
+    hipEvent_t ev_proj[2] = {nullptr, nullptr};
+    hipStream_t proj_stream[2] = {nullptr, nullptr};
+    bool proj_pending[2] = {false, false};
+    int64_t block_seq = 0;        // block pushes so far
+    int last_packed = -1;         // parity packed by the latest push, -1 if none
     dmd::SolveArgs* solve_tbl = nullptr;  // device: sets 0 .. kmax-2, then the current window
     int32_t last_block_k = 0;     // k of the latest push if it was a solved block push, else 0
 
@@ -165,7 +177,26 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 // Order the handle's work across streams: a call on a new stream first waits
 // for everything enqueued before it.
 hipError_t begin(dmd_stream* h, hipStream_t s) {
-    if (h->has_last && h->last_stream != s) return hipStreamWaitEvent(s, h->ev_last, 0);
+    if (h->has_last && h->last_stream != s) {
+        hipError_t e = hipStreamWaitEvent(s, h->ev_last, 0);
+        if (e != hipSuccess) return e;
+    }
+    for (int p = 0; p < 2; ++p)
+        if (h->proj_pending[p] && h->proj_stream[p] != s) {
+            hipError_t e = hipStreamWaitEvent(s, h->ev_proj[p], 0);
+            if (e != hipSuccess) return e;
+        }
+    return hipSuccess;
+}
+// A block push of parity p: after everything but the projection of the
+// previous block (parity 1 - p), which reads neither the slots this push
+// writes nor its packed inputs.
+hipError_t begin_block(dmd_stream* h, hipStream_t s, int p) {
+    if (h->has_last && h->last_stream != s) {
+        hipError_t e = hipStreamWaitEvent(s, h->ev_last, 0);
+        if (e != hipSuccess) return e;
+    }
+    if (h->proj_pending[p] && h->proj_stream[p] != s) return hipStreamWaitEvent(s, h->ev_proj[p], 0);
     return hipSuccess;
 }
 hipError_t end(dmd_stream* h, hipStream_t s) {
@@ -191,12 +222,14 @@ void free_all(dmd_stream* h) {
     void* bufs[] = {h->ring, h->ring_idx, h->ring_val, h->ring_nnz, h->scatter, h->flag, h->G, h->partials,
                     h->res_dev, h->V, h->At, h->W, h->work, h->Vfull, h->gfull, h->Bphi, h->Bpod,
                     h->Bbg, h->bpartial, h->gblock, h->bflag, h->sh_dev, h->sh_V, h->sh_At, h->sh_W, h->sh_work,
-                    h->sh_Vfull, h->sh_Bphi, h->sh_Bpod, h->cfrag, h->solve_tbl};
+                    h->sh_Vfull, h->sh_Bphi, h->sh_Bpod, h->cfrag, h->bdesc, h->solve_tbl};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (h->res_host) (void)hipHostFree(h->res_host);
     if (h->sh_host) (void)hipHostFree(h->sh_host);
     if (h->ev_last) (void)hipEventDestroy(h->ev_last);
+    for (hipEvent_t e : h->ev_proj)
+        if (e) (void)hipEventDestroy(e);
     if (h->ev_solved) (void)hipEventDestroy(h->ev_solved);
 }
 
@@ -296,6 +329,7 @@ void fill_project_args(const dmd_stream* h, dmd::ProjectArgs& a, void* out, int6
 
 int enqueue_solve(dmd_stream* h, hipStream_t s) {
     h->last_block_k = 0;
+    h->last_packed = -1;
     dmd::SolveArgs a;
     fill_solve_args(h, a);
     HIP_TRY(timed("solve_sym", s, [&] {
@@ -407,7 +441,9 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
     h->m = m;
     h->r = r;
     h->kmax = o.max_block;
-    h->slots = m + 1 + h->kmax;
+    // a block stream keeps 2 max_block spare slots: the columns of the
+    // previous block's windows survive the next block push
+    h->slots = m + 1 + (h->kmax > 1 ? 2 * h->kmax : 1);
     h->opts = o;
     h->cplx = (o.dtype == DMD_C64_CSR);
     h->elem_bytes = (o.dtype == DMD_F64) ? 8 : 4;
@@ -466,7 +502,9 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
         ALLOC(h->sh_Vfull, sizeof(double) * ns * z.Vfull);
         ALLOC(h->sh_Bphi, ns * z.Bphi);
         ALLOC(h->sh_Bpod, ns * z.Bpod);
-        ALLOC(h->cfrag, dmd::project_block_frag_bytes(m, h->kmax));
+        h->cfrag_elems = dmd::project_block_frag_bytes(m, h->kmax) / sizeof(uint4);
+        ALLOC(h->cfrag, 2 * h->cfrag_elems * sizeof(uint4));
+        ALLOC(h->bdesc, 2 * sizeof(dmd::BlockDesc));
         if (rc == DMD_OK) {
             hipError_t e = hipHostMalloc((void**)&h->sh_host, ns * h->sh_stride,
                                          hipHostMallocMapped | hipHostMallocCoherent);
@@ -506,6 +544,7 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
     if (rc == DMD_OK) {
         hipError_t e = hipEventCreateWithFlags(&h->ev_last, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_solved, hipEventDisableTiming);
+        for (int p = 0; p < 2 && e == hipSuccess; ++p) e = hipEventCreateWithFlags(&h->ev_proj[p], hipEventDisableTiming);
         if (e == hipSuccess) e = hipDeviceSynchronize();
         if (e != hipSuccess) rc = hip_fail(e, "event/sync");
     }
@@ -525,6 +564,8 @@ DMD_API int dmd_stream_destroy(dmd_stream_t* h) {
     if (!h) return DMD_OK;
     DeviceGuard g(h->device);
     if (h->has_last) (void)hipEventSynchronize(h->ev_last);
+    for (int p = 0; p < 2; ++p)
+        if (h->proj_pending[p]) (void)hipEventSynchronize(h->ev_proj[p]);
     free_all(h);
     delete h;
     return DMD_OK;
@@ -565,6 +606,7 @@ DMD_API int dmd_stream_reset(dmd_stream_t* h, void* stream) {
     HIP_TRY(hipGetLastError());
     h->solve_enqueued = false;
     h->last_block_k = 0;
+    h->last_packed = -1;
     HIP_TRY(end(h, s));
     return DMD_OK;
 }
@@ -592,6 +634,7 @@ DMD_API int dmd_stream_push(dmd_stream_t* h, const void* x, void* stream) {
                   [&] { return dmd::launch_gram_finalize(h->G, h->partials, nblk, h->m, h->slots, st, s); });
     if (e != hipSuccess) return hip_fail(e, "gram push launch");
     h->last_block_k = 0;
+    h->last_packed = -1;
     if (h->opts.auto_solve)
         if (int rc = enqueue_solve(h, s)) return rc;
     HIP_TRY(end(h, s));
@@ -615,11 +658,36 @@ DMD_API int dmd_stream_push_csr(dmd_stream_t* h, int32_t nnz, const int32_t* idx
     });
     if (e != hipSuccess) return hip_fail(e, "sparse push launch");
     h->last_block_k = 0;
+    h->last_packed = -1;
     if (h->opts.auto_solve)
         if (int rc = enqueue_solve(h, s)) return rc;
     HIP_TRY(end(h, s));
     return DMD_OK;
 }
+
+namespace {
+// Block projection arguments of a k-column push packed into parity par.
+void fill_block_project_args(dmd_stream* h, dmd::BlockProjectArgs& a, int k, int par) {
+    a = dmd::BlockProjectArgs{};
+    a.ring = h->ring;
+    a.ld = h->ld;
+    a.n = h->n;
+    a.m = h->m;
+    a.r = h->r;
+    a.slots = h->slots;
+    a.k = k;
+    a.kmax = h->kmax;
+    a.st = reinterpret_cast<const DevState*>(h->res_dev);
+    a.shadow = h->sh_dev;
+    a.shadow_stride = (int)h->sh_stride;
+    a.Bphi = static_cast<const float*>(h->Bphi);
+    a.Bphi_sets = static_cast<const float*>(h->sh_Bphi);
+    a.bphi_stride = (int64_t)set_sizes(h).Bphi / sizeof(float);
+    a.bf16x3 = h->opts.precision == DMD_PREC_BF16X3;
+    a.cfrag = h->cfrag + (size_t)par * h->cfrag_elems;
+    a.desc = h->bdesc + par;
+}
+}  // namespace
 
 DMD_API int dmd_stream_push_block(dmd_stream_t* h, const void* X_new, int64_t ldx, int32_t k,
                                   void* stream) {
@@ -631,7 +699,8 @@ DMD_API int dmd_stream_push_block(dmd_stream_t* h, const void* X_new, int64_t ld
     if ((uintptr_t)X_new % h->elem_bytes) return fail(DMD_E_INVAL, "X_new not %d-byte aligned", h->elem_bytes);
     DeviceGuard g(h->device);
     hipStream_t s = as_stream(stream);
-    HIP_TRY(begin(h, s));
+    const int par = (int)(h->block_seq & 1);
+    HIP_TRY(begin_block(h, s, par));
     dmd::BlockArgs a{};
     a.ring = h->ring;
     a.ld = h->ld;
@@ -652,6 +721,7 @@ DMD_API int dmd_stream_push_block(dmd_stream_t* h, const void* X_new, int64_t ld
     a.kmax = h->kmax;
     HIP_TRY(timed("gram_block", s, [&] { return dmd::launch_gram_block(a, h->elem_bytes == 8, s); }));
     h->last_block_k = 0;
+    h->last_packed = -1;
     if (h->opts.auto_solve) {
         const dmd::SolveArgs* t = h->solve_tbl + (h->kmax - k);
         const bool lds = h->m + (h->m & 1) <= 64;
@@ -663,7 +733,14 @@ DMD_API int dmd_stream_push_block(dmd_stream_t* h, const void* X_new, int64_t ld
         HIP_TRY(hipEventRecord(h->ev_solved, s));
         h->solve_enqueued = true;
         h->last_block_k = k;
+        if (h->elem_bytes == 4 && !h->coef_f64 && dmd::project_block_fits(h->m, k, h->r)) {
+            dmd::BlockProjectArgs pa;
+            fill_block_project_args(h, pa, k, par);
+            HIP_TRY(timed("pack_block", s, [&] { return dmd::launch_pack_block(pa, s); }));
+            h->last_packed = par;
+        }
     }
+    ++h->block_seq;
     HIP_TRY(end(h, s));
     return DMD_OK;
 }
@@ -707,33 +784,29 @@ DMD_API int dmd_stream_block_modes(dmd_stream_t* h, void* phi, int64_t ld, int64
     if (h->last_block_k == 0) return fail(DMD_E_NOT_READY, "the latest push was not a solved block push");
     DeviceGuard g(h->device);
     hipStream_t s = as_stream(stream);
-    HIP_TRY(begin(h, s));
     const int k = h->last_block_k;
     const size_t celem = h->coef_f64 ? 16 : 8;  // complex128 or complex64
-    if (h->elem_bytes == 4 && !h->coef_f64 && dmd::project_block_fits(h->m, k, h->r)) {
-        dmd::BlockProjectArgs a{};
-        a.ring = h->ring;
-        a.ld = h->ld;
-        a.n = h->n;
-        a.m = h->m;
-        a.r = h->r;
-        a.slots = h->slots;
-        a.k = k;
-        a.kmax = h->kmax;
-        a.st = reinterpret_cast<const DevState*>(h->res_dev);
-        a.shadow = h->sh_dev;
-        a.shadow_stride = (int)h->sh_stride;
-        a.Bphi = static_cast<const float*>(h->Bphi);
-        a.Bphi_sets = static_cast<const float*>(h->sh_Bphi);
-        a.bphi_stride = (int64_t)set_sizes(h).Bphi / sizeof(float);
+    if (h->last_packed >= 0) {
+        // reads only the ring columns of the block's windows and the inputs
+        // packed after its solves: ordered after the push, not after later
+        // calls' other work; later calls that touch those inputs wait for it
+        const int par = h->last_packed;
+        if (h->has_last && h->last_stream != s) HIP_TRY(hipStreamWaitEvent(s, h->ev_last, 0));
+        if (h->proj_pending[par] && h->proj_stream[par] != s) HIP_TRY(hipStreamWaitEvent(s, h->ev_proj[par], 0));
+        dmd::BlockProjectArgs a;
+        fill_block_project_args(h, a, k, par);
         a.out = static_cast<float2*>(phi);
         a.ldo = ld;
         a.ldw = ldw;
-        a.bf16x3 = h->opts.precision == DMD_PREC_BF16X3;
-        a.cfrag = h->cfrag;
         a.out16 = (reinterpret_cast<uintptr_t>(phi) % 16 == 0) && ld % 2 == 0 && ldw % 2 == 0;
         HIP_TRY(timed("project_block", s, [&] { return dmd::launch_project_block(a, s); }));
-    } else {
+        HIP_TRY(hipEventRecord(h->ev_proj[par], s));
+        h->proj_stream[par] = s;
+        h->proj_pending[par] = true;
+        return DMD_OK;
+    }
+    HIP_TRY(begin(h, s));
+    {
         // FP64 data or coefficients, or tiles beyond the LDS: one projection per window from its own state
         for (int w = 0; w < k; ++w) {
             dmd::ProjectArgs a;
@@ -928,6 +1001,7 @@ DMD_API int dmd_stream_load_window(dmd_stream_t* h, const void* X, int64_t ldx, 
     HIP_TRY(begin(h, s));
     DevState* st = reinterpret_cast<DevState*>(h->res_dev);
     h->last_block_k = 0;
+    h->last_packed = -1;
     HIP_TRY(dmd::launch_copy_columns(X, ldx, h->ring, h->ld, h->n, ncols, h->elem_bytes == 8, s));
     HIP_TRY(timed("gram_full", s, [&] {
         return dmd::launch_gram_full(h->ring, h->ld, h->n, h->m, h->slots, h->elem_bytes == 8, h->opts.precision,
@@ -947,6 +1021,7 @@ DMD_API int dmd_stream_resync(dmd_stream_t* h, void* stream) {
     HIP_TRY(begin(h, s));
     DevState* st = reinterpret_cast<DevState*>(h->res_dev);
     h->last_block_k = 0;
+    h->last_packed = -1;
     HIP_TRY(timed("gram_full", s, [&] {
         return dmd::launch_gram_full(h->ring, h->ld, h->n, h->m, h->slots, h->elem_bytes == 8, h->opts.precision,
                                      h->m + 1, -1, h->gfull, h->G, st, 2, s);
@@ -1268,6 +1343,7 @@ DMD_API int dmd_batch_tick(dmd_batch_t* b, int32_t count, dmd_stream_t* const* s
         HIP_TRY(hipEventRecord(h->ev_solved, s));
         h->solve_enqueued = true;
         h->last_block_k = 0;
+        h->last_packed = -1;
         HIP_TRY(end(h, s));
     }
     b->last_stream = s;

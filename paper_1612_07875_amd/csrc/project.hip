@@ -369,13 +369,13 @@ template <int NT, bool BF3>
 __global__ __launch_bounds__(kThreads, (BF3 && NT >= 3) ? 2 : 3)
 void k_project_block(BlockProjectArgs a) {
     extern __shared__ float dynp[];
-    const DevState* stf = a.st;
-    if (stf->count < a.m + 1 || stf->block_rejected) return;
+    const BlockDesc* desc = a.desc;
+    if (!desc->valid) return;
     const int m = a.m, k = a.k;
     const int ncols = m + k - 1;
     float* U = dynp;
     const int64_t row0 = (int64_t)blockIdx.x * kBlkRows;
-    const int base = stf->oldest + 2 - k + a.slots;  // slot of staged column 0, before the wrap
+    const int base = desc->base;  // slot of staged column 0, before the wrap
     const float* ring = static_cast<const float*>(a.ring);
     for (int t = threadIdx.x; t < ncols * (kBlkRows / 4); t += kThreads) {
         const int c = t / (kBlkRows / 4), q = t % (kBlkRows / 4);
@@ -473,10 +473,7 @@ void k_project_block(BlockProjectArgs a) {
             if (nq > 1) load_frag(wave, 1, f1);
     }
     for (int w = wave; w < k; w += kThreads / 64) {
-        const int set = a.kmax - k + w;
-        const DevState* st =
-            w == k - 1 ? stf : reinterpret_cast<const DevState*>(a.shadow + (size_t)set * a.shadow_stride);
-        const int kc = (st->solve_status == ST_OK || st->solve_status == ST_W_RANK) ? 2 * st->r_eff : 0;
+        const int kc = desc->kc[w];
         v4f acc[4][NT];
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt)
@@ -553,6 +550,13 @@ void k_pack_coef(BlockProjectArgs a) {
     const float* B = w == k - 1 ? a.Bphi : a.Bphi_sets + (int64_t)set * a.bphi_stride;
     const int li = lane & 15, lk = lane >> 4;
     const int c = 16 * nt + li;
+    if (blockIdx.x == 0 && lane == 0) {
+        a.desc->kc[w] = kc;
+        if (w == k - 1) {
+            a.desc->valid = a.st->count >= a.m + 1 && !a.st->block_rejected;
+            a.desc->base = a.st->oldest + 2 - k + a.slots;
+        }
+    }
     float y[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -585,14 +589,9 @@ template <int NT>
 hipError_t launch_block_nt(const BlockProjectArgs& a, hipStream_t s) {
     const size_t lds = block_lds(a.m, a.k);
     if (lds > kBlockLdsMax) return hipErrorInvalidValue;
-    if (!a.cfrag) return hipErrorInvalidValue;
-    const dim3 pgrid((unsigned)(((a.m + 31) / 32) * NT), (unsigned)a.k);
-    if (a.bf16x3) hipLaunchKernelGGL((k_pack_coef<NT, true>), pgrid, dim3(64), 0, s, a);
-    else hipLaunchKernelGGL((k_pack_coef<NT, false>), pgrid, dim3(64), 0, s, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (!a.cfrag || !a.desc) return hipErrorInvalidValue;
     auto kern = a.bf16x3 ? k_project_block<NT, true> : k_project_block<NT, false>;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const unsigned gx = (unsigned)((a.n + kBlkRows - 1) / kBlkRows);
@@ -605,6 +604,24 @@ hipError_t launch_block_nt(const BlockProjectArgs& a, hipStream_t s) {
 size_t project_block_frag_bytes(int m, int kmax) { return (size_t)kmax * ((m + 31) / 32) * 4 * 64 * 32; }
 
 bool project_block_fits(int m, int k, int r) { return 2 * r <= 64 && k <= 64 && block_lds(m, k) <= kBlockLdsMax; }
+
+template <int NT>
+hipError_t launch_pack_nt(const BlockProjectArgs& a, hipStream_t s) {
+    if (!a.cfrag || !a.desc) return hipErrorInvalidValue;
+    const dim3 pgrid((unsigned)(((a.m + 31) / 32) * NT), (unsigned)a.k);
+    if (a.bf16x3) hipLaunchKernelGGL((k_pack_coef<NT, true>), pgrid, dim3(64), 0, s, a);
+    else hipLaunchKernelGGL((k_pack_coef<NT, false>), pgrid, dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_block(const BlockProjectArgs& a, hipStream_t s) {
+    const int kc_max = 2 * a.r;
+    if (kc_max > 64 || a.k < 1 || a.k > a.kmax) return hipErrorInvalidValue;
+    if (kc_max <= 16) return launch_pack_nt<1>(a, s);
+    if (kc_max <= 32) return launch_pack_nt<2>(a, s);
+    if (kc_max <= 48) return launch_pack_nt<3>(a, s);
+    return launch_pack_nt<4>(a, s);
+}
 
 hipError_t launch_project_block(const BlockProjectArgs& a, hipStream_t s) {
     const int kc_max = 2 * a.r;
