@@ -32,6 +32,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix, published
+BF16_MFMA_TFLOPS = 2500.0  # MI355X dense BF16 matrix, published
 
 H, W, M, R = 1080, 1920, 64, 20
 COPY_BYTES = 1 << 30
@@ -53,6 +55,8 @@ def parse():
     ap.add_argument("--latency-blocks", type=int, default=5, help="block mode: blocks timed one by one")
     ap.add_argument("--cpu-windows", type=int, default=4, help="windows in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-split", action="store_true",
+                    help="block mode, FP32: skip the comparison run with split-BF16 projections")
     ap.add_argument("--serve", action="store_true",
                     help="run the 64-stream serving mix (Poisson arrivals) instead of the single-stream workload")
     ap.add_argument("--serve-streams", type=int, default=64)
@@ -249,21 +253,41 @@ def kernel_table(dmd, names):
     return out
 
 
-def roofline_of(kernels, bytes_per, source_of):
-    """Roofline of the dominant HBM-streaming kernel (longest average launch)."""
+def roofline_of(kernels, bytes_per, source_of, mfma=None, traffic_key=None):
+    """Roofline of the dominant kernel (longest average launch) among those
+    with algorithmic bytes: bound by HBM or, where `mfma` gives its matrix-core
+    work (flops per launch, the peak of its dtype), by whichever roof needs
+    more time."""
+    mfma = mfma or {}
     dom = max(bytes_per, key=lambda k: kernels.get(k, {}).get("avg_us", 0.0))
     avg_s = kernels[dom]["avg_us"] * 1e-6
-    achieved = bytes_per[dom] / avg_s / 1e9
     for k in bytes_per:
         if k in kernels:
             kernels[k]["algorithmic_bytes"] = bytes_per[k]
             kernels[k]["algorithmic_GBps"] = round(bytes_per[k] / (kernels[k]["avg_us"] * 1e-6) / 1e9, 1)
-    return {
-        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(dom, source_of[dom]),
-        "kernel": dom, "algorithmic_bytes_per_launch": bytes_per[dom],
-        "avg_launch_us": round(kernels[dom]["avg_us"], 2),
-    }
+            if k in mfma:
+                kernels[k]["mfma_flops"] = mfma[k][0]
+                kernels[k]["mfma_TFLOPs"] = round(mfma[k][0] / (kernels[k]["avg_us"] * 1e-6) / 1e12, 2)
+    t_hbm = bytes_per[dom] / (HBM_PEAK_GBS * 1e9)
+    out = {"kernel": dom, "algorithmic_bytes_per_launch": bytes_per[dom],
+           "avg_launch_us": round(kernels[dom]["avg_us"], 2),
+           "floors_us": {"hbm": round(t_hbm * 1e6, 1)}}
+    if dom in mfma:
+        flops, peak_tf, kind = mfma[dom]
+        t_mfma = flops / (peak_tf * 1e12)
+        out["floors_us"]["mfma"] = round(t_mfma * 1e6, 1)
+        out["mfma_work"] = kind
+        if t_mfma > t_hbm:
+            achieved = flops / avg_s / 1e12
+            out.update({"bound": "mfma", "achieved": round(achieved, 2), "peak": peak_tf, "unit": "TFLOP/s",
+                        "frac": round(achieved / peak_tf, 4),
+                        "traffic": traffic_for((traffic_key or {}).get(dom, dom), source_of[dom])})
+            return out
+    achieved = bytes_per[dom] / avg_s / 1e9
+    out.update({"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic_for((traffic_key or {}).get(dom, dom), source_of[dom])})
+    return out
 
 
 def single_latency(s, frames, t, L, phi):
@@ -335,7 +359,9 @@ def bench_single(args):
         kernels,
         {"gram_columns": (M + 2) * n * 4,             # read m kept columns + new frame, write the frame
          "project_modes": M * n * 4 + n * r_eff * 8},  # read X', write Phi (complex64)
-        {"gram_columns": "gram_push.hip", "project_modes": "project.hip"})
+        {"gram_columns": "gram_push.hip", "project_modes": "project.hip"},
+        {"project_modes": ((3.0 if args.precision == "bf16x3" else 1.0) * 2.0 * n * M * 2 * r_eff,
+                           BF16_MFMA_TFLOPS if args.precision == "bf16x3" else FP32_MFMA_TFLOPS, args.precision)})
     out = result_line(K / elapsed, K, Wu, elapsed, "f32", {
         "workload": "blob video 1920x1080 FP32 (n=2073600), m=64, r=20; single-frame mode: "
                     "step = push of one frame + FP64 solves + modes of its window",
@@ -347,27 +373,14 @@ def bench_single(args):
     return out, host_keep
 
 
-def bench_block(args):
-    """k frames per step (multi-column update): one block push, the FP64
-    solves of all k windows side by side, and the modes of all k windows."""
-    import numpy as np
-    import torch
-
-    import paper_1612_07875_amd as dmd
-
-    n = H * W
-    kb = args.block
-    K, Wu, L = args.steps, args.warmup, args.latency_frames
-    LB = args.latency_blocks
+def timed_blocks(dmd, torch, frames, n, kb, K, Wu, precision):
+    """Fill a window with block pushes, then Wu untimed and K timed steps of
+    one block push + the modes of all its windows.  Pushes (Gram update +
+    solves) go on one stream and projections on another, so the projection of
+    block b overlaps the Gram update and solves of block b + 1."""
     fill = M + 1
-    T = fill + (Wu + K + LB) * kb + L
-    keep = M + 1 + (args.cpu_windows if not args.no_cpu_baseline else 0)
-    frames, host_keep = make_frames(T, keep)
-
-    s = dmd.Stream(n, M, R, dtype="f32", max_block=kb, precision=args.precision)
+    s = dmd.Stream(n, M, R, dtype="f32", max_block=kb, precision=precision)
     phis = torch.zeros((kb, R, n), dtype=torch.complex64, device="cuda")
-    # pushes (Gram update + solves) on one stream, projections on another: the
-    # projection of block b overlaps the Gram update and solves of block b + 1
     sp, sm = torch.cuda.Stream(), torch.cuda.Stream()
     sp.wait_stream(torch.cuda.current_stream())
     sm.wait_stream(torch.cuda.current_stream())
@@ -395,14 +408,61 @@ def bench_block(args):
     dmd.profile_enable(False)
     kernels = kernel_table(dmd, ("gram_block", "block_solve", "pack_block", "project_block"))
     dmd.profile_reset()
-    print(f"[bench] timed {K} blocks of {kb} frames in {elapsed:.3f} s", file=sys.stderr, flush=True)
     wins, _ = s.block_eigs()
     bad = [w for w in wins if w[0] not in (0, 1)]
     if bad:
         raise RuntimeError(f"a window of the last block was not solved: status {bad[0][0]}")
-    r_eff = min(w[1].size for w in wins)
+    r_effs = [int(w[1].size) for w in wins]
+    return s, phis, t, elapsed, kernels, r_effs
 
-    # block latency: enqueue of a block -> all k windows' modes written
+
+def block_roofline(kernels, n, kb, r_effs, precision):
+    """Algorithmic bytes and flops of the block kernels (per launch)."""
+    kc_total = sum(2 * r for r in r_effs)           # real output columns over the k windows
+    flops = 2.0 * n * M * kc_total                   # project_block: X' (n x m) times m x kc per window
+    mfma = {"project_block": (flops, FP32_MFMA_TFLOPS, "fp32")}
+    if precision == "bf16x3":                        # three BF16 products per FP32 product
+        mfma = {"project_block": (3 * flops, BF16_MFMA_TFLOPS, "bf16x3")}
+    return roofline_of(
+        kernels,
+        {"gram_block": (M + 1 + kb) * n * 4 + kb * n * 4,                 # read window + block, write the block
+         "project_block": (M + kb - 1) * n * 4 + n * 8 * (kc_total // 2)},  # read the union of X', write k Phi
+        {"gram_block": "gram_block.hip", "project_block": "project.hip"},
+        mfma, {"project_block": "project_block_bf16x3"} if precision == "bf16x3" else None)
+
+
+def bench_block(args):
+    """k frames per step (multi-column update): one block push, the FP64
+    solves of all k windows side by side, and the modes of all k windows."""
+    import numpy as np
+    import torch
+
+    import paper_1612_07875_amd as dmd
+
+    n = H * W
+    kb = args.block
+    K, Wu, L = args.steps, args.warmup, args.latency_frames
+    LB = args.latency_blocks
+    fill = M + 1
+    T = fill + (Wu + K + LB) * kb + L
+    keep = M + 1 + (args.cpu_windows if not args.no_cpu_baseline else 0)
+    frames, host_keep = make_frames(T, keep)
+
+    split = None
+    if args.precision == "fp32" and not args.no_split:
+        # the same workload with split-BF16 projections, for comparison
+        s2, _, _, el2, kern2, re2 = timed_blocks(dmd, torch, frames, n, kb, K, Wu, "bf16x3")
+        s2.close()
+        torch.cuda.synchronize()
+        split = {"value": round(kb * K / el2, 2), "ms_per_step": round(1000.0 * el2 / K, 4),
+                 "kernels": kern2, "roofline": block_roofline(kern2, n, kb, re2, "bf16x3")}
+        print(f"[bench] split-BF16: {kb * K / el2:.1f} window updates/s", file=sys.stderr, flush=True)
+
+    s, phis, t, elapsed, kernels, r_effs = timed_blocks(dmd, torch, frames, n, kb, K, Wu, args.precision)
+    print(f"[bench] timed {K} blocks of {kb} frames in {elapsed:.3f} s", file=sys.stderr, flush=True)
+    r_eff = min(r_effs)
+
+    # block latency: enqueue of a block -> all k windows' modes written (one stream)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     blat = []
@@ -417,11 +477,7 @@ def bench_block(args):
     latency, t = single_latency(s, frames, t, L, phis[0].T)
     info = s.info()
     s.close()
-    roofline = roofline_of(
-        kernels,
-        {"gram_block": (M + 1 + kb) * n * 4 + kb * n * 4,           # read window + block, write the block
-         "project_block": (M + kb - 1) * n * 4 + kb * n * r_eff * 8},  # read the union of X', write k Phi
-        {"gram_block": "gram_block.hip", "project_block": "project.hip"})
+    roofline = block_roofline(kernels, n, kb, r_effs, args.precision)
     out = result_line(kb * K / elapsed, K, Wu, elapsed, "f32", {
         "workload": f"blob video 1920x1080 FP32 (n=2073600), m=64, r=20; block mode: step = one push of "
                     f"{kb} frames (multi-column update) + FP64 solves of all {kb} windows + modes of all {kb} windows",
@@ -436,6 +492,8 @@ def bench_block(args):
                 "latency_ms": latency, "latency_note": "latency_ms: single-frame pushes (push -> modes) on "
                                                        "the same stream after the timed blocks",
                 "jacobi_sweeps": int(info.sweeps), "qr_iters": int(info.qr_iters)})
+    if split is not None:
+        out["split_bf16"] = split
     return out, host_keep
 
 

@@ -373,14 +373,15 @@ void k_project_block(BlockProjectArgs a) {
     if (!desc->valid) return;
     const int m = a.m, k = a.k;
     const int ncols = m + k - 1;
+    const int ncols_pad = k - 1 + 32 * ((m + 31) / 32);  // whole chunks for every window
     float* U = dynp;
     const int64_t row0 = (int64_t)blockIdx.x * kBlkRows;
     const int base = desc->base;  // slot of staged column 0, before the wrap
     const float* ring = static_cast<const float*>(a.ring);
-    for (int t = threadIdx.x; t < ncols * (kBlkRows / 4); t += kThreads) {
+    for (int t = threadIdx.x; t < ncols_pad * (kBlkRows / 4); t += kThreads) {
         const int c = t / (kBlkRows / 4), q = t % (kBlkRows / 4);
-        const float* src = ring + (int64_t)((base + c) % a.slots) * a.ld + row0 + 4 * q;
-        const float4 x = *reinterpret_cast<const float4*>(src);
+        float4 x = float4{0.0f, 0.0f, 0.0f, 0.0f};
+        if (c < ncols) x = *reinterpret_cast<const float4*>(ring + (int64_t)((base + c) % a.slots) * a.ld + row0 + 4 * q);
         if constexpr (BF3) {
             *reinterpret_cast<uint4*>(&U[c * kBlkLDR + 4 * q]) =
                 uint4{split_word(x.x), split_word(x.y), split_word(x.z), split_word(x.w)};
@@ -409,9 +410,10 @@ void k_project_block(BlockProjectArgs a) {
             f[nt].y = fb[nt * 128 + 1];
         }
     };
-    // acc += (window w's columns cb .. cb+31) x (their coefficient fragments)
+    // acc += (window w's columns cb .. cb+31) x (their coefficient fragments).
+    // Columns past m read the zero padding of the stage (and meet zero
+    // coefficients), so no chunk needs masks.
     auto chunk = [&](int w, int cb, const Frag (&f)[NT], v4f (&acc)[4][NT]) {
-        const bool full = cb + 32 <= m;  // a whole chunk (the common case) needs no masks
         if constexpr (BF3) {
             v8bf bhi[NT], blo[NT];
 #pragma unroll
@@ -423,12 +425,7 @@ void k_project_block(BlockProjectArgs a) {
             for (int rt = 0; rt < 4; ++rt) {
                 unsigned d[8];
 #pragma unroll
-                for (int ks = 0; ks < 8; ++ks) {
-                    const int col = cb + 4 * ks + lk;
-                    const bool cin = full || col < m;
-                    const unsigned v = U32[(w + (cin ? col : 0)) * kBlkLDR + 16 * rt + li];
-                    d[ks] = cin ? v : 0u;
-                }
+                for (int ks = 0; ks < 8; ++ks) d[ks] = U32[(w + cb + 4 * ks + lk) * kBlkLDR + 16 * rt + li];
                 uint4 h, l;
                 h.x = __builtin_amdgcn_perm(d[1], d[0], 0x05040100u);
                 h.y = __builtin_amdgcn_perm(d[3], d[2], 0x05040100u);
@@ -445,9 +442,7 @@ void k_project_block(BlockProjectArgs a) {
         } else {
 #pragma unroll
             for (int ks = 0; ks < 8; ++ks) {
-                const int col = cb + 4 * ks + lk;
-                const bool cin = full || col < m;
-                const float* ucol = U + (w + (cin ? col : 0)) * kBlkLDR;
+                const float* ucol = U + (w + cb + 4 * ks + lk) * kBlkLDR;
                 float bv[NT];
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) {
@@ -457,7 +452,7 @@ void k_project_block(BlockProjectArgs a) {
                 }
 #pragma unroll
                 for (int rt = 0; rt < 4; ++rt) {
-                    const float av = cin ? ucol[16 * rt + li] : 0.0f;
+                    const float av = ucol[16 * rt + li];
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt)
                         acc[rt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[nt], acc[rt][nt], 0, 0, 0);
@@ -465,6 +460,7 @@ void k_project_block(BlockProjectArgs a) {
             }
         }
     };
+
 
     Frag f0[PF >= 1 ? NT : 1], f1[PF == 2 ? NT : 1];
     if (wave < k) {
@@ -583,7 +579,7 @@ void k_pack_coef(BlockProjectArgs a) {
     }
 }
 
-size_t block_lds(int m, int k) { return sizeof(float) * (size_t)(m + k - 1) * kBlkLDR; }
+size_t block_lds(int m, int k) { return sizeof(float) * (size_t)(k - 1 + 32 * ((m + 31) / 32)) * kBlkLDR; }
 
 template <int NT>
 hipError_t launch_block_nt(const BlockProjectArgs& a, hipStream_t s) {
