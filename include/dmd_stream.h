@@ -126,7 +126,15 @@ typedef struct {
                             2 max_block spare slots, and there are max_block - 1
                             extra solve workspaces                               */
     int32_t eig_solver;  /* dmd_eig_solver_t for the symmetric eig of X^* X       */
-    int32_t reserved[5]; /* must be zero                                             */
+    int32_t buildup;     /* 1: build-up start (Sec. 5): while the window fills, a
+                            window of c >= 3 snapshots is solved as a window of
+                            m' = c - 1 columns (X = its first c - 1 snapshots,
+                            X' = its last c - 1, rank <= min(r, m')), so results
+                            exist from the third push on; sigma and the rows of
+                            V past m' read zero.  Dense streams with
+                            max_block = 1 only.  0 (default): DMD_E_NOT_READY
+                            until the window holds m + 1 snapshots              */
+    int32_t reserved[4]; /* must be zero                                             */
 } dmd_opts_t;
 
 typedef struct dmd_stream dmd_stream_t;

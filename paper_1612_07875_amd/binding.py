@@ -39,7 +39,8 @@ class Opts(ctypes.Structure):
         ("dtype", ctypes.c_int32), ("precision", ctypes.c_int32), ("max_nnz", ctypes.c_int32),
         ("max_sweeps", ctypes.c_int32), ("max_qr_iter", ctypes.c_int32), ("auto_solve", ctypes.c_int32),
         ("rcond", ctypes.c_double), ("tol", ctypes.c_double), ("warm_start", ctypes.c_int32),
-        ("max_block", ctypes.c_int32), ("eig_solver", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5),
+        ("max_block", ctypes.c_int32), ("eig_solver", ctypes.c_int32), ("buildup", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -165,7 +166,7 @@ class Stream:
     def __init__(self, n: int, m: int, r: int, dtype: str = "f32", precision: str = "default",
                  auto_solve: bool = True, rcond: Optional[float] = None, tol: float = 0.0,
                  max_nnz: int = 0, max_sweeps: int = 0, max_qr_iter: int = 0, warm_start: bool = False,
-                 max_block: int = 1, eig_solver: str = "default"):
+                 max_block: int = 1, eig_solver: str = "default", buildup: bool = False):
         if not torch.cuda.is_available():
             raise RuntimeError("libdmdstream needs a HIP GPU; none is available")
         lib = load()
@@ -182,6 +183,7 @@ class Stream:
         o.warm_start = 1 if warm_start else 0
         o.max_block = int(max_block)
         o.eig_solver = EIG_SOLVERS[eig_solver]
+        o.buildup = 1 if buildup else 0
         h = _P()
         check(lib.dmd_stream_create(int(n), int(m), int(r), ctypes.byref(o), ctypes.byref(h)))
         self._h = h

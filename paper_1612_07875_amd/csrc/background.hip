@@ -28,10 +28,11 @@ void k_background(BackgroundArgs a) {
     constexpr int N = V16<TX>::N;
     __shared__ T s_beta[2 * kMaxM];
     const DevState* st = a.st;
-    if (st->count < a.m + 1 || (st->solve_status != ST_OK && st->solve_status != ST_W_RANK) || st->r_eff == 0)
+    const int m = window_cols(a.m, a.buildup, st);  // columns of X' (fewer during a build-up start)
+    if (m == 0 || (st->solve_status != ST_OK && st->solve_status != ST_W_RANK) || st->r_eff == 0)
         return;
     const T* beta = static_cast<const T*>(a.beta);
-    for (int i = threadIdx.x; i < 2 * a.m; i += kThreads) s_beta[i] = beta[i];
+    for (int i = threadIdx.x; i < 2 * m; i += kThreads) s_beta[i] = beta[i];
     __syncthreads();
 
     const int64_t r0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * N;
@@ -43,7 +44,7 @@ void k_background(BackgroundArgs a) {
     for (int e = 0; e < N; ++e) re[e] = im[e] = xn[e] = T(0);
     // rows r0 .. r0+N-1 lie inside the padded column (ld is a multiple of 64)
 #pragma unroll 4
-    for (int j = 0; j < a.m; ++j) {
+    for (int j = 0; j < m; ++j) {
         const VT v = *reinterpret_cast<const VT*>(ring + (int64_t)slot_of(oldest, 1 + j, a.slots) * a.ld + r0);
         const TX* pv = reinterpret_cast<const TX*>(&v);
         const T br = s_beta[2 * j], bi = s_beta[2 * j + 1];

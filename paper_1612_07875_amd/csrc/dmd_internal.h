@@ -53,6 +53,15 @@ struct ResultsLayout {
 };
 
 // Physical slot of logical window column l (0 = oldest).
+// Columns of X in the current window: m once the window holds m+1 snapshots;
+// during a build-up start (Sec. 5: results while the window fills) count - 1
+// from count = 3 on; 0 while there is nothing to solve.
+__device__ inline int window_cols(int m, int buildup, const DevState* st) {
+    const int c = st->count;
+    if (c >= m + 1) return m;
+    return (buildup && c >= 3) ? c - 1 : 0;
+}
+
 __host__ __device__ inline int slot_of(int oldest, int l, int slots) {
     int s = oldest + l;
     return s >= slots ? s - slots : s;
@@ -120,10 +129,12 @@ struct SolveArgs {
     double rcond, tol;
     int max_sweeps, max_qr_iter;
     int warm_start;        // start Jacobi from the previous solve's eigenvectors
-    double* sigma;         // results block: m sigmas
+    int buildup;           // solve partial windows of 3..m snapshots (window_cols)
+    double* sigma;         // results block: m sigmas (zero past the window's columns)
     double* lam;           // results block: 2 r doubles
     double* amp;           // results block: 2 r doubles, mode amplitudes b
-    double* V;             // m x r (complex: interleaved), canonical columns
+    double* V;             // m x r (complex: interleaved), canonical columns, leading
+                           // dimension m (rows past the window's columns zero)
     double* At;            // r x r (complex: interleaved)
     double* W;             // r x r complex
     double* work;          // global scratch: 4 M (M+1) values (A, V, Q or Z, tail scratch)
@@ -193,6 +204,7 @@ struct ProjectArgs {
     int coef_f64;          // coefficients, accumulation and output in double
     int precision;         // DMD_PREC_* used for float data
     int block_only;        // a window of a block push: skip it if the block was rejected
+    int buildup;           // partial windows (window_cols): X_sub has window_cols columns
 };
 hipError_t launch_project(const ProjectArgs& a, hipStream_t s);
 // Grouped FP32 projections of many streams in one launch.
@@ -251,6 +263,7 @@ struct BackgroundArgs {
     const void* ring;
     int64_t ld, n;
     int m, slots;
+    int buildup;           // partial windows (window_cols)
     const void* beta;      // m complex, float or double (elem_f64 / coef_f64)
     void* fg;              // n values of the data type (may be null)
     void* bg;              // n values of the data type (may be null)

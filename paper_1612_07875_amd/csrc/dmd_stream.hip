@@ -270,6 +270,7 @@ void fill_solve_args(const dmd_stream* h, dmd::SolveArgs& a) {
     a.max_sweeps = h->opts.max_sweeps;
     a.max_qr_iter = h->opts.max_qr_iter;
     a.warm_start = h->opts.warm_start;
+    a.buildup = h->opts.buildup;
     a.sigma = reinterpret_cast<double*>(h->res_dev + h->L.sigma_off);
     a.lam = reinterpret_cast<double*>(h->res_dev + h->L.lam_off);
     a.amp = reinterpret_cast<double*>(h->res_dev + h->L.amp_off);
@@ -293,6 +294,7 @@ void fill_shadow_args(const dmd_stream* h, dmd::SolveArgs& a, int e) {
     char* res = h->sh_dev + (size_t)e * h->sh_stride;
     a.st = reinterpret_cast<DevState*>(res);
     a.warm_start = 0;
+    a.buildup = 0;
     a.sigma = reinterpret_cast<double*>(res + h->L.sigma_off);
     a.lam = reinterpret_cast<double*>(res + h->L.lam_off);
     a.amp = reinterpret_cast<double*>(res + h->L.amp_off);
@@ -325,6 +327,7 @@ void fill_project_args(const dmd_stream* h, dmd::ProjectArgs& a, void* out, int6
     a.elem_f64 = h->elem_bytes == 8;
     a.coef_f64 = h->coef_f64;
     a.precision = h->opts.precision;
+    a.buildup = h->opts.buildup;
 }
 
 int enqueue_solve(dmd_stream* h, hipStream_t s) {
@@ -401,7 +404,7 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
     dmd_opts_init(&o);
     if (opts) {
         o = *opts;
-        for (int i = 0; i < 5; ++i)
+        for (int i = 0; i < 4; ++i)
             if (o.reserved[i] != 0) return fail(DMD_E_INVAL, "opts.reserved must be zero");
         if (o.max_sweeps == 0) o.max_sweeps = 40;
         if (o.max_qr_iter == 0) o.max_qr_iter = 60;
@@ -418,6 +421,7 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
     if (o.max_sweeps < 1 || o.max_qr_iter < 1) return fail(DMD_E_INVAL, "iteration limits must be positive");
     if (o.auto_solve != 0 && o.auto_solve != 1) return fail(DMD_E_INVAL, "auto_solve must be 0 or 1");
     if (o.warm_start != 0 && o.warm_start != 1) return fail(DMD_E_INVAL, "warm_start must be 0 or 1");
+    if (o.buildup != 0 && o.buildup != 1) return fail(DMD_E_INVAL, "buildup must be 0 or 1");
     if (o.eig_solver < DMD_EIG_DEFAULT || o.eig_solver > DMD_EIG_TRIDIAG)
         return fail(DMD_E_INVAL, "unknown eig_solver %d", o.eig_solver);
     if (o.eig_solver == DMD_EIG_TRIDIAG && o.warm_start)
@@ -425,6 +429,8 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
     if (o.max_block == 0) o.max_block = 1;
     if (o.max_block < 1 || o.max_block > 64) return fail(DMD_E_INVAL, "max_block must be in [1, 64] (got %d)", o.max_block);
     if (o.dtype == DMD_C64_CSR && o.max_block != 1) return fail(DMD_E_UNSUPPORTED, "block pushes are for dense streams");
+    if (o.buildup && (o.dtype == DMD_C64_CSR || o.max_block != 1))
+        return fail(DMD_E_UNSUPPORTED, "the build-up start is for dense streams with single pushes");
     if (o.dtype == DMD_C64_CSR) {
         if (o.max_nnz == 0) o.max_nnz = (int32_t)(n < INT32_MAX ? n : INT32_MAX);
         if (o.max_nnz < 1 || o.max_nnz > n) return fail(DMD_E_INVAL, "max_nnz must be in [1, n]");
@@ -979,6 +985,7 @@ DMD_API int dmd_stream_background(dmd_stream_t* h, void* fg, void* bg, void* str
     a.n = h->n;
     a.m = h->m;
     a.slots = h->slots;
+    a.buildup = h->opts.buildup;
     a.beta = h->Bbg;
     a.fg = fg;
     a.bg = bg;

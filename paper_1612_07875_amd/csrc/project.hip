@@ -93,7 +93,7 @@ __device__ void project_body(const ProjectArgs& a, int blk, T* stage) {
     const int k_eff = st->r_eff;
     const int kcols = a.cplx_out ? 2 * k_eff : k_eff;
     if (kcols == 0) return;
-    const int m = a.m;
+    const int m = window_cols(a.m, a.buildup, st);  // columns of X_sub (fewer during a build-up start)
     const int rowstride = a.cplx_out ? 2 * a.kmax : a.kmax;
     const T* B = reinterpret_cast<const T*>(a.B);
 
@@ -201,7 +201,7 @@ __device__ void project_body_bf3(const ProjectArgs& a, int blk, float* stage) {
     const int k_eff = st->r_eff;
     const int kcols = a.cplx_out ? 2 * k_eff : k_eff;
     if (kcols == 0) return;
-    const int m = a.m;
+    const int m = window_cols(a.m, a.buildup, st);  // columns of X_sub (fewer during a build-up start)
     const int rowstride = a.cplx_out ? 2 * a.kmax : a.kmax;
     const float* B = reinterpret_cast<const float*>(a.B);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

@@ -172,12 +172,14 @@ __device__ void sym_tail(const SolveArgs& a, int ld, S* Vc, S* spare1, S* spare2
                          int nvec, int sweeps, bool converged, int warm) {
     using SC = Scal<S>;
     const int tid = threadIdx.x;
-    const int m = a.m;
     const int slots = a.slots;
     DevState* st = a.st;
+    const int m = window_cols(a.m, a.buildup, st);  // columns of X (fewer during a build-up start)
+    const int ldv = a.m;                            // storage stride of V and V_full
     const int oldest = st->oldest;
     const int nw = NT / 64, lane = tid & 63, wv = tid >> 6;
     __shared__ int s_reff;
+    for (int i = m + tid; i < a.m; i += NT) a.sigma[i] = 0.0;
     // sigma = sqrt(|d|), sorted descending (stable in the index)
     for (int i = tid; i < m; i += NT) {
         const double si = s_sig[i];
@@ -201,11 +203,12 @@ __device__ void sym_tail(const SolveArgs& a, int ld, S* Vc, S* spare1, S* spare2
         s_reff = k;
     }
     // the eigenvectors in sigma order, kept for the next solve's warm start
-    // (only when all m are known)
-    if (nvec >= m) {
+    // (only when all m are known and the window is full)
+    const bool keep_full = nvec >= m && m == ldv;
+    if (keep_full) {
         for (int idx = tid; idx < m * m; idx += NT) {
             const int i = idx % m, k = idx / m;
-            store_s<S>(a.Vfull, i + (int64_t)k * m, Vc[i + (size_t)s_perm[k] * ld]);
+            store_s<S>(a.Vfull, i + (int64_t)k * ldv, Vc[i + (size_t)s_perm[k] * ld]);
         }
     }
     __syncthreads();
@@ -231,8 +234,9 @@ __device__ void sym_tail(const SolveArgs& a, int ld, S* Vc, S* spare1, S* spare2
         for (int i = lane; i < m; i += 64) {
             const S v = mulr(Vc[i + (size_t)col * ld], ph);
             Vr[i + (size_t)k * ld] = v;
-            store_s<S>(a.V, i + (int64_t)k * m, v);
+            store_s<S>(a.V, i + (int64_t)k * ldv, v);
         }
+        for (int i = m + lane; i < ldv; i += 64) store_s<S>(a.V, i + (int64_t)k * ldv, SC::zero());
     }
     __syncthreads();
 
@@ -280,7 +284,7 @@ __device__ void sym_tail(const SolveArgs& a, int ld, S* Vc, S* spare1, S* spare2
         st->sweeps = sweeps;
         st->solve_status = converged ? (k_eff < lim ? ST_W_RANK : ST_OK) : ST_E_CONVERGENCE;
         if (k_eff == 0) st->solve_status = ST_W_RANK;
-        st->vprev_valid = (converged && nvec >= m) ? 1 : 0;
+        st->vprev_valid = (converged && keep_full) ? 1 : 0;
         st->vprev_push = st->pushes;
         st->warm = warm;
     }
@@ -293,12 +297,12 @@ __device__ void solve_sym_body(const SolveArgs& a, int M) {
     using SC = Scal<S>;
     extern __shared__ double dyn[];
     const int tid = threadIdx.x;
-    const int m = a.m;
     const int slots = a.slots;
     DevState* st = a.st;
-
-    const int count = st->count;
-    if (count < m + 1) {
+    // the columns of X; a partial window (build-up) is the leading block of
+    // the zero-padded M x M matrix, whose padding no rotation touches
+    const int m = window_cols(a.m, a.buildup, st);
+    if (m == 0) {
         if (tid == 0) {
             st->solve_status = ST_E_NOT_READY;
             st->r_eff = 0;
@@ -359,7 +363,7 @@ __device__ void solve_sym_body(const SolveArgs& a, int M) {
             if (i < m && j < m) {
                 int src = i + shift;
                 if (src >= m) src -= m;
-                v = load_s<S>(a.Vfull, src + (int64_t)j * m);
+                v = load_s<S>(a.Vfull, src + (int64_t)j * a.m);
             }
             bufQ[i + (size_t)j * ld] = v;
         }
@@ -544,7 +548,8 @@ __device__ void solve_eig_body(const SolveArgs& a) {
     DevState* st = a.st;
     const int status0 = st->solve_status;
     const int k = st->r_eff;
-    const int m = a.m;
+    const int m = window_cols(a.m, a.buildup, st);  // columns of X
+    const int ldv = a.m;                            // leading dimension of V
     if (st->skipped) {
         publish(a);
         return;
@@ -874,8 +879,8 @@ __device__ void solve_eig_body(const SolveArgs& a) {
         H[i + q * LDH] = Y[i + q * LDH] * s_ls[q];
     }
     if (lane < k) {
-        const cplx v0 = a.cplx ? cplx{a.V[2 * ((int64_t)lane * m)], a.V[2 * ((int64_t)lane * m) + 1]}
-                               : mkc(a.V[(int64_t)lane * m]);
+        const cplx v0 = a.cplx ? cplx{a.V[2 * ((int64_t)lane * ldv)], a.V[2 * ((int64_t)lane * ldv) + 1]}
+                               : mkc(a.V[(int64_t)lane * ldv]);
         s_rhs[lane] = s_sig[lane] * conj(v0);
     }
     __syncthreads();
@@ -958,8 +963,8 @@ __device__ void solve_eig_body(const SolveArgs& a) {
         for (int p = 0; p < kRMax; ++p) {
             cplx v = mkc(0.0);
             if (p < k) {
-                if (a.cplx) v = cplx{a.V[2 * (i + (int64_t)p * m)], a.V[2 * (i + (int64_t)p * m) + 1]};
-                else v = mkc(a.V[i + (int64_t)p * m]);
+                if (a.cplx) v = cplx{a.V[2 * (i + (int64_t)p * ldv)], a.V[2 * (i + (int64_t)p * ldv) + 1]};
+                else v = mkc(a.V[i + (int64_t)p * ldv]);
                 v = v * (1.0 / s_sig[p]);
             }
             vrow[p] = v;
@@ -1122,10 +1127,10 @@ __device__ void solve_trid_body(const SolveArgs& a) {
     extern __shared__ double dyn[];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
-    const int m = a.m, n = m;
     const int slots = a.slots;
     DevState* st = a.st;
-    if (st->count < m + 1) {
+    const int m = window_cols(a.m, a.buildup, st), n = m;  // fewer columns during a build-up start
+    if (m == 0) {
         if (tid == 0) {
             st->solve_status = ST_E_NOT_READY;
             st->r_eff = 0;

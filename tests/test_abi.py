@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_opts_struct_matches_header_layout():
-    # 6 int32 + 2 double + warm_start + max_block + 6 int32 reserved
+    # 6 int32 + 2 double + warm_start, max_block, eig_solver, buildup + 4 int32 reserved
     assert ctypes.sizeof(binding.Opts) == 6 * 4 + 2 * 8 + 8 * 4
     lib = dmd.load()
     o = binding.Opts()
@@ -72,6 +72,26 @@ def test_create_rejects_bad_options():
     o.dtype = 7
     assert lib.dmd_stream_create(100, 8, 2, ctypes.byref(o), ctypes.byref(h)) == dmd.E_INVAL
     assert lib.dmd_stream_create(100, 8, 2, None, None) == dmd.E_INVAL
+
+
+def test_buildup_option_checks():
+    """The build-up start: off by default, 0/1 only, dense single-push streams only."""
+    lib = dmd.load()
+    o = binding.Opts()
+    lib.dmd_opts_init(ctypes.byref(o))
+    assert o.buildup == 0
+    h = ctypes.c_void_p()
+    o.buildup = 2
+    assert lib.dmd_stream_create(100, 8, 2, ctypes.byref(o), ctypes.byref(h)) == dmd.E_INVAL
+    lib.dmd_opts_init(ctypes.byref(o))
+    o.buildup = 1
+    o.max_block = 4
+    assert lib.dmd_stream_create(100, 8, 2, ctypes.byref(o), ctypes.byref(h)) == dmd.E_UNSUPPORTED
+    lib.dmd_opts_init(ctypes.byref(o))
+    o.buildup = 1
+    o.dtype = binding.DTYPES["c64_csr"]
+    assert lib.dmd_stream_create(100, 8, 2, ctypes.byref(o), ctypes.byref(h)) == dmd.E_UNSUPPORTED
+    assert not h.value
 
 
 def test_null_handle_calls_fail_cleanly():
