@@ -271,6 +271,33 @@ int dmd_stream_atilde(dmd_stream_t* h, double* Atilde, int64_t lda, double* W, i
  * else double.  Waits for the handle's work. */
 int dmd_stream_gram(dmd_stream_t* h, double* G, int64_t ldg, int32_t* ncols);
 
+/* ------------------------------------------------------------ checkpoint / resume (Sec. 5) */
+
+/* A checkpoint holds what the streaming update keeps between pushes: the
+ * window's snapshots (in window order), its Gram (FP64, window order) and the
+ * stream's counters, in a versioned host-memory format; solve results are
+ * recomputed on restore.  dmd_stream_checkpoint_bytes gives the size for the
+ * current window (waits for the handle's state-changing work).  Errors:
+ * DMD_E_INVAL (NULL), DMD_E_DEVICE. */
+int dmd_stream_checkpoint_bytes(dmd_stream_t* h, int64_t* bytes);
+
+/* Write a checkpoint of h into the host buffer buf (bytes >=
+ * dmd_stream_checkpoint_bytes).  Waits for the handle's state-changing work;
+ * blocks until written.  Errors: DMD_E_INVAL (NULL, buffer too small),
+ * DMD_E_DEVICE. */
+int dmd_stream_save(dmd_stream_t* h, void* buf, int64_t bytes);
+
+/* Replace the window of h by the checkpoint in buf: h must have been created
+ * with the same dtype, n, m and r (sparse streams: max_nnz at least the
+ * checkpoint's largest snapshot); its options may differ.  Ordered after
+ * h's earlier work on any stream; writes the window and Gram from host memory
+ * (blocking), then, with auto_solve on, enqueues the solves on `stream`.
+ * Pushes after a restore give the results the saved stream would give
+ * (bitwise: same kernels on the same values), except that a warm-started
+ * Jacobi solve starts cold once.  Errors: DMD_E_INVAL (NULL, not a
+ * checkpoint, other shape, truncated or inconsistent), DMD_E_DEVICE. */
+int dmd_stream_restore(dmd_stream_t* h, const void* buf, int64_t bytes, void* stream);
+
 /* ------------------------------------------------------------ projections (Eq. Phi, Sec. 2.1) */
 
 /* DMD modes Phi = X' V Sigma^-1 W of the latest solve into `phi` (device,

@@ -80,6 +80,9 @@ SIGNATURES = {
     "dmd_stream_svd": [_P, _DP, _DP, _I64, _I32P],
     "dmd_stream_atilde": [_P, _DP, _I64, _DP, _I64, _I32P],
     "dmd_stream_gram": [_P, _DP, _I64, _I32P],
+    "dmd_stream_checkpoint_bytes": [_P, ctypes.POINTER(ctypes.c_int64)],
+    "dmd_stream_save": [_P, ctypes.c_void_p, _I64],
+    "dmd_stream_restore": [_P, ctypes.c_void_p, _I64, ctypes.c_void_p],
     "dmd_stream_modes": [_P, _P, _I64, _P],
     "dmd_stream_pod": [_P, _P, _I64, _P],
     "dmd_stream_amplitudes": [_P, _DP, _DP, _I32P, _I32P],
@@ -338,6 +341,21 @@ class Stream:
         G = G[:k, : k * cw]
         G = (G[:, 0::2] + 1j * G[:, 1::2]) if cw == 2 else G
         return np.ascontiguousarray(G.T)
+
+    # ---------------------------------------------------------------- checkpoint / resume
+    def save(self) -> bytes:
+        """Checkpoint of the window (snapshots, Gram, counters) as bytes."""
+        lib = load()
+        nb = ctypes.c_int64(0)
+        check(lib.dmd_stream_checkpoint_bytes(self._h, ctypes.byref(nb)))
+        buf = ctypes.create_string_buffer(nb.value)
+        check(lib.dmd_stream_save(self._h, buf, nb.value))
+        return buf.raw
+
+    def restore(self, blob: bytes, stream=None) -> int:
+        """Replace the window by a checkpoint from save() of a stream of the same shape."""
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        return check(load().dmd_stream_restore(self._h, buf, len(blob), _stream_ptr(stream)))
 
     # ---------------------------------------------------------------- projections
     def modes(self, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:

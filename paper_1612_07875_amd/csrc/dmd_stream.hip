@@ -920,6 +920,202 @@ DMD_API int dmd_stream_gram(dmd_stream_t* h, double* G, int64_t ldg, int32_t* nc
     return DMD_OK;
 }
 
+// ------------------------------------------------------------ checkpoint / resume
+
+namespace {
+// A checkpoint: this header, then the window's Gram (count x count, window
+// order, column-major FP64; interleaved complex for sparse streams), then the
+// window's snapshots in window order (dense: count x n elements; sparse: the
+// count nnz values, then each snapshot's indices and complex64 values).
+struct CkptHeader {
+    char magic[8];          // "DMDCKPT1"
+    int32_t version;        // 1
+    int32_t dtype;
+    int64_t n;
+    int32_t m, r, count, max_nnz;
+    int32_t pushes, solves, rejected_nonfinite, rejected_index;
+    int64_t gram_bytes, data_bytes;
+};
+constexpr char kCkptMagic[8] = {'D', 'M', 'D', 'C', 'K', 'P', 'T', '1'};
+
+// Bytes of the window's snapshots in a checkpoint (sparse: needs the nnz of each).
+int ckpt_data_bytes(dmd_stream* h, const DevState& st, std::vector<int32_t>* nnz, int64_t* bytes) {
+    if (!h->cplx) {
+        *bytes = (int64_t)st.count * h->n * h->elem_bytes;
+        return DMD_OK;
+    }
+    std::vector<int32_t> all(h->slots);
+    HIP_TRY(hipMemcpy(all.data(), h->ring_nnz, sizeof(int32_t) * h->slots, hipMemcpyDeviceToHost));
+    int64_t b = sizeof(int32_t) * (int64_t)st.count;
+    nnz->resize(st.count);
+    for (int j = 0; j < st.count; ++j) {
+        (*nnz)[j] = all[dmd::slot_of(st.oldest, j, h->slots)];
+        b += (int64_t)(*nnz)[j] * (sizeof(int32_t) + sizeof(float2));
+    }
+    *bytes = b;
+    return DMD_OK;
+}
+}  // namespace
+
+DMD_API int dmd_stream_checkpoint_bytes(dmd_stream_t* h, int64_t* bytes) {
+    if (int rc = check_handle(h)) return rc;
+    if (!bytes) return fail(DMD_E_INVAL, "null bytes");
+    DeviceGuard g(h->device);
+    DevState st;
+    if (int rc = read_state(h, &st)) return rc;
+    std::vector<int32_t> nnz;
+    int64_t data = 0;
+    if (int rc = ckpt_data_bytes(h, st, &nnz, &data)) return rc;
+    const int cw = h->cplx ? 2 : 1;
+    *bytes = (int64_t)sizeof(CkptHeader) + (int64_t)sizeof(double) * cw * st.count * st.count + data;
+    return DMD_OK;
+}
+
+DMD_API int dmd_stream_save(dmd_stream_t* h, void* buf, int64_t bytes) {
+    if (int rc = check_handle(h)) return rc;
+    if (!buf) return fail(DMD_E_INVAL, "null buffer");
+    DeviceGuard g(h->device);
+    DevState st;
+    if (int rc = read_state(h, &st)) return rc;  // waits for the handle's state-changing work
+    std::vector<int32_t> nnz;
+    int64_t data = 0;
+    if (int rc = ckpt_data_bytes(h, st, &nnz, &data)) return rc;
+    const int cw = h->cplx ? 2 : 1;
+    const int64_t gbytes = (int64_t)sizeof(double) * cw * st.count * st.count;
+    if (bytes < (int64_t)sizeof(CkptHeader) + gbytes + data)
+        return fail(DMD_E_INVAL, "buffer too small (%lld < %lld bytes)", (long long)bytes,
+                    (long long)(sizeof(CkptHeader) + gbytes + data));
+    char* out = static_cast<char*>(buf);
+    CkptHeader hd{};
+    std::memcpy(hd.magic, kCkptMagic, 8);
+    hd.version = 1;
+    hd.dtype = h->opts.dtype;
+    hd.n = h->n;
+    hd.m = h->m;
+    hd.r = h->r;
+    hd.count = st.count;
+    hd.max_nnz = h->cplx ? h->max_nnz : 0;
+    hd.pushes = st.pushes;
+    hd.solves = st.solves;
+    hd.rejected_nonfinite = st.rejected_nonfinite;
+    hd.rejected_index = st.rejected_index;
+    hd.gram_bytes = gbytes;
+    hd.data_bytes = data;
+    std::memcpy(out, &hd, sizeof(hd));
+    out += sizeof(hd);
+    // Gram in window order
+    std::vector<double> G((size_t)cw * h->slots * h->slots);
+    HIP_TRY(hipMemcpy(G.data(), h->G, sizeof(double) * G.size(), hipMemcpyDeviceToHost));
+    double* go = reinterpret_cast<double*>(out);
+    for (int j = 0; j < st.count; ++j)
+        for (int i = 0; i < st.count; ++i) {
+            const int si = dmd::slot_of(st.oldest, i, h->slots), sj = dmd::slot_of(st.oldest, j, h->slots);
+            for (int c = 0; c < cw; ++c)
+                go[cw * (i + (size_t)j * st.count) + c] = G[cw * (si + (size_t)sj * h->slots) + c];
+        }
+    out += gbytes;
+    // snapshots in window order
+    if (!h->cplx) {
+        const size_t col = (size_t)h->n * h->elem_bytes;
+        for (int j = 0; j < st.count; ++j) {
+            const char* src = static_cast<const char*>(h->ring) +
+                              (size_t)dmd::slot_of(st.oldest, j, h->slots) * h->ld * h->elem_bytes;
+            HIP_TRY(hipMemcpy(out + j * col, src, col, hipMemcpyDeviceToHost));
+        }
+    } else {
+        std::memcpy(out, nnz.data(), sizeof(int32_t) * st.count);
+        out += sizeof(int32_t) * st.count;
+        for (int j = 0; j < st.count; ++j) {
+            const size_t sl = (size_t)dmd::slot_of(st.oldest, j, h->slots);
+            HIP_TRY(hipMemcpy(out, h->ring_idx + sl * h->max_nnz, sizeof(int32_t) * nnz[j], hipMemcpyDeviceToHost));
+            out += sizeof(int32_t) * nnz[j];
+            HIP_TRY(hipMemcpy(out, h->ring_val + sl * h->max_nnz, sizeof(float2) * nnz[j], hipMemcpyDeviceToHost));
+            out += sizeof(float2) * nnz[j];
+        }
+    }
+    return DMD_OK;
+}
+
+DMD_API int dmd_stream_restore(dmd_stream_t* h, const void* buf, int64_t bytes, void* stream) {
+    if (int rc = check_handle(h)) return rc;
+    if (!buf || bytes < (int64_t)sizeof(CkptHeader)) return fail(DMD_E_INVAL, "null or short checkpoint");
+    CkptHeader hd;
+    std::memcpy(&hd, buf, sizeof(hd));
+    if (std::memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 1)
+        return fail(DMD_E_INVAL, "not a checkpoint of this library");
+    if (hd.dtype != h->opts.dtype || hd.n != h->n || hd.m != h->m || hd.r != h->r)
+        return fail(DMD_E_INVAL, "checkpoint of another shape (dtype %d, n %lld, m %d, r %d)", hd.dtype,
+                    (long long)hd.n, hd.m, hd.r);
+    const int cw = h->cplx ? 2 : 1;
+    if (hd.count < 0 || hd.count > h->m + 1 ||
+        hd.gram_bytes != (int64_t)sizeof(double) * cw * hd.count * hd.count || hd.data_bytes < 0 ||
+        bytes < (int64_t)sizeof(CkptHeader) + hd.gram_bytes + hd.data_bytes)
+        return fail(DMD_E_INVAL, "truncated or inconsistent checkpoint");
+    const char* in = static_cast<const char*>(buf) + sizeof(hd);
+    const double* gi = reinterpret_cast<const double*>(in);
+    const char* data = in + hd.gram_bytes;
+    // validate the snapshot part before touching the device
+    std::vector<int32_t> nnz;
+    if (!h->cplx) {
+        if (hd.data_bytes != (int64_t)hd.count * h->n * h->elem_bytes) return fail(DMD_E_INVAL, "inconsistent checkpoint");
+    } else {
+        nnz.assign(reinterpret_cast<const int32_t*>(data), reinterpret_cast<const int32_t*>(data) + hd.count);
+        int64_t b = sizeof(int32_t) * (int64_t)hd.count;
+        for (int j = 0; j < hd.count; ++j) {
+            if (nnz[j] < 0 || nnz[j] > h->max_nnz)
+                return fail(DMD_E_INVAL, "checkpoint snapshot %d has %d nonzeros (max_nnz %d)", j, nnz[j], h->max_nnz);
+            b += (int64_t)nnz[j] * (sizeof(int32_t) + sizeof(float2));
+        }
+        if (b != hd.data_bytes) return fail(DMD_E_INVAL, "inconsistent checkpoint");
+    }
+    DeviceGuard g(h->device);
+    hipStream_t s = as_stream(stream);
+    HIP_TRY(begin(h, s));
+    HIP_TRY(hipStreamSynchronize(s));  // the window is rewritten from host memory below
+    // window snapshot j goes to slot j (oldest = 0); the other slots keep
+    // whatever they hold: they are outside the window
+    if (!h->cplx) {
+        const size_t col = (size_t)h->n * h->elem_bytes;
+        for (int j = 0; j < hd.count; ++j)
+            HIP_TRY(hipMemcpy(static_cast<char*>(h->ring) + (size_t)j * h->ld * h->elem_bytes, data + j * col, col,
+                              hipMemcpyHostToDevice));
+    } else {
+        const char* p = data + sizeof(int32_t) * hd.count;
+        std::vector<int32_t> all(h->slots, 0);
+        for (int j = 0; j < hd.count; ++j) {
+            all[j] = nnz[j];
+            HIP_TRY(hipMemcpy(h->ring_idx + (size_t)j * h->max_nnz, p, sizeof(int32_t) * nnz[j], hipMemcpyHostToDevice));
+            p += sizeof(int32_t) * nnz[j];
+            HIP_TRY(hipMemcpy(h->ring_val + (size_t)j * h->max_nnz, p, sizeof(float2) * nnz[j], hipMemcpyHostToDevice));
+            p += sizeof(float2) * nnz[j];
+        }
+        HIP_TRY(hipMemcpy(h->ring_nnz, all.data(), sizeof(int32_t) * h->slots, hipMemcpyHostToDevice));
+    }
+    std::vector<double> G((size_t)cw * h->slots * h->slots, 0.0);
+    for (int j = 0; j < hd.count; ++j)
+        for (int i = 0; i < hd.count; ++i)
+            for (int c = 0; c < cw; ++c) G[cw * (i + (size_t)j * h->slots) + c] = gi[cw * (i + (size_t)j * hd.count) + c];
+    HIP_TRY(hipMemcpy(h->G, G.data(), sizeof(double) * G.size(), hipMemcpyHostToDevice));
+    DevState st{};
+    st.oldest = 0;
+    st.count = hd.count;
+    st.pushes = hd.pushes;
+    st.solves = hd.solves;
+    st.rejected_nonfinite = hd.rejected_nonfinite;
+    st.rejected_index = hd.rejected_index;
+    st.solve_status = dmd::ST_E_NOT_READY;
+    HIP_TRY(hipMemcpy(h->res_dev, &st, sizeof(st), hipMemcpyHostToDevice));
+    h->reported_nonfinite = hd.rejected_nonfinite;
+    h->reported_index = hd.rejected_index;
+    h->solve_enqueued = false;
+    h->last_block_k = 0;
+    h->last_packed = -1;
+    if (h->opts.auto_solve)
+        if (int rc = enqueue_solve(h, s)) return rc;
+    HIP_TRY(end(h, s));
+    return DMD_OK;
+}
+
 static int project(dmd_stream_t* h, void* out, int64_t ld, void* stream, bool modes) {
     if (int rc = check_handle(h)) return rc;
     if (!out) return fail(DMD_E_INVAL, "null output");
