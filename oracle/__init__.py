@@ -26,6 +26,9 @@ LAPACK routines as the only library steps:
 * :mod:`oracle.background` -- mode amplitudes b = (W Lambda)^-1 alpha_1 and
                             the background/foreground split of the newest
                             snapshot (Sec. 3.3, Algorithm 3).
+* :mod:`oracle.fourier`  -- the spatial -> Fourier ingest of the sparse path
+                            (Sec. 3.5): unitary 2-D DFT and the lowest-|k|
+                            support.
 
 Readings of the paper that this oracle fixes (where the paper is silent):
 the window holds m+1 snapshots (X = first m, X' = last m); rank truncation
@@ -42,9 +45,10 @@ from .dmd import (
 )
 from . import metrics
 from . import background
+from . import fourier
 
 __all__ = [
     "as_fp64", "gram", "mos_svd", "exact_dmd", "StreamingMoS", "DMDResult",
     "canonical_columns", "sort_eigs", "r_effective", "default_rcond", "pod_modes",
-    "dmd_from_gram", "densify", "metrics", "background",
+    "dmd_from_gram", "densify", "metrics", "background", "fourier",
 ]
