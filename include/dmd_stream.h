@@ -189,6 +189,35 @@ int dmd_stream_push(dmd_stream_t* h, const void* x, void* stream);
 int dmd_stream_push_csr(dmd_stream_t* h, int32_t nnz, const int32_t* idx,
                         const void* val, void* stream);
 
+/* Spatial -> Fourier ingest for sparse streams (Sec. 3.5: SVD and DMD are
+ * unchanged by a unitary change of basis, so dense frames may enter the
+ * sparse path as Fourier coefficients).  Setup: h is a DMD_C64_CSR stream
+ * with n = height x width; the support is the nkeep (1 <= nkeep <= max_nnz)
+ * bins of the height x width 2-D DFT with the smallest ky^2 + kx^2, the
+ * wavenumbers signed in FFT order (bin k of N is k for k < (N+1)/2, else
+ * k - N), ties broken by the flattened index ky * width + kx; width <= 16384.
+ * Computes the support and the tables on the host and allocates the
+ * device buffers (a later call replaces them, after waiting for earlier
+ * pushes).  Errors: DMD_E_INVAL (sizes), DMD_E_UNSUPPORTED (dense stream),
+ * DMD_E_NOMEM, DMD_E_DEVICE. */
+int dmd_stream_fourier_setup(dmd_stream_t* h, int32_t height, int32_t width, int32_t nkeep);
+
+/* The support of the Fourier ingest: *nkeep receives its size and, when idx
+ * is not NULL (host, cap >= nkeep entries), idx the flattened indices in
+ * increasing order -- the index order of the coefficients the stream holds
+ * and of the rows of its (dense, n-long) modes.  DMD_E_NOT_READY before
+ * dmd_stream_fourier_setup. */
+int dmd_stream_fourier_support(dmd_stream_t* h, int32_t* idx, int32_t cap, int32_t* nkeep);
+
+/* Push one spatial frame: `frame` is height x width FP32 on the device,
+ * row-major with row stride ld_row >= width elements (4-byte aligned).
+ * Enqueues on `stream` the unitary 2-D DFT at the support points
+ * ((height width)^-1/2 sum_y sum_x x[y][x] e^{-2 pi i (ky y / height + kx x / width)},
+ * FP64 sums, stored as complex64) and then the sparse push of those
+ * coefficients (dmd_stream_push_csr).  Asynchronous.  Errors: DMD_E_NOT_READY
+ * (no setup), DMD_E_INVAL, DMD_E_DEVICE, and those of dmd_stream_push_csr. */
+int dmd_stream_push_fourier(dmd_stream_t* h, const float* frame, int64_t ld_row, void* stream);
+
 /* Append k dense snapshots at once (Sec. 5, updating with more than one new
  * column at a time): X_new is n x k in the stream's dtype (device,
  * column-major, leading dimension ldx >= n), 1 <= k <= opts.max_block.
@@ -419,7 +448,7 @@ int dmd_batch_info(dmd_batch_t* b, int32_t* nstreams, int64_t* used_bytes,
  * When enabled, every kernel launch of every handle is bracketed by HIP events
  * recorded on its launch stream.  Kernel names: "gram_columns", "gram_finalize", "solve_sym",
  * "solve_eig", "project_modes", "project_pod", "background", "csr_gram",
- * "csr_project", "gram_full", for block pushes "gram_block" (block Gram pass, reduction and
+ * "csr_project", "gram_full", "fourier" (the ingest's two DFT kernels), for block pushes "gram_block" (block Gram pass, reduction and
  * commit), "block_solve" (all windows' solves), "pack_block" (packing the
  * projection inputs) and "project_block" (all windows' modes), and for batch ticks
  * "batch_gram", "batch_solve", "batch_project".

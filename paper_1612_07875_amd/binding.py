@@ -80,6 +80,9 @@ SIGNATURES = {
     "dmd_stream_svd": [_P, _DP, _DP, _I64, _I32P],
     "dmd_stream_atilde": [_P, _DP, _I64, _DP, _I64, _I32P],
     "dmd_stream_gram": [_P, _DP, _I64, _I32P],
+    "dmd_stream_fourier_setup": [_P, _I32, _I32, _I32],
+    "dmd_stream_fourier_support": [_P, _I32P, _I32, _I32P],
+    "dmd_stream_push_fourier": [_P, ctypes.c_void_p, _I64, ctypes.c_void_p],
     "dmd_stream_checkpoint_bytes": [_P, ctypes.POINTER(ctypes.c_int64)],
     "dmd_stream_save": [_P, ctypes.c_void_p, _I64],
     "dmd_stream_restore": [_P, ctypes.c_void_p, _I64, ctypes.c_void_p],
@@ -341,6 +344,25 @@ class Stream:
         G = G[:k, : k * cw]
         G = (G[:, 0::2] + 1j * G[:, 1::2]) if cw == 2 else G
         return np.ascontiguousarray(G.T)
+
+    # ---------------------------------------------------------------- Fourier ingest (Sec. 3.5)
+    def fourier_setup(self, height: int, width: int, nkeep: int) -> None:
+        """Sparse streams: ingest height x width spatial frames as their nkeep lowest-|k| DFT coefficients."""
+        check(load().dmd_stream_fourier_setup(self._h, int(height), int(width), int(nkeep)))
+        self.fourier_shape = (int(height), int(width))
+
+    def fourier_support(self) -> np.ndarray:
+        k = ctypes.c_int32(0)
+        check(load().dmd_stream_fourier_support(self._h, None, 0, ctypes.byref(k)))
+        idx = np.zeros(k.value, dtype=np.int32)
+        check(load().dmd_stream_fourier_support(self._h, idx.ctypes.data_as(_I32P), k.value, ctypes.byref(k)))
+        return idx
+
+    def push_fourier(self, frame: torch.Tensor, stream=None) -> int:
+        """frame: (height, width) float32 CUDA tensor (rows may be strided)."""
+        assert frame.is_cuda and frame.dtype == torch.float32 and frame.dim() == 2 and frame.stride(1) == 1
+        return check(load().dmd_stream_push_fourier(self._h, ctypes.c_void_p(frame.data_ptr()),
+                                                   frame.stride(0), _stream_ptr(stream)))
 
     # ---------------------------------------------------------------- checkpoint / resume
     def save(self) -> bytes:

@@ -272,6 +272,28 @@ struct BackgroundArgs {
 };
 hipError_t launch_background(const BackgroundArgs& a, hipStream_t s);
 
+// Spatial -> Fourier ingest (Sec. 3.5): the unitary 2-D DFT of an H x W
+// FP32 frame (row-major, row stride ld_row) at the nkeep support points
+// (ky[c], kx[col[c]]), into val (complex64), through the row transforms R
+// (H x nkx, FP64) at the nkx distinct kx bins.  tw_N[j] = e^{-2 pi i j / N}.
+constexpr int kFourierMaxW = 16384;  // the row is staged in LDS
+struct FourierArgs {
+    const float* frame;
+    int64_t ld_row;
+    int H, W;
+    const int* kx;         // nkx distinct kx bins
+    int nkx;
+    const int* ky;         // ky bin of each kept coefficient
+    const int* col;        // index into kx of each kept coefficient
+    int nkeep;
+    const double2* twW;    // W roots of unity
+    const double2* twH;    // H roots of unity
+    double2* R;            // H x nkx scratch
+    float2* val;           // nkeep coefficients
+    double scale;          // (H W)^-1/2
+};
+hipError_t launch_fourier(const FourierArgs& a, hipStream_t s);
+
 // Sparse projection: out = X_sub * B (complex) into a dense n x r_eff
 // complex64 output (zero outside the window's support).
 hipError_t launch_csr_project(const DevState* st, const int32_t* ring_idx,

@@ -1,6 +1,8 @@
 // C-ABI runtime of libdmdstream: stream handles, device memory, argument
 // checks and the ordering of kernels for one frame.  See include/dmd_stream.h
 // for the contract of every entry point.
+#include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -157,6 +159,17 @@ struct dmd_stream {
     bool proj_pending[2] = {false, false};
     int64_t block_seq = 0;        // block pushes so far
     int last_packed = -1;         // parity packed by the latest push, -1 if none
+    // Spatial -> Fourier ingest (sparse streams): grid, support and tables
+    int four_H = 0, four_W = 0, four_nkeep = 0, four_nkx = 0;
+    int32_t* f_idx = nullptr;     // flattened support indices, increasing
+    int32_t* f_ky = nullptr;      // ky bin per support point
+    int32_t* f_col = nullptr;     // column of R per support point
+    int32_t* f_kx = nullptr;      // distinct kx bins
+    double2* f_twW = nullptr;
+    double2* f_twH = nullptr;
+    double2* f_R = nullptr;
+    float2* f_val = nullptr;
+    std::vector<int32_t> four_support;  // host copy of f_idx
     dmd::SolveArgs* solve_tbl = nullptr;  // device: sets 0 .. kmax-2, then the current window
     int32_t last_block_k = 0;     // k of the latest push if it was a solved block push, else 0
 
@@ -222,7 +235,8 @@ void free_all(dmd_stream* h) {
     void* bufs[] = {h->ring, h->ring_idx, h->ring_val, h->ring_nnz, h->scatter, h->flag, h->G, h->partials,
                     h->res_dev, h->V, h->At, h->W, h->work, h->Vfull, h->gfull, h->Bphi, h->Bpod,
                     h->Bbg, h->bpartial, h->gblock, h->bflag, h->sh_dev, h->sh_V, h->sh_At, h->sh_W, h->sh_work,
-                    h->sh_Vfull, h->sh_Bphi, h->sh_Bpod, h->cfrag, h->bdesc, h->solve_tbl};
+                    h->sh_Vfull, h->sh_Bphi, h->sh_Bpod, h->cfrag, h->bdesc, h->solve_tbl,
+                    h->f_idx, h->f_ky, h->f_col, h->f_kx, h->f_twW, h->f_twH, h->f_R, h->f_val};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (h->res_host) (void)hipHostFree(h->res_host);
@@ -918,6 +932,137 @@ DMD_API int dmd_stream_gram(dmd_stream_t* h, double* G, int64_t ldg, int32_t* nc
         }
     delete[] tmp;
     return DMD_OK;
+}
+
+// ------------------------------------------------------------ spatial -> Fourier ingest (Sec. 3.5)
+
+namespace {
+// Bin k of N as a signed wavenumber (FFT order: 0, 1, ..., then negatives).
+int signed_bin(int k, int N) { return k < (N + 1) / 2 ? k : k - N; }
+
+void free_fourier(dmd_stream* h) {
+    void* bufs[] = {h->f_idx, h->f_ky, h->f_col, h->f_kx, h->f_twW, h->f_twH, h->f_R, h->f_val};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    h->f_idx = h->f_ky = h->f_col = h->f_kx = nullptr;
+    h->f_twW = h->f_twH = h->f_R = nullptr;
+    h->f_val = nullptr;
+    h->four_H = h->four_W = h->four_nkeep = h->four_nkx = 0;
+    h->four_support.clear();
+}
+
+std::vector<double2> roots_of_unity(int N) {
+    std::vector<double2> w(N);
+    for (int j = 0; j < N; ++j) {
+        const double t = 2.0 * 3.14159265358979323846 * (double)j / (double)N;
+        w[j] = double2{std::cos(t), -std::sin(t)};
+    }
+    return w;
+}
+
+template <typename T>
+int upload(dmd_stream* h, T** dst, const std::vector<T>& src) {
+    if (int rc = dev_alloc(h, dst, sizeof(T) * src.size())) return rc;
+    HIP_TRY(hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice));
+    return DMD_OK;
+}
+}  // namespace
+
+DMD_API int dmd_stream_fourier_setup(dmd_stream_t* h, int32_t height, int32_t width, int32_t nkeep) {
+    if (int rc = check_handle(h)) return rc;
+    if (!h->cplx) return fail(DMD_E_UNSUPPORTED, "the Fourier ingest feeds sparse (DMD_C64_CSR) streams");
+    if (height < 1 || width < 1 || (int64_t)height * width != h->n)
+        return fail(DMD_E_INVAL, "height x width must equal n = %lld", (long long)h->n);
+    if (width > dmd::kFourierMaxW) return fail(DMD_E_INVAL, "width must be <= %d", dmd::kFourierMaxW);
+    if (nkeep < 1 || nkeep > h->max_nnz) return fail(DMD_E_INVAL, "nkeep must be in [1, max_nnz=%d]", h->max_nnz);
+    DeviceGuard g(h->device);
+    if (h->has_last) HIP_TRY(hipEventSynchronize(h->ev_last));  // buffers may be in use by earlier pushes
+    free_fourier(h);
+    // the nkeep bins of smallest ky^2 + kx^2 (signed), ties by flattened index
+    const int64_t n = h->n;
+    std::vector<std::pair<int64_t, int32_t>> key((size_t)n);
+    for (int y = 0; y < height; ++y) {
+        const int64_t ky = signed_bin(y, height);
+        for (int x = 0; x < width; ++x) {
+            const int64_t kx = signed_bin(x, width);
+            const int32_t i = y * width + x;
+            key[(size_t)i] = {ky * ky + kx * kx, i};
+        }
+    }
+    std::nth_element(key.begin(), key.begin() + (nkeep - 1), key.end());
+    std::vector<int32_t> idx(nkeep);
+    for (int c = 0; c < nkeep; ++c) idx[c] = key[(size_t)c].second;
+    // nth_element leaves the nkeep smallest (k^2, index) pairs first, in any order
+    std::sort(idx.begin(), idx.end());
+    std::vector<int32_t> kxs;
+    for (int32_t i : idx) kxs.push_back(i % width);
+    std::sort(kxs.begin(), kxs.end());
+    kxs.erase(std::unique(kxs.begin(), kxs.end()), kxs.end());
+    std::vector<int32_t> ky(nkeep), col(nkeep);
+    for (int c = 0; c < nkeep; ++c) {
+        ky[c] = idx[c] / width;
+        col[c] = (int32_t)(std::lower_bound(kxs.begin(), kxs.end(), idx[c] % width) - kxs.begin());
+    }
+    int rc = DMD_OK;
+    if (!rc) rc = upload(h, &h->f_idx, idx);
+    if (!rc) rc = upload(h, &h->f_ky, ky);
+    if (!rc) rc = upload(h, &h->f_col, col);
+    if (!rc) rc = upload(h, &h->f_kx, kxs);
+    if (!rc) rc = upload(h, &h->f_twW, roots_of_unity(width));
+    if (!rc) rc = upload(h, &h->f_twH, roots_of_unity(height));
+    if (!rc) rc = dev_alloc(h, &h->f_R, sizeof(double2) * (size_t)height * kxs.size());
+    if (!rc) rc = dev_alloc(h, &h->f_val, sizeof(float2) * (size_t)nkeep);
+    if (rc) {
+        free_fourier(h);
+        return rc;
+    }
+    h->four_H = height;
+    h->four_W = width;
+    h->four_nkeep = nkeep;
+    h->four_nkx = (int)kxs.size();
+    h->four_support = idx;
+    return DMD_OK;
+}
+
+DMD_API int dmd_stream_fourier_support(dmd_stream_t* h, int32_t* idx, int32_t cap, int32_t* nkeep) {
+    if (int rc = check_handle(h)) return rc;
+    if (!nkeep) return fail(DMD_E_INVAL, "null nkeep");
+    if (h->four_nkeep == 0) return fail(DMD_E_NOT_READY, "no Fourier ingest set up");
+    *nkeep = h->four_nkeep;
+    if (idx) {
+        if (cap < h->four_nkeep) return fail(DMD_E_INVAL, "cap < nkeep (%d)", h->four_nkeep);
+        std::memcpy(idx, h->four_support.data(), sizeof(int32_t) * h->four_nkeep);
+    }
+    return DMD_OK;
+}
+
+DMD_API int dmd_stream_push_fourier(dmd_stream_t* h, const float* frame, int64_t ld_row, void* stream) {
+    if (int rc = check_handle(h)) return rc;
+    if (h->four_nkeep == 0) return fail(DMD_E_NOT_READY, "no Fourier ingest set up (dmd_stream_fourier_setup)");
+    if (!frame) return fail(DMD_E_INVAL, "null frame");
+    if (ld_row < h->four_W) return fail(DMD_E_INVAL, "ld_row < width");
+    if ((uintptr_t)frame % 4) return fail(DMD_E_INVAL, "frame not 4-byte aligned");
+    DeviceGuard g(h->device);
+    hipStream_t s = as_stream(stream);
+    HIP_TRY(begin(h, s));
+    dmd::FourierArgs a{};
+    a.frame = frame;
+    a.ld_row = ld_row;
+    a.H = h->four_H;
+    a.W = h->four_W;
+    a.kx = h->f_kx;
+    a.nkx = h->four_nkx;
+    a.ky = h->f_ky;
+    a.col = h->f_col;
+    a.nkeep = h->four_nkeep;
+    a.twW = h->f_twW;
+    a.twH = h->f_twH;
+    a.R = h->f_R;
+    a.val = h->f_val;
+    a.scale = 1.0 / std::sqrt((double)h->n);
+    HIP_TRY(timed("fourier", s, [&] { return dmd::launch_fourier(a, s); }));
+    HIP_TRY(end(h, s));
+    return dmd_stream_push_csr(h, h->four_nkeep, h->f_idx, h->f_val, stream);
 }
 
 // ------------------------------------------------------------ checkpoint / resume
