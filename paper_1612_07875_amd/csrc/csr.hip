@@ -167,8 +167,10 @@ __global__ __launch_bounds__(kThreads)
 void k_csr_project(const DevState* __restrict__ st, const int32_t* __restrict__ ring_idx,
                    const float2* __restrict__ ring_val, const int32_t* __restrict__ ring_nnz, int max_nnz, int m,
                    int first, const float2* __restrict__ B, int kmax, float2* __restrict__ out, int64_t ldo,
-                   int64_t n) {
-    if (st->solve_status == ST_E_NOT_READY) return;
+                   int64_t n, const int* __restrict__ overflow) {
+    // fallback, used only when the window's union of supports exceeds the
+    // dense block's capacity: one workgroup per output column
+    if (st->solve_status == ST_E_NOT_READY || !*overflow) return;
     const int q = blockIdx.x;
     if (q >= st->r_eff) return;
     const int slots = m + 2;
@@ -193,6 +195,124 @@ void k_csr_project(const DevState* __restrict__ st, const int32_t* __restrict__ 
     }
 }
 
+// ---- projection through the union of the window's supports
+//
+// Every index that occurs in a window column gets a row u of a dense block
+// D (u x m, complex64; row order is immaterial, so the rows are handed out by
+// an atomic counter); D holds the window on its union U, zero elsewhere, so
+// out[U[u]][q] = sum_j D[u][j] B[j][q] is a small dense product, summed in
+// column order j = 0 .. m-1 exactly as a column-by-column scatter would (a
+// missing entry adds an exact zero).  Outside U the output is zero.
+struct UnionArgs {
+    const DevState* st;
+    const int32_t* ring_idx;
+    const float2* ring_val;
+    const int32_t* ring_nnz;
+    int max_nnz, m, first;
+    int32_t* pos;     // n entries, -1 outside U (restored after use)
+    int32_t* U;       // cap entries
+    int* ucount;      // |U|
+    int* overflow;    // |U| > cap: the fallback kernel runs instead
+    int cap;
+    float2* D;        // cap x m
+};
+
+__global__ __launch_bounds__(64)
+void k_union_reset(UnionArgs a) {
+    if (threadIdx.x == 0) {
+        *a.ucount = 0;
+        *a.overflow = 0;
+    }
+}
+
+// one pass over the window's entries: first occurrence of an index claims a row
+__global__ __launch_bounds__(kThreads)
+void k_union_mark(UnionArgs a) {
+    const DevState* st = a.st;
+    if (st->solve_status == ST_E_NOT_READY) return;
+    const int slots = a.m + 2;
+    const int j = blockIdx.y;
+    const int slot = slot_of(st->oldest, a.first + j, slots);
+    const int nz = a.ring_nnz[slot];
+    const int64_t base = (int64_t)slot * a.max_nnz;
+    for (int e = blockIdx.x * kThreads + threadIdx.x; e < nz; e += gridDim.x * kThreads) {
+        const int32_t i = a.ring_idx[base + e];
+        if (atomicCAS(&a.pos[i], -1, INT32_MAX) == -1) {
+            const int u = atomicAdd(a.ucount, 1);
+            if (u < a.cap) a.U[u] = i;
+            else atomicOr(a.overflow, 1);
+            a.pos[i] = u;  // read only by later kernels
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads)
+void k_union_zero(UnionArgs a) {
+    if (a.st->solve_status == ST_E_NOT_READY || *a.overflow) return;
+    const int64_t total = (int64_t)*a.ucount * a.m;
+    for (int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x; k < total; k += (int64_t)gridDim.x * kThreads)
+        a.D[k] = float2{0.0f, 0.0f};
+}
+
+__global__ __launch_bounds__(kThreads)
+void k_union_gather(UnionArgs a) {
+    const DevState* st = a.st;
+    if (st->solve_status == ST_E_NOT_READY || *a.overflow) return;
+    const int slots = a.m + 2;
+    const int j = blockIdx.y;
+    const int slot = slot_of(st->oldest, a.first + j, slots);
+    const int nz = a.ring_nnz[slot];
+    const int64_t base = (int64_t)slot * a.max_nnz;
+    for (int e = blockIdx.x * kThreads + threadIdx.x; e < nz; e += gridDim.x * kThreads)
+        a.D[(int64_t)a.pos[a.ring_idx[base + e]] * a.m + j] = a.ring_val[base + e];
+}
+
+// zero the n x r_eff output (16-byte stores where aligned)
+__global__ __launch_bounds__(kThreads)
+void k_union_clear_out(UnionArgs a, float2* __restrict__ out, int64_t ldo, int64_t n) {
+    const DevState* st = a.st;
+    if (st->solve_status == ST_E_NOT_READY || *a.overflow) return;
+    const int q = blockIdx.y;
+    if (q >= st->r_eff) return;
+    float2* col = out + (int64_t)q * ldo;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+        col[i] = float2{0.0f, 0.0f};
+}
+
+__global__ __launch_bounds__(kThreads)
+void k_union_product(UnionArgs a, const float2* __restrict__ B, int kmax, float2* __restrict__ out, int64_t ldo) {
+    const DevState* st = a.st;
+    if (st->solve_status == ST_E_NOT_READY || *a.overflow) return;
+    const int q = blockIdx.y;
+    if (q >= st->r_eff) return;
+    const int nu = *a.ucount;
+    for (int u = blockIdx.x * kThreads + threadIdx.x; u < nu; u += gridDim.x * kThreads) {
+        const float2* d = a.D + (int64_t)u * a.m;
+        float2 o{0.0f, 0.0f};
+        for (int j = 0; j < a.m; ++j) {
+            const float2 v = d[j];
+            const float2 c = B[(int64_t)j * kmax + q];
+            o.x = fmaf(v.x, c.x, fmaf(-v.y, c.y, o.x));
+            o.y = fmaf(v.x, c.y, fmaf(v.y, c.x, o.y));
+        }
+        out[a.U[u] + (int64_t)q * ldo] = o;
+    }
+}
+
+// give the index map back its -1s (the whole map after an overflow, when
+// rows past the capacity were not recorded in U)
+__global__ __launch_bounds__(kThreads)
+void k_union_restore(UnionArgs a, int64_t n) {
+    if (a.st->solve_status == ST_E_NOT_READY) return;
+    if (*a.overflow) {
+        for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+            a.pos[i] = -1;
+        return;
+    }
+    const int nu = *a.ucount;
+    for (int u = blockIdx.x * kThreads + threadIdx.x; u < nu; u += gridDim.x * kThreads) a.pos[a.U[u]] = -1;
+}
+
 }  // namespace
 
 hipError_t launch_csr_push(const int32_t* idx, const float2* val, int nnz, int64_t n, int32_t* ring_idx,
@@ -215,11 +335,29 @@ hipError_t launch_csr_push(const int32_t* idx, const float2* val, int nnz, int64
 
 int csr_partials_per_column() { return kChunks; }
 
+int csr_union_cap(int64_t n, int max_nnz) {
+    const int64_t c = 4 * (int64_t)max_nnz;
+    return (int)(c < n ? c : n);
+}
+
 hipError_t launch_csr_project(const DevState* st, const int32_t* ring_idx, const float2* ring_val,
                               const int32_t* ring_nnz, int max_nnz, int m, int first, const float2* B, int kmax,
-                              float2* out, int64_t ldo, int64_t n, hipStream_t s) {
+                              float2* out, int64_t ldo, int64_t n, const CsrUnionScratch& u, hipStream_t s) {
+    UnionArgs a{st, ring_idx, ring_val, ring_nnz, max_nnz, m, first, u.pos, u.U, u.ucount, u.overflow, u.cap, u.D};
+    const unsigned ge = (unsigned)((max_nnz + kThreads - 1) / kThreads);
+    const unsigned gz = (unsigned)(((int64_t)u.cap * m + kThreads - 1) / kThreads);
+    const unsigned gu = (unsigned)((u.cap + kThreads - 1) / kThreads);
+    const int64_t gn = (n + kThreads - 1) / kThreads;
+    const unsigned go = (unsigned)(gn < 4096 ? gn : 4096);
+    hipLaunchKernelGGL(k_union_reset, dim3(1), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_union_mark, dim3(ge, m), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(k_union_zero, dim3(gz < 4096 ? gz : 4096), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(k_union_gather, dim3(ge, m), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(k_union_clear_out, dim3(go, kmax), dim3(kThreads), 0, s, a, out, ldo, n);
+    hipLaunchKernelGGL(k_union_product, dim3(gu, kmax), dim3(kThreads), 0, s, a, B, kmax, out, ldo);
     hipLaunchKernelGGL(k_csr_project, dim3(kmax), dim3(kThreads), 0, s, st, ring_idx, ring_val, ring_nnz, max_nnz, m,
-                       first, B, kmax, out, ldo, n);
+                       first, B, kmax, out, ldo, n, u.overflow);
+    hipLaunchKernelGGL(k_union_restore, dim3(go), dim3(kThreads), 0, s, a, n);
     return hipGetLastError();
 }
 

@@ -296,10 +296,21 @@ hipError_t launch_fourier(const FourierArgs& a, hipStream_t s);
 
 // Sparse projection: out = X_sub * B (complex) into a dense n x r_eff
 // complex64 output (zero outside the window's support).
-hipError_t launch_csr_project(const DevState* st, const int32_t* ring_idx,
-                              const float2* ring_val, const int32_t* ring_nnz,
-                              int max_nnz, int m, int first, const float2* B, int kmax,
-                              float2* out, int64_t ldo, int64_t n, hipStream_t s);
+// Scratch of the sparse projection: the index map pos (n entries, all -1
+// between calls), the union list U and the dense block D (cap x m) of the
+// window on its union; cap = csr_union_cap(n, max_nnz).
+struct CsrUnionScratch {
+    int32_t* pos;
+    int32_t* U;
+    int* ucount;
+    int* overflow;
+    int cap;
+    float2* D;
+};
+int csr_union_cap(int64_t n, int max_nnz);
+hipError_t launch_csr_project(const DevState* st, const int32_t* ring_idx, const float2* ring_val,
+                              const int32_t* ring_nnz, int max_nnz, int m, int first, const float2* B, int kmax,
+                              float2* out, int64_t ldo, int64_t n, const CsrUnionScratch& u, hipStream_t s);
 
 // Whole Gram of the window's first kcols columns on the matrix cores (FP64,
 // FP32 or BF16x3 products), split over rows with a fixed-order FP64 sum.

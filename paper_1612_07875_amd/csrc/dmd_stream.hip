@@ -108,6 +108,11 @@ struct dmd_stream {
     float2* ring_val = nullptr;   // sparse: slots x max_nnz values
     int32_t* ring_nnz = nullptr;  // sparse: slots counts
     float2* scatter = nullptr;    // sparse: n dense scratch (kept zero)
+    int32_t* upos = nullptr;      // sparse projection: index -> union row (-1 outside)
+    int32_t* ulist = nullptr;     // union rows -> index
+    int* ucount = nullptr;        // |U| and the overflow flag
+    float2* ublock = nullptr;     // window on its union, ucap x m
+    int ucap = 0;
     int* flag = nullptr;          // sparse: bad-index flag of the push in flight
     int max_nnz = 0;
 
@@ -236,7 +241,8 @@ void free_all(dmd_stream* h) {
                     h->res_dev, h->V, h->At, h->W, h->work, h->Vfull, h->gfull, h->Bphi, h->Bpod,
                     h->Bbg, h->bpartial, h->gblock, h->bflag, h->sh_dev, h->sh_V, h->sh_At, h->sh_W, h->sh_work,
                     h->sh_Vfull, h->sh_Bphi, h->sh_Bpod, h->cfrag, h->bdesc, h->solve_tbl,
-                    h->f_idx, h->f_ky, h->f_col, h->f_kx, h->f_twW, h->f_twH, h->f_R, h->f_val};
+                    h->f_idx, h->f_ky, h->f_col, h->f_kx, h->f_twW, h->f_twH, h->f_R, h->f_val,
+                    h->upos, h->ulist, h->ucount, h->ublock};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (h->res_host) (void)hipHostFree(h->res_host);
@@ -491,6 +497,14 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
         ALLOC(h->ring_nnz, sizeof(int32_t) * (size_t)h->slots);
         ALLOC(h->scatter, sizeof(float2) * (size_t)n);
         ALLOC(h->flag, sizeof(int));
+        // projection through the union of the window's supports
+        h->ucap = dmd::csr_union_cap(n, h->max_nnz);
+        ALLOC(h->upos, sizeof(int32_t) * (size_t)n);
+        ALLOC(h->ulist, sizeof(int32_t) * (size_t)h->ucap);
+        ALLOC(h->ucount, 2 * sizeof(int));
+        ALLOC(h->ublock, sizeof(float2) * (size_t)h->ucap * m);
+        if (rc == DMD_OK && hipMemset(h->upos, 0xFF, sizeof(int32_t) * (size_t)n) != hipSuccess)
+            rc = fail(DMD_E_DEVICE, "hipMemset(index map)");
     } else {
         ALLOC(h->ring, (size_t)h->slots * h->ld * h->elem_bytes);
         ALLOC(h->gfull, sizeof(double) * 64 * 64 * (size_t)dmd::gram_full_tiles(m) * dmd::gram_full_splits(m));
@@ -1274,7 +1288,10 @@ static int project(dmd_stream_t* h, void* out, int64_t ld, void* stream, bool mo
             return dmd::launch_csr_project(reinterpret_cast<const DevState*>(h->res_dev), h->ring_idx, h->ring_val,
                                            h->ring_nnz, h->max_nnz, h->m, modes ? 1 : 0,
                                            static_cast<const float2*>(modes ? h->Bphi : h->Bpod), h->r,
-                                           static_cast<float2*>(out), ld, h->n, s);
+                                           static_cast<float2*>(out), ld, h->n,
+                                           dmd::CsrUnionScratch{h->upos, h->ulist, h->ucount, h->ucount + 1,
+                                                                h->ucap, h->ublock},
+                                           s);
         }));
         HIP_TRY(end(h, s));
         return DMD_OK;
