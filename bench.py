@@ -202,6 +202,8 @@ def serve_bench(args):
     burst = sorted((0.0, s.stream) for s in mix for _ in range(sat_frames))
     sat = srv.run(burst)
     ex_gpu.shutdown()
+    torch.cuda.synchronize()
+    modes_cmp = None if args.no_split else modes_saturation(mix, frames, GPUExecutor, Server, StreamSpec)
     footprint = sum((s.m + 2) * s.n * 4 for s in mix)
     out = {
         "metric": "DMD window updates/s + Gram HBM GB/s vs roofline; p99 frame latency",
@@ -213,14 +215,67 @@ def serve_bench(args):
         "config": {"workload": f"serving mix: {len(mix)} streams, n log-uniform in [65536, 2097152], "
                                f"m in {{16,32,64,128}}, r = min(m/2, 32), blob video / travelling waves; "
                                f"Poisson arrivals {args.serve_rate:.0f} frames/s for {args.serve_seconds:.0f} s; "
-                               f"each update = Gram column + FP64 solves (no modes)",
+                               f"each update = Gram column + FP64 solves (no modes; modes_saturation "
+                               f"adds them)",
                    "streams": len(mix), "ring_bytes": footprint},
         "latency_ms": {"p50": round(st.p50_ms, 3), "p99": round(st.p99_ms, 3), "max": round(st.max_ms, 3)},
         "mean_batch": round(st.mean_batch, 2), "ticks": st.ticks,
         "saturation": {"updates_per_s": round(sat.updates_per_s, 1), "frames": sat.frames,
                        "mean_batch": round(sat.mean_batch, 2), "p99_ms": round(sat.p99_ms, 2)},
     }
+    if modes_cmp is not None:
+        out["modes_saturation"] = modes_cmp
     print(json.dumps(out), flush=True)
+
+
+def modes_saturation(mix, frames, GPUExecutor, Server, StreamSpec, sat_frames=6):
+    """Every stream backlogged, every update with its modes: plain per-stream
+    FP32 (one stream after another, no batching) against batched ticks with
+    FP32 and with split-BF16 projections."""
+    import torch
+
+    import paper_1612_07875_amd as dmd
+
+    res = {}
+    # plain per-stream FP32: each stream on its own, push + modes per frame
+    streams = {s.stream: dmd.Stream(s.n, s.m, s.r) for s in mix}
+    outs = {s.stream: torch.zeros((s.r, s.n), dtype=torch.complex64, device="cuda").T for s in mix}
+    for s in mix:
+        X = frames[s.stream]
+        for t in range(s.m + 1):
+            streams[s.stream].push(X[t % X.shape[0]])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for f in range(sat_frames):
+        for s in mix:
+            X = frames[s.stream]
+            h = streams[s.stream]
+            h.push(X[(s.m + 1 + f) % X.shape[0]])
+            h.modes(outs[s.stream])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    res["per_stream_fp32"] = round(sat_frames * len(mix) / el, 1)
+    for h in streams.values():
+        h.close()
+    del outs
+    torch.cuda.synchronize()
+    for prec, key in (("default", "batched_fp32"), ("bf16x3", "batched_bf16x3")):
+        ex = GPUExecutor(frames, modes=True)
+        srv = Server(ex)
+        for s in mix:
+            srv.open(s.stream, StreamSpec(s.n, s.m, s.r, precision=prec))
+        srv.run(sorted((0.0, s.stream) for s in mix for _ in range(s.m + 1)))
+        srv.records.clear()
+        srv.batch_sizes.clear()
+        srv.ticks = 0
+        st = srv.run(sorted((0.0, s.stream) for s in mix for _ in range(sat_frames)))
+        res[key] = round(st.updates_per_s, 1)
+        ex.shutdown()
+        torch.cuda.synchronize()
+    print(f"[serve] modes at saturation: {res}", file=sys.stderr, flush=True)
+    res["note"] = ("every stream backlogged, each update with its DMD modes; per_stream_fp32 runs the "
+                   "streams one after another without batching")
+    return res
 
 
 def make_frames(T, keep):

@@ -30,6 +30,7 @@ class StreamSpec:
     n: int
     m: int
     r: int
+    precision: str = "default"   # projections: "default" (FP32), "bf16x3", ...
 
 
 @dataclass
@@ -175,9 +176,12 @@ class Server:
 
 class GPUExecutor:
     """Executor backed by libdmdstream: one Stream per sid in one Batch.
-    Frame `index` of stream `sid` is read from frames[sid][index % len]."""
+    Frame `index` of stream `sid` is read from frames[sid][index % len].
+    With modes=True every update also projects the window's DMD modes into a
+    resident per-stream buffer (in the stream's precision)."""
 
-    def __init__(self, frames: Dict[int, "object"], hbm_budget: int = 0, max_streams: int = 1024):
+    def __init__(self, frames: Dict[int, "object"], hbm_budget: int = 0, max_streams: int = 1024,
+                 modes: bool = False):
         import torch
         from .binding import Batch, DMDError, Stream, E_NOMEM
         self.torch = torch
@@ -187,9 +191,11 @@ class GPUExecutor:
         self.frames = frames
         self.batch = Batch(max_streams=max_streams, hbm_budget=hbm_budget)
         self.streams = {}
+        self.want_modes = modes
+        self.modes = {}
 
     def open(self, sid, spec) -> bool:
-        s = self.Stream(spec.n, spec.m, spec.r)
+        s = self.Stream(spec.n, spec.m, spec.r, precision=spec.precision)
         try:
             self.batch.attach(s)
         except self.DMDError as e:
@@ -198,17 +204,23 @@ class GPUExecutor:
                 return False
             raise
         self.streams[sid] = s
+        if self.want_modes:
+            self.modes[sid] = self.torch.zeros((spec.r, spec.n), dtype=s.mode_dtype, device="cuda").T
         return True
 
     def close(self, sid) -> None:
         s = self.streams.pop(sid)
+        self.modes.pop(sid, None)
         self.batch.detach(s)
         s.close()
 
     def tick(self, items):
         ss = [self.streams[sid] for sid, _ in items]
         xs = [self.frames[sid][idx % self.frames[sid].shape[0]] for sid, idx in items]
-        self.batch.tick(ss, xs)
+        if self.want_modes:
+            self.batch.tick(ss, xs, modes=[self.modes[sid] for sid, _ in items])
+        else:
+            self.batch.tick(ss, xs)
         ev = self.torch.cuda.Event()
         ev.record()
         return ev
