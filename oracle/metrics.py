@@ -15,6 +15,8 @@ def match_eigs(lam_hat, lam) -> np.ndarray:
     """perm such that lam_hat[i] pairs with lam[perm[i]] (min total |difference|)."""
     lam_hat = np.asarray(lam_hat)
     lam = np.asarray(lam)
+    if lam_hat.size > lam.size:
+        raise ValueError(f"cannot match {lam_hat.size} eigenvalues to {lam.size}")
     cost = np.abs(lam_hat[:, None] - lam[None, :])
     row, col = linear_sum_assignment(cost)
     perm = np.empty(lam_hat.size, dtype=np.int64)
