@@ -543,6 +543,165 @@ void k_solve_sym_grouped(const SolveArgs* __restrict__ items) {
 // --------------------------------------------------------------------------
 constexpr int LDH = kRMax;
 
+
+// Real Schur form of the real upper Hessenberg k x k matrix held in the real
+// parts of H (imaginary parts zero), one wavefront: implicit double-shift
+// (Francis) QR -- each sweep chases a 3 x 3 Householder bulge started from
+// the first column of (H - mu1)(H - mu2), mu1,2 the eigenvalues of the
+// trailing 2 x 2 block (an exceptional pair every 10th sweep), so that a
+// complex-conjugate pair converges together in real arithmetic; Z (complex
+// storage, real values) accumulates the transformations.  The 2 x 2 blocks
+// left on the diagonal are then triangularized by one complex rotation each,
+// so that H becomes the complex upper triangular T of the complex Schur form.
+__device__ void real_schur(cplx* H, cplx* Z, int k, int lane, int max_iter, double hmax, int& total, bool& failed) {
+    auto h = [&](int i, int j) -> double& { return H[i + j * LDH].re; };
+    int nn = k - 1, its = 0;
+    while (nn >= 0) {
+        // deflation: largest l in [1, nn] with a negligible subdiagonal
+        bool small = false;
+        if (lane >= 1 && lane <= nn) {
+            const double sub = fabs(h(lane, lane - 1));
+            double scale = fabs(h(lane, lane)) + fabs(h(lane - 1, lane - 1));
+            if (scale == 0.0) scale = hmax;
+            small = sub <= kEps * scale;
+        }
+        const unsigned long long mask = __ballot(small);
+        const int l = mask ? 63 - __clzll(mask) : 0;
+        __syncthreads();
+        if (l > 0 && lane == 0) h(l, l - 1) = 0.0;
+        __syncthreads();
+        if (l >= nn - 1) {  // a 1 x 1 or 2 x 2 block splits off
+            nn = l - 1;
+            its = 0;
+            continue;
+        }
+        if (its >= max_iter) {
+            failed = true;
+            break;
+        }
+        ++its;
+        ++total;
+        // shift pair by its sum s and product t
+        double s, t;
+        {
+            const double a11 = h(nn - 1, nn - 1), a12 = h(nn - 1, nn), a21 = h(nn, nn - 1), a22 = h(nn, nn);
+            if (its % 10 == 0) {
+                const double e = fabs(a21) + fabs(h(nn - 1, nn - 2));
+                const double mu = a22 + 0.75 * e;
+                s = 2.0 * mu;
+                t = mu * mu + 0.4375 * e * e;
+            } else {
+                s = a11 + a22;
+                t = a11 * a22 - a12 * a21;
+            }
+        }
+        for (int kk = l; kk < nn; ++kk) {
+            double x, y, z;
+            if (kk == l) {
+                const double h00 = h(l, l), h10 = h(l + 1, l);
+                x = h00 * h00 + h(l, l + 1) * h10 - s * h00 + t;
+                y = h10 * (h00 + h(l + 1, l + 1) - s);
+                z = h10 * h(l + 2, l + 1);
+            } else {
+                x = h(kk, kk - 1);
+                y = h(kk + 1, kk - 1);
+                z = kk + 2 <= nn ? h(kk + 2, kk - 1) : 0.0;
+            }
+            const bool three = kk + 2 <= nn;
+            const double nrm = sqrt(x * x + y * y + z * z);
+            // reflector P = I - tau v v^T, v = (x - alpha, y, z), P (x, y, z) = (alpha, 0, 0)
+            const double alpha = x > 0.0 ? -nrm : nrm;
+            const double v0 = x - alpha;
+            const double vtv = v0 * v0 + y * y + z * z;
+            const double tau = vtv > 0.0 ? 2.0 / vtv : 0.0;
+            __syncthreads();
+            if (tau != 0.0) {
+                // rows kk .. kk+2 over columns jlo .. k-1 (lane = column)
+                const int jlo = kk > l ? kk - 1 : l;
+                const int j = lane;
+                if (j >= jlo && j < k) {
+                    const double r0 = h(kk, j), r1 = h(kk + 1, j), r2 = three ? h(kk + 2, j) : 0.0;
+                    const double f = tau * (v0 * r0 + y * r1 + z * r2);
+                    h(kk, j) = r0 - f * v0;
+                    h(kk + 1, j) = r1 - f * y;
+                    if (three) h(kk + 2, j) = r2 - f * z;
+                }
+            }
+            __syncthreads();
+            if (tau != 0.0) {
+                if (kk > l && lane == 0) {
+                    h(kk + 1, kk - 1) = 0.0;
+                    if (three) h(kk + 2, kk - 1) = 0.0;
+                }
+                // columns kk .. kk+2 over rows 0 .. min(kk+3, nn); Z over all rows (lane = row)
+                const int i = lane;
+                const int ihi = kk + 3 < nn ? kk + 3 : nn;
+                if (i <= ihi) {
+                    const double c0 = h(i, kk), c1 = h(i, kk + 1), c2 = three ? h(i, kk + 2) : 0.0;
+                    const double f = tau * (c0 * v0 + c1 * y + c2 * z);
+                    h(i, kk) = c0 - f * v0;
+                    h(i, kk + 1) = c1 - f * y;
+                    if (three) h(i, kk + 2) = c2 - f * z;
+                }
+                if (i < k) {
+                    double& z0 = Z[i + kk * LDH].re;
+                    double& z1 = Z[i + (kk + 1) * LDH].re;
+                    const double c0 = z0, c1 = z1, c2 = three ? Z[i + (kk + 2) * LDH].re : 0.0;
+                    const double f = tau * (c0 * v0 + c1 * y + c2 * z);
+                    z0 = c0 - f * v0;
+                    z1 = c1 - f * y;
+                    if (three) Z[i + (kk + 2) * LDH].re = c2 - f * z;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    // triangularize each 2 x 2 diagonal block [[a, b], [c, d]], c != 0: with
+    // u = (lambda_1 - d, c) / ||.||, lambda_1 an eigenvalue of the block, the
+    // rotation G = [[u0, -conj(u1)], [u1, conj(u0)]] gives G^* B G = [[lambda_1, .], [0, lambda_2]]
+    for (int i = 0; i + 1 < k; ++i) {
+        const double c = h(i + 1, i);
+        if (c == 0.0) continue;
+        const double a = h(i, i), b = h(i, i + 1), d = h(i + 1, i + 1);
+        const double half = 0.5 * (a - d), disc = half * half + b * c;
+        cplx l1;
+        if (disc >= 0.0) l1 = mkc(0.5 * (a + d) + copysign(sqrt(disc), half));
+        else l1 = cplx{0.5 * (a + d), sqrt(-disc)};
+        cplx u0 = l1 - mkc(d), u1 = mkc(c);
+        const double nu = sqrt(abs2(u0) + abs2(u1));
+        u0 = (1.0 / nu) * u0;
+        u1 = (1.0 / nu) * u1;
+        __syncthreads();
+        {
+            const int j = lane;  // rows i, i+1 over columns i .. k-1
+            if (j >= i && j < k) {
+                const cplx r0 = H[i + j * LDH], r1 = H[(i + 1) + j * LDH];
+                H[i + j * LDH] = conj_mul(u0, r0) + conj_mul(u1, r1);
+                H[(i + 1) + j * LDH] = u0 * r1 - u1 * r0;
+            }
+        }
+        __syncthreads();
+        {
+            const int r = lane;  // columns i, i+1 over rows 0 .. i+1; Z over all rows
+            if (r <= i + 1) {
+                const cplx c0 = H[r + i * LDH], c1 = H[r + (i + 1) * LDH];
+                H[r + i * LDH] = c0 * u0 + c1 * u1;
+                H[r + (i + 1) * LDH] = mul_conj(c1, u0) - mul_conj(c0, u1);
+            }
+            if (r < k) {
+                const cplx c0 = Z[r + i * LDH], c1 = Z[r + (i + 1) * LDH];
+                Z[r + i * LDH] = c0 * u0 + c1 * u1;
+                Z[r + (i + 1) * LDH] = mul_conj(c1, u0) - mul_conj(c0, u1);
+            }
+        }
+        __syncthreads();
+        if (lane == 0) H[(i + 1) + i * LDH] = mkc(0.0);
+        __syncthreads();
+        ++i;  // the next row belongs to this block
+    }
+}
+
 __device__ void solve_eig_body(const SolveArgs& a) {
     const int lane = threadIdx.x;
     DevState* st = a.st;
@@ -631,15 +790,21 @@ __device__ void solve_eig_body(const SolveArgs& a) {
         __syncthreads();
     }
 
-    // ---- single-shift complex QR to Schur form (full T and Z)
+    // ---- Schur form T = Z^* A~ Z (full T and Z): real A~ by the implicit
+    // double-shift QR, each 2 x 2 block then triangularized by one complex
+    // rotation; complex A~ by the single-shift complex QR
     double hmax = 0.0;
     for (int idx = lane; idx < k * k; idx += 64) hmax = fmax(hmax, cabs(H[(idx % k) + (idx / k) * LDH]));
     for (int off = 32; off >= 1; off >>= 1) hmax = fmax(hmax, __shfl_xor(hmax, off, 64));
     const double smallnum = (hmax > 0.0 ? hmax : 1.0) * kEps;
 
-    int hi = k - 1, iter = 0, total = 0;
+    int total = 0;
     bool failed = false;
     const int max_iter = a.max_qr_iter;
+    if (!a.cplx) {
+        real_schur(H, Z, k, lane, max_iter, hmax, total, failed);
+    } else {
+    int hi = k - 1, iter = 0;
     while (hi > 0) {
         // deflation: largest l in [1, hi] with a negligible subdiagonal
         bool small = false;
@@ -738,6 +903,7 @@ __device__ void solve_eig_body(const SolveArgs& a) {
             }
             __syncthreads();
         }
+    }
     }
     __syncthreads();
 
