@@ -259,8 +259,9 @@ def modes_saturation(mix, frames, GPUExecutor, Server, StreamSpec, sat_frames=6)
         h.close()
     del outs
     torch.cuda.synchronize()
-    for prec, key in (("default", "batched_fp32"), ("bf16x3", "batched_bf16x3")):
-        ex = GPUExecutor(frames, modes=True)
+    for prec, key, graphs in (("default", "batched_fp32", 0), ("default", "batched_fp32_graph", 8),
+                              ("bf16x3", "batched_bf16x3", 0)):
+        ex = GPUExecutor(frames, modes=True, graphs=graphs)
         srv = Server(ex)
         for s in mix:
             srv.open(s.stream, StreamSpec(s.n, s.m, s.r, precision=prec))
@@ -274,7 +275,7 @@ def modes_saturation(mix, frames, GPUExecutor, Server, StreamSpec, sat_frames=6)
         torch.cuda.synchronize()
     print(f"[serve] modes at saturation: {res}", file=sys.stderr, flush=True)
     res["note"] = ("every stream backlogged, each update with its DMD modes; per_stream_fp32 runs the "
-                   "streams one after another without batching")
+                   "streams one after another without batching; _graph replays each tick as one HIP graph")
     return res
 
 

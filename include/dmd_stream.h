@@ -408,7 +408,13 @@ typedef struct dmd_batch dmd_batch_t;
 
 typedef struct {
     int32_t max_streams;  /* capacity, 1 .. 1024 (0 = 256)                          */
-    int32_t reserved0;    /* must be zero                                            */
+    int32_t graphs;       /* 0 (default): a tick enqueues its launches one by one;
+                             1 .. 256: a tick runs as one HIP graph launch, captured
+                             the first time a tick of its shape occurs (number of
+                             streams of each solver kind, Gram and projection
+                             workgroups, descriptor buffer) and replayed after that;
+                             up to `graphs` graphs are kept (least recently used
+                             evicted).  Results are identical to the eager form.    */
     int64_t hbm_budget;   /* bytes the attached streams may own together
                              (0 = 90 % of the device memory free at creation)       */
     int32_t reserved[8];  /* must be zero                                            */
@@ -451,7 +457,7 @@ int dmd_batch_info(dmd_batch_t* b, int32_t* nstreams, int64_t* used_bytes,
  * "csr_project", "gram_full", "fourier" (the ingest's two DFT kernels), for block pushes "gram_block" (block Gram pass, reduction and
  * commit), "block_solve" (all windows' solves), "pack_block" (packing the
  * projection inputs) and "project_block" (all windows' modes), and for batch ticks
- * "batch_gram", "batch_solve", "batch_project".
+ * "batch_gram", "batch_solve", "batch_project" (eager ticks) or "batch_graph" (graph ticks).
  * dmd_profile_read waits for the recorded events and returns the number of
  * launches of `kernel` and their summed duration in milliseconds since the
  * last dmd_profile_reset. */

@@ -45,7 +45,7 @@ class Opts(ctypes.Structure):
 
 
 class BatchOpts(ctypes.Structure):
-    _fields_ = [("max_streams", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+    _fields_ = [("max_streams", ctypes.c_int32), ("graphs", ctypes.c_int32),
                 ("hbm_budget", ctypes.c_int64), ("reserved", ctypes.c_int32 * 8)]
 
 
@@ -430,7 +430,9 @@ class Stream:
 class Batch:
     """Many streams advanced together (see dmd_batch_create / dmd_batch_tick)."""
 
-    def __init__(self, max_streams: int = 256, hbm_budget: int = 0):
+    def __init__(self, max_streams: int = 256, hbm_budget: int = 0, graphs: int = 0):
+        """graphs > 0 replays each tick as one HIP graph launch, keeping up to
+        that many captured tick shapes."""
         if not torch.cuda.is_available():
             raise RuntimeError("libdmdstream needs a HIP GPU; none is available")
         lib = load()
@@ -438,6 +440,7 @@ class Batch:
         check(lib.dmd_batch_opts_init(ctypes.byref(o)))
         o.max_streams = int(max_streams)
         o.hbm_budget = int(hbm_budget)
+        o.graphs = int(graphs)
         h = _P()
         check(lib.dmd_batch_create(ctypes.byref(o), ctypes.byref(h)))
         self._h = h

@@ -1481,9 +1481,30 @@ struct TickLayout {
 
 }  // namespace
 
+// A tick replayed as a HIP graph: its launches depend only on these counts
+// and on the descriptor buffer, everything else reaches the kernels through
+// the descriptors that the graph's first node copies from pinned memory.
+struct TickShape {
+    int buf, count, nl, ng, ntl, ntg, gtot, np, ptot;
+    bool operator==(const TickShape& o) const {
+        return buf == o.buf && count == o.count && nl == o.nl && ng == o.ng && ntl == o.ntl && ntg == o.ntg &&
+               gtot == o.gtot && np == o.np && ptot == o.ptot;
+    }
+};
+struct TickGraph {
+    TickShape shape;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;
+};
+
 struct dmd_batch {
     int device = 0;
     int cap = 0;
+    int graphs = 0;                    // > 0: ticks replayed as graphs, at most this many cached
+    std::vector<TickGraph> tick_graphs;
+    uint64_t uses = 0;
+    hipStream_t cap_stream = nullptr;  // capture stream (default priority)
     int64_t budget = 0, used = 0;
     std::vector<dmd_stream*> members;
     TickLayout L{};
@@ -1505,6 +1526,12 @@ DMD_API int dmd_batch_opts_init(dmd_batch_opts_t* o) {
 }
 
 static void batch_free(dmd_batch* b) {
+    for (TickGraph& g : b->tick_graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    b->tick_graphs.clear();
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     for (int i = 0; i < 2; ++i) {
         if (b->host[i]) (void)hipHostFree(b->host[i]);
         if (b->dev[i]) (void)hipFree(b->dev[i]);
@@ -1520,7 +1547,7 @@ DMD_API int dmd_batch_create(const dmd_batch_opts_t* opts, dmd_batch_t** out) {
     dmd_batch_opts_init(&o);
     if (opts) {
         o = *opts;
-        if (o.reserved0) return fail(DMD_E_INVAL, "opts.reserved0 must be zero");
+        if (o.graphs < 0 || o.graphs > 256) return fail(DMD_E_INVAL, "graphs must be in [0, 256]");
         for (int i = 0; i < 8; ++i)
             if (o.reserved[i]) return fail(DMD_E_INVAL, "opts.reserved must be zero");
         if (o.max_streams == 0) o.max_streams = 256;
@@ -1534,6 +1561,7 @@ DMD_API int dmd_batch_create(const dmd_batch_opts_t* opts, dmd_batch_t** out) {
         return fail(DMD_E_DEVICE, "no HIP device");
     }
     b->cap = o.max_streams;
+    b->graphs = o.graphs;
     b->budget = o.hbm_budget;
     if (b->budget == 0) {
         size_t fr = 0, tot = 0;
@@ -1551,6 +1579,7 @@ DMD_API int dmd_batch_create(const dmd_batch_opts_t* opts, dmd_batch_t** out) {
         if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done[i], hipEventDisableTiming);
     }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_last, hipEventDisableTiming);
+    if (e == hipSuccess && b->graphs > 0) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         batch_free(b);
         delete b;
@@ -1681,25 +1710,69 @@ DMD_API int dmd_batch_tick(dmd_batch_t* b, int32_t count, dmd_stream_t* const* s
     // order after every member's earlier work and the batch's previous tick
     for (int i = 0; i < count; ++i) HIP_TRY(begin(streams[i], s));
     if (b->has_last && b->last_stream != s) HIP_TRY(hipStreamWaitEvent(s, b->ev_last, 0));
-    HIP_TRY(hipMemcpyAsync(D, H, b->L.bytes, hipMemcpyHostToDevice, s));
-    auto* dgi = reinterpret_cast<const dmd::GramItem*>(D + b->L.gram);
-    auto* dgblk = reinterpret_cast<const int*>(D + b->L.gblk);
-    HIP_TRY(timed("batch_gram", s, [&] { return dmd::launch_gram_grouped(dgi, dgblk, count, gtot, s); }));
-    HIP_TRY(timed("batch_solve", s, [&] {
-        hipError_t e = dmd::launch_jacobi_grouped(reinterpret_cast<const dmd::SolveArgs*>(D + b->L.lds), nl,
-                                                  reinterpret_cast<const dmd::SolveArgs*>(D + b->L.glb), ng, s);
-        if (e == hipSuccess)
-            e = dmd::launch_trid_grouped(reinterpret_cast<const dmd::SolveArgs*>(D + b->L.tlds), ntl,
-                                         reinterpret_cast<const dmd::SolveArgs*>(D + b->L.tglb), ntg, s);
-        if (e == hipSuccess)
-            e = dmd::launch_eig_grouped(reinterpret_cast<const dmd::SolveArgs*>(D + b->L.all), count, s);
-        return e;
-    }));
-    if (np > 0)
-        HIP_TRY(timed("batch_project", s, [&] {
+    // the tick's work: descriptors to the device, then one grouped launch per phase
+    auto enqueue = [&](hipStream_t q, bool time_phases) -> hipError_t {
+        hipError_t e = hipMemcpyAsync(D, H, b->L.bytes, hipMemcpyHostToDevice, q);
+        if (e != hipSuccess) return e;
+        auto phase = [&](const char* name, auto&& fn) { return time_phases ? timed(name, q, fn) : fn(); };
+        auto* dgi = reinterpret_cast<const dmd::GramItem*>(D + b->L.gram);
+        auto* dgblk = reinterpret_cast<const int*>(D + b->L.gblk);
+        e = phase("batch_gram", [&] { return dmd::launch_gram_grouped(dgi, dgblk, count, gtot, q); });
+        if (e != hipSuccess) return e;
+        e = phase("batch_solve", [&] {
+            hipError_t f = dmd::launch_jacobi_grouped(reinterpret_cast<const dmd::SolveArgs*>(D + b->L.lds), nl,
+                                                      reinterpret_cast<const dmd::SolveArgs*>(D + b->L.glb), ng, q);
+            if (f == hipSuccess)
+                f = dmd::launch_trid_grouped(reinterpret_cast<const dmd::SolveArgs*>(D + b->L.tlds), ntl,
+                                             reinterpret_cast<const dmd::SolveArgs*>(D + b->L.tglb), ntg, q);
+            if (f == hipSuccess)
+                f = dmd::launch_eig_grouped(reinterpret_cast<const dmd::SolveArgs*>(D + b->L.all), count, q);
+            return f;
+        });
+        if (e != hipSuccess || np == 0) return e;
+        return phase("batch_project", [&] {
             return dmd::launch_project_grouped(reinterpret_cast<const dmd::ProjectArgs*>(D + b->L.proj),
-                                               reinterpret_cast<const int*>(D + b->L.pblk), np, ptot, s);
-        }));
+                                               reinterpret_cast<const int*>(D + b->L.pblk), np, ptot, q);
+        });
+    };
+    if (b->graphs > 0) {
+        const TickShape shape{buf, count, nl, ng, ntl, ntg, gtot, np, ptot};
+        TickGraph* tg = nullptr;
+        for (TickGraph& g : b->tick_graphs)
+            if (g.shape == shape) tg = &g;
+        if (!tg) {
+            if ((int)b->tick_graphs.size() >= b->graphs) {  // evict the least recently used
+                size_t lru = 0;
+                for (size_t i = 1; i < b->tick_graphs.size(); ++i)
+                    if (b->tick_graphs[i].last_use < b->tick_graphs[lru].last_use) lru = i;
+                HIP_TRY(hipGraphExecDestroy(b->tick_graphs[lru].exec));
+                HIP_TRY(hipGraphDestroy(b->tick_graphs[lru].graph));
+                b->tick_graphs.erase(b->tick_graphs.begin() + (long)lru);
+            }
+            TickGraph g;
+            g.shape = shape;
+            HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed));
+            const hipError_t ce = enqueue(b->cap_stream, false);
+            hipGraph_t graph = nullptr;
+            const hipError_t ee = hipStreamEndCapture(b->cap_stream, &graph);
+            if (ce != hipSuccess || ee != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return hip_fail(ce != hipSuccess ? ce : ee, "tick capture");
+            }
+            g.graph = graph;
+            const hipError_t ie = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+            if (ie != hipSuccess) {
+                (void)hipGraphDestroy(graph);
+                return hip_fail(ie, "hipGraphInstantiate");
+            }
+            b->tick_graphs.push_back(g);
+            tg = &b->tick_graphs.back();
+        }
+        tg->last_use = ++b->uses;
+        HIP_TRY(timed("batch_graph", s, [&] { return hipGraphLaunch(tg->exec, s); }));
+    } else {
+        HIP_TRY(enqueue(s, true));
+    }
     HIP_TRY(hipEventRecord(b->done[buf], s));
     b->used_buf[buf] = true;
     b->next ^= 1;

@@ -178,10 +178,11 @@ class GPUExecutor:
     """Executor backed by libdmdstream: one Stream per sid in one Batch.
     Frame `index` of stream `sid` is read from frames[sid][index % len].
     With modes=True every update also projects the window's DMD modes into a
-    resident per-stream buffer (in the stream's precision)."""
+    resident per-stream buffer (in the stream's precision).  graphs > 0 runs
+    each tick as one HIP graph launch (tick shapes cached, see Batch)."""
 
     def __init__(self, frames: Dict[int, "object"], hbm_budget: int = 0, max_streams: int = 1024,
-                 modes: bool = False):
+                 modes: bool = False, graphs: int = 0):
         import torch
         from .binding import Batch, DMDError, Stream, E_NOMEM
         self.torch = torch
@@ -189,7 +190,7 @@ class GPUExecutor:
         self.DMDError = DMDError
         self.E_NOMEM = E_NOMEM
         self.frames = frames
-        self.batch = Batch(max_streams=max_streams, hbm_budget=hbm_budget)
+        self.batch = Batch(max_streams=max_streams, hbm_budget=hbm_budget, graphs=graphs)
         self.streams = {}
         self.want_modes = modes
         self.modes = {}

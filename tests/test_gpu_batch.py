@@ -127,3 +127,79 @@ def test_batch_rejects_unsupported_members():
         s64.close()
         s.close()
         other.close()
+
+
+@pytest.mark.parametrize("graphs", [1, 3, 64])
+def test_graph_ticks_equal_eager_ticks(graphs):
+    """Ticks replayed as HIP graphs give the eager ticks' results, bit for bit.
+
+    Streams join at different ticks and modes are asked for on some ticks
+    only, so several tick shapes occur (with graphs = 1 and 3 the cache
+    evicts and recaptures); between replays the program runs eager work of
+    its own (a plain stream push, a torch reduction) and synchronizes.
+    """
+    dmd = _dmd()
+    mix = [MIX[0], MIX[1], MIX[4], MIX[5]]
+    T = 48
+    gens = [make_gen(i, n, kind) for i, (n, m, r, kind) in enumerate(mix)]
+    dev = [torch.from_numpy(np.stack([g.frame(t) for t in range(T)], axis=0)).cuda() for g in gens]
+    start = [0, 3, 9, 9]
+
+    def run(graph_cache, side):
+        streams = [dmd.Stream(n, m, r) for (n, m, r, kind) in mix]
+        batch = dmd.Batch(max_streams=8, graphs=graph_cache)
+        for s in streams:
+            batch.attach(s)
+        outs = [torch.zeros((s.r, s.n), dtype=torch.complex64, device="cuda").T for s in streams]
+        trace = []
+        for t in range(T):
+            act = [i for i in range(len(mix)) if t >= start[i]]
+            want_modes = t % 3 != 1
+            batch.tick([streams[i] for i in act], [dev[i][t - start[i]] for i in act],
+                       modes=[outs[i] for i in act] if want_modes else None)
+            if side is not None:
+                side.push(dev[0][t])
+                torch.cuda.synchronize()
+                _ = float(dev[1][t].abs().sum())
+            torch.cuda.synchronize()
+            rec = []
+            for i in act:
+                s = streams[i]
+                G = s.gram()
+                try:
+                    lam, sig, _ = s.eigs()
+                except dmd.DMDError as e:
+                    assert e.code == dmd.E_NOT_READY
+                    rec.append((G, None, None, None))
+                    continue
+                phi = outs[i].cpu().numpy()[:, :lam.size] if want_modes else None
+                rec.append((G, lam, sig, phi))
+            trace.append(rec)
+        batch.close()
+        for s in streams:
+            s.close()
+        return trace
+
+    eager = run(0, None)
+    with dmd.Stream(*mix[0][:3]) as side:
+        graphed = run(graphs, side)
+    ready = 0
+    for t, (re, rg) in enumerate(zip(eager, graphed)):
+        for i, (a, b) in enumerate(zip(re, rg)):
+            assert np.array_equal(a[0], b[0]), (t, i)
+            if a[1] is None:
+                assert b[1] is None, (t, i)
+                continue
+            ready += 1
+            assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2]), (t, i)
+            if a[3] is not None:
+                assert np.array_equal(a[3], b[3]), (t, i)
+    assert ready > 40
+
+
+def test_graph_option_checks():
+    dmd = _dmd()
+    for bad in (-1, 257):
+        with pytest.raises(dmd.DMDError) as ei:
+            dmd.Batch(max_streams=4, graphs=bad)
+        assert ei.value.code == dmd.E_INVAL
