@@ -51,6 +51,7 @@ def parse():
                     help="block: k frames per step (multi-column update, every window solved and projected); "
                          "single: one frame per step")
     ap.add_argument("--block", type=int, default=32, help="frames per block in block mode (1..64)")
+    ap.add_argument("--rank", type=int, default=R, help="truncation rank r (the workload's is 20)")
     ap.add_argument("--precision", choices=("fp32", "bf16x3"), default="fp32",
                     help="arithmetic of the mode projections: FP32 MFMA, or three BF16 MFMA products "
                          "(hi*hi + hi*lo + lo*hi) with FP32 accumulation")
@@ -653,7 +654,9 @@ def result_line(value, K, Wu, elapsed, dtype, config):
 
 
 def main():
+    global R
     args = defaults(parse())
+    R = args.rank
     if args.copy_probe and args.gpus == 1:
         copy_probe()
         return

@@ -363,10 +363,18 @@ constexpr int kBlkRows = 64;
 constexpr int kBlkLDR = kBlkRows + 16;  // column stride: the four k-slots of a fragment hit distinct banks
 constexpr size_t kBlockLdsMax = 150 * 1024;  // dynamic LDS of the one-pass block projection
 
-// Three waves per SIMD, two for the BF16x3 form with three or more column
-// tiles (whose A-fragment assembly needs the registers to prefetch two chunks).
+// Windows ahead whose coefficient fragments a wavefront holds (see below):
+// two for the FP32 form with two or more column tiles, one otherwise.
 template <int NT, bool BF3>
-__global__ __launch_bounds__(kThreads, (BF3 && NT >= 3) ? 2 : 3)
+constexpr int kBlockAhead = (!BF3 && NT >= 2) ? 2 : 1;
+// Waves per SIMD: two for the BF16x3 form with three or more column tiles
+// (whose A-fragment assembly needs the registers to prefetch two chunks) and
+// for the FP32 form holding two windows' fragments, three otherwise.  Two
+// waves also leave a CU room for a small solve when one of its projection
+// workgroups retires, so the solves of the next block push run beside the
+// projection instead of after it.
+template <int NT, bool BF3>
+__global__ __launch_bounds__(kThreads, ((BF3 && NT >= 3) || kBlockAhead<NT, BF3> == 2) ? 2 : 3)
 void k_project_block(BlockProjectArgs a) {
     extern __shared__ float dynp[];
     const BlockDesc* desc = a.desc;
@@ -402,6 +410,7 @@ void k_project_block(BlockProjectArgs a) {
     // order, so a load issued after those stores could not be waited for
     // without waiting for the stores as well.
     constexpr int PF = (NT <= 3 || BF3) ? 2 : 1;
+    constexpr int PA = kBlockAhead<NT, BF3>;
     auto load_frag = [&](int w, int q, Frag (&f)[NT]) {
         const uint4* fb = a.cfrag + ((size_t)(w * nq + q) * NT * 64 + lane) * 2;
 #pragma unroll
@@ -462,13 +471,26 @@ void k_project_block(BlockProjectArgs a) {
     };
 
 
-    Frag f0[PF >= 1 ? NT : 1], f1[PF == 2 ? NT : 1];
-    if (wave < k) {
-        if constexpr (PF >= 1) load_frag(wave, 0, f0);
-        if constexpr (PF == 2)
-            if (nq > 1) load_frag(wave, 1, f1);
+    // Fragments are loaded PA windows ahead: with PA = 2 a window's stores
+    // have two windows of products to complete before a wait for fragments
+    // (which in issue order follows them) has to see them done.  The window
+    // loop is unrolled by PA so that every fragment array is indexed
+    // statically (kept in registers).
+    Frag fr[PA][PF == 2 ? 2 : 1][NT];
+#pragma unroll
+    for (int s = 0; s < PA; ++s) {
+        const int w = wave + (kThreads / 64) * s;
+        if (w < k) {
+            if constexpr (PF >= 1) load_frag(w, 0, fr[s][0]);
+            if constexpr (PF == 2)
+                if (nq > 1) load_frag(w, 1, fr[s][1]);
+        }
     }
-    for (int w = wave; w < k; w += kThreads / 64) {
+    for (int w0 = wave; w0 < k; w0 += (kThreads / 64) * PA) {
+#pragma unroll
+    for (int s = 0; s < PA; ++s) {
+        const int w = w0 + (kThreads / 64) * s;
+        if (w >= k) break;
         const int kc = desc->kc[w];
         v4f acc[4][NT];
 #pragma unroll
@@ -476,19 +498,20 @@ void k_project_block(BlockProjectArgs a) {
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) acc[rt][nt] = v4f{0, 0, 0, 0};
         if (kc > 0) {
-            if constexpr (PF >= 1) chunk(w, 0, f0, acc);
+            if constexpr (PF >= 1) chunk(w, 0, fr[s][0], acc);
             if constexpr (PF == 2)
-                if (nq > 1) chunk(w, 32, f1, acc);
+                if (nq > 1) chunk(w, 32, fr[s][1], acc);
             for (int q = PF; q < nq; ++q) {
                 Frag g[NT];
                 load_frag(w, q, g);
                 chunk(w, 32 * q, g, acc);
             }
         }
-        if (w + kThreads / 64 < k) {
-            if constexpr (PF >= 1) load_frag(w + kThreads / 64, 0, f0);
+        const int wn = w + (kThreads / 64) * PA;
+        if (wn < k) {
+            if constexpr (PF >= 1) load_frag(wn, 0, fr[s][0]);
             if constexpr (PF == 2)
-                if (nq > 1) load_frag(w + kThreads / 64, 1, f1);
+                if (nq > 1) load_frag(wn, 1, fr[s][1]);
         }
         if (kc == 0) continue;  // unsolved window: its output is left untouched
         // Output straight from the accumulators: lane (li, lq) of tile (rt, nt)
@@ -524,6 +547,7 @@ void k_project_block(BlockProjectArgs a) {
         };
         if (a.out16 && row0 + kBlkRows <= a.n) store(std::true_type{});
         else store(std::false_type{});
+    }
     }
 }
 
