@@ -435,6 +435,18 @@ def bench_single(args):
     return out, host_keep
 
 
+_STREAMS = None
+
+
+def bench_streams(torch):
+    """The push and projection streams, created once: every timed leg runs on
+    the same pair of HIP streams (and so the same hardware queues)."""
+    global _STREAMS
+    if _STREAMS is None:
+        _STREAMS = (torch.cuda.Stream(), torch.cuda.Stream())
+    return _STREAMS
+
+
 def timed_blocks(dmd, torch, frames, n, kb, K, Wu, precision):
     """Fill a window with block pushes, then Wu untimed and K timed steps of
     one block push + the modes of all its windows.  Pushes (Gram update +
@@ -443,7 +455,7 @@ def timed_blocks(dmd, torch, frames, n, kb, K, Wu, precision):
     fill = M + 1
     s = dmd.Stream(n, M, R, dtype="f32", max_block=kb, precision=precision)
     phis = torch.zeros((kb, R, n), dtype=torch.complex64, device="cuda")
-    sp, sm = torch.cuda.Stream(), torch.cuda.Stream()
+    sp, sm = bench_streams(torch)
     sp.wait_stream(torch.cuda.current_stream())
     sm.wait_stream(torch.cuda.current_stream())
     t = 0

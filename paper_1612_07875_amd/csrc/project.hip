@@ -603,6 +603,231 @@ void k_pack_coef(BlockProjectArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP32 block projection over window pairs.  When 2 r = 8 (mod 16) the real
+// columns of one window fill NT tiles of 16 only partly (r = 20: 40 of 48),
+// but two windows fill 4r/16 tiles exactly.  Windows 2p and 2p+1 read stage
+// columns one apart, so as one product they read the m + 1 columns 2p ..
+// 2p + m against a pair matrix P (rows i = 0 .. m, columns 0 .. 4r - 1):
+// P[i][c] = C_2p[i][c] (c < 2r, i < m) and C_2p+1[i - 1][c - 2r] (c >= 2r,
+// i >= 1), zero elsewhere.  The pair costs ceil((m + 1) / 4) k-steps of 4r/16
+// tiles instead of 2 (m / 4) steps of ceil(2r / 16) tiles (r = 12, m = 32:
+// 4 x 27 MFMAs per 64 rows instead of 4 x 32).  k-steps come as chunks of
+// eight (two 16-byte loads per lane and tile) plus at most one single step.
+// Up to three tiles (r = 4, 12): with five (r = 20) the pair's accumulators
+// and fragments take all 256 registers of two waves per SIMD, and although
+// the product itself is faster, the next block's solves then find no room on
+// the CUs and run after it instead of beside it (measured: the per-window
+// form with two windows of fragments in flight wins there).
+constexpr int kPairMaxTiles = 3;
+
+struct PairShape {
+    int nfull;  // whole 8-step chunks
+    int tail;   // single steps after them (0 or 1)
+};
+__host__ __device__ inline PairShape pair_shape(int m) {
+    const int nsteps = (m + 1 + 3) / 4;
+    return PairShape{nsteps / 8, nsteps % 8};
+}
+// Whether the pair form applies: FP32, 2r = 8 mod 16, at most kPairMaxTiles
+// tiles, at least one whole chunk and at most one tail step.
+bool use_pairs(const BlockProjectArgs& a) {
+    const int tiles = 4 * a.r / 16;
+    const PairShape ps = pair_shape(a.m);
+    return !a.bf16x3 && (2 * a.r) % 16 == 8 && tiles <= kPairMaxTiles && ps.nfull >= 1 && ps.tail <= 1;
+}
+size_t pair_lds(int m, int k) {
+    const PairShape ps = pair_shape(m);
+    return sizeof(float) * (size_t)(k + 1 + 4 * (8 * ps.nfull + ps.tail)) * kBlkLDR;
+}
+
+// Coefficients of window w of the block (m x 2 r row-major) and 2 r_eff, 0 if
+// the window has no solve.
+__device__ inline const float* window_coef(const BlockProjectArgs& a, int w, int& kc) {
+    const int set = a.kmax - a.k + w;
+    const DevState* st =
+        w == a.k - 1 ? a.st : reinterpret_cast<const DevState*>(a.shadow + (size_t)set * a.shadow_stride);
+    kc = (st->solve_status == ST_OK || st->solve_status == ST_W_RANK) ? 2 * st->r_eff : 0;
+    return w == a.k - 1 ? a.Bphi : a.Bphi_sets + (int64_t)set * a.bphi_stride;
+}
+
+// Packs P of pair p = blockIdx.y, tile t = blockIdx.x.  Pair p starts at
+// float p (8 nfull + tail) NTG 64; in it, float ((q NTG + t) 64 + lane) 8 + e
+// of chunk q holds P[32 q + 4 e + lane/16][16 t + lane%16] (e = 0..7: one
+// lane's eight steps, two 16-byte loads), and after the chunks float
+// t 64 + lane of the tail step holds P[32 nfull + lane/16][16 t + lane%16].
+template <int NTG>
+__global__ __launch_bounds__(64)
+void k_pack_pair(BlockProjectArgs a) {
+    const int lane = threadIdx.x, t = blockIdx.x, p = blockIdx.y;
+    const int li = lane & 15, lk = lane >> 4;
+    const int k = a.k, m = a.m, r2 = 2 * a.r;
+    const PairShape ps = pair_shape(m);
+    const int w0 = 2 * p, w1 = 2 * p + 1;
+    int kc0 = 0, kc1 = 0;
+    const float* B0 = window_coef(a, w0, kc0);
+    const float* B1 = w1 < k ? window_coef(a, w1, kc1) : nullptr;
+    if (t == 0 && lane == 0) {
+        a.desc->kc[w0] = kc0;
+        if (w1 < k) a.desc->kc[w1] = kc1;
+        if (w0 == k - 1 || w1 == k - 1) {
+            a.desc->valid = a.st->count >= a.m + 1 && !a.st->block_rejected;
+            a.desc->base = a.st->oldest + 2 - k + a.slots;
+        }
+    }
+    const int c = 16 * t + li;
+    auto P = [&](int i) -> float {
+        if (c < r2) return (i < m && c < kc0) ? B0[(int64_t)i * r2 + c] : 0.0f;
+        const int cc = c - r2;
+        return (w1 < k && i >= 1 && i <= m && cc < kc1) ? B1[(int64_t)(i - 1) * r2 + cc] : 0.0f;
+    };
+    const size_t pair_base = (size_t)p * (8 * ps.nfull + ps.tail) * NTG * 64;
+    float* out = reinterpret_cast<float*>(a.cfrag) + pair_base;
+    for (int q = 0; q < ps.nfull; ++q) {
+        float* o = out + (((size_t)q * NTG + t) * 64 + lane) * 8;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) o[e] = P(32 * q + 4 * e + lk);
+    }
+    if (ps.tail) out[((size_t)8 * ps.nfull * NTG + t) * 64 + lane] = P(32 * ps.nfull + lk);
+}
+
+template <int NTG>
+__global__ __launch_bounds__(kThreads, 2)
+void k_project_pair(BlockProjectArgs a) {
+    extern __shared__ float dynp[];
+    const BlockDesc* desc = a.desc;
+    if (!desc->valid) return;
+    const int m = a.m, k = a.k, r2 = 2 * a.r;
+    const PairShape ps = pair_shape(m);
+    const int nst = 8 * ps.nfull + ps.tail;
+    const int ncols = m + k - 1;
+    const int ncols_pad = k + 1 + 4 * nst;  // the last pair's steps read zero columns past the union
+    float* U = dynp;
+    const int64_t row0 = (int64_t)blockIdx.x * kBlkRows;
+    const int base = desc->base;
+    const float* ring = static_cast<const float*>(a.ring);
+    for (int t = threadIdx.x; t < ncols_pad * (kBlkRows / 4); t += kThreads) {
+        const int c = t / (kBlkRows / 4), q = t % (kBlkRows / 4);
+        float4 x = float4{0.0f, 0.0f, 0.0f, 0.0f};
+        if (c < ncols) x = *reinterpret_cast<const float4*>(ring + (int64_t)((base + c) % a.slots) * a.ld + row0 + 4 * q);
+        *reinterpret_cast<float4*>(&U[c * kBlkLDR + 4 * q]) = x;
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int npairs = (k + 1) / 2;
+    const float* cf = reinterpret_cast<const float*>(a.cfrag);
+    const size_t pair_stride = (size_t)nst * NTG * 64;
+    // Chunk 0 and the tail step of a pair are loaded one pair ahead (before
+    // the previous pair's stores, so waiting for them does not wait for
+    // those); every later chunk at the top of the pair's iteration, a chunk
+    // of products ahead of its use.
+    Frag f0[NTG];
+    float ft[NTG];
+    auto load_chunk = [&](int p, int q, Frag (&f)[NTG]) {
+        const float* pb = cf + (size_t)p * pair_stride;
+#pragma unroll
+        for (int t = 0; t < NTG; ++t) {
+            const uint4* g = reinterpret_cast<const uint4*>(pb + (((size_t)q * NTG + t) * 64 + lane) * 8);
+            f[t].x = g[0];
+            f[t].y = g[1];
+        }
+    };
+    auto load = [&](int p) {
+        load_chunk(p, 0, f0);
+        const float* pb = cf + (size_t)p * pair_stride;
+#pragma unroll
+        for (int t = 0; t < NTG; ++t) ft[t] = ps.tail ? pb[((size_t)8 * ps.nfull * NTG + t) * 64 + lane] : 0.0f;
+    };
+    // acc += stage columns c0 + 4 s + lk (s = 0..7) x the chunk's coefficients
+    auto chunk = [&](int c0, const Frag (&f)[NTG], v4f (&acc)[4][NTG]) {
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+            const float* ucol = U + (c0 + 4 * ks + lk) * kBlkLDR;
+            float bv[NTG];
+#pragma unroll
+            for (int t = 0; t < NTG; ++t) {
+                const uint4& u = ks < 4 ? f[t].x : f[t].y;
+                const unsigned e = (ks & 3) == 0 ? u.x : (ks & 3) == 1 ? u.y : (ks & 3) == 2 ? u.z : u.w;
+                bv[t] = __builtin_bit_cast(float, e);
+            }
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
+                const float av = ucol[16 * rt + li];
+#pragma unroll
+                for (int t = 0; t < NTG; ++t)
+                    acc[rt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[t], acc[rt][t], 0, 0, 0);
+            }
+        }
+    };
+    if (wave < npairs) load(wave);
+    for (int p = wave; p < npairs; p += kThreads / 64) {
+        const int w0 = 2 * p, w1 = 2 * p + 1;
+        const int kc0 = desc->kc[w0], kc1 = w1 < k ? desc->kc[w1] : 0;
+        v4f acc[4][NTG];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int t = 0; t < NTG; ++t) acc[rt][t] = v4f{0, 0, 0, 0};
+        if (kc0 + kc1 > 0) {
+            Frag g[NTG];
+            if (ps.nfull > 1) load_chunk(p, 1, g);
+            chunk(w0, f0, acc);
+            for (int q = 1; q < ps.nfull; ++q) {
+                chunk(w0 + 32 * q, g, acc);
+                if (q + 1 < ps.nfull) load_chunk(p, q + 1, g);
+            }
+            if (ps.tail) {
+                const float* ucol = U + (w0 + 32 * ps.nfull + lk) * kBlkLDR;
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt) {
+                    const float av = ucol[16 * rt + li];
+#pragma unroll
+                    for (int t = 0; t < NTG; ++t)
+                        acc[rt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, ft[t], acc[rt][t], 0, 0, 0);
+                }
+            }
+        }
+        if (p + kThreads / 64 < npairs) load(p + kThreads / 64);
+        if (kc0 + kc1 == 0) continue;
+        // Stores as in k_project_block: one swap with the neighbouring lane
+        // gives whole complex values of two consecutive rows; real column
+        // 16 t + li of the pair is column (16 t + li) of window 2p below 2 r,
+        // of window 2p + 1 above (r is even here, so a tile's lane pairs never
+        // straddle the two).
+        const bool odd = li & 1;
+        auto store = [&](auto full) {
+#pragma unroll
+            for (int t = 0; t < NTG; ++t) {
+                const int c = 16 * t + li;
+                const bool second = c >= r2;
+                const int w = second ? w1 : w0;
+                const int j = (second ? c - r2 : c) >> 1;
+                const int r_eff = (second ? kc1 : kc0) >> 1;
+                float2* out = a.out + (int64_t)w * a.ldw;
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt) {
+                    const v4f d = acc[rt][t];
+                    const float x = odd ? d[0] : d[2], y = odd ? d[1] : d[3];
+                    const float xs = swap_pair(x), ys = swap_pair(y);
+                    const float4 val = odd ? float4{xs, d[2], ys, d[3]} : float4{d[0], xs, d[1], ys};
+                    const int64_t row = row0 + 16 * rt + 4 * lk + (odd ? 2 : 0);
+                    float2* o = out + row + (int64_t)j * a.ldo;
+                    if constexpr (decltype(full)::value) {
+                        if (j < r_eff) *reinterpret_cast<float4*>(o) = val;
+                    } else if (j < r_eff && row < a.n) {
+                        o[0] = float2{val.x, val.y};
+                        if (row + 1 < a.n) o[1] = float2{val.z, val.w};
+                    }
+                }
+            }
+        };
+        if (a.out16 && row0 + kBlkRows <= a.n) store(std::true_type{});
+        else store(std::false_type{});
+    }
+}
+
 size_t block_lds(int m, int k) { return sizeof(float) * (size_t)(k - 1 + 32 * ((m + 31) / 32)) * kBlkLDR; }
 
 template <int NT>
@@ -621,9 +846,16 @@ hipError_t launch_block_nt(const BlockProjectArgs& a, hipStream_t s) {
 
 }  // namespace
 
-size_t project_block_frag_bytes(int m, int kmax) { return (size_t)kmax * ((m + 31) / 32) * 4 * 64 * 32; }
+size_t project_block_frag_bytes(int m, int kmax) {
+    const PairShape ps = pair_shape(m);
+    const size_t per_window = (size_t)kmax * ((m + 31) / 32) * 4 * 64 * 32;
+    const size_t pairs = (size_t)((kmax + 1) / 2) * (8 * ps.nfull + ps.tail) * kPairMaxTiles * 64 * sizeof(float);
+    return per_window > pairs ? per_window : pairs;
+}
 
-bool project_block_fits(int m, int k, int r) { return 2 * r <= 64 && k <= 64 && block_lds(m, k) <= kBlockLdsMax; }
+bool project_block_fits(int m, int k, int r) {
+    return 2 * r <= 64 && k <= 64 && block_lds(m, k) <= kBlockLdsMax && pair_lds(m, k) <= kBlockLdsMax;
+}
 
 template <int NT>
 hipError_t launch_pack_nt(const BlockProjectArgs& a, hipStream_t s) {
@@ -634,9 +866,35 @@ hipError_t launch_pack_nt(const BlockProjectArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int NTG>
+hipError_t launch_pair_ntg(const BlockProjectArgs& a, hipStream_t s, bool pack) {
+    if (!a.cfrag || !a.desc) return hipErrorInvalidValue;
+    if (pack) {
+        hipLaunchKernelGGL(k_pack_pair<NTG>, dim3(NTG, (unsigned)((a.k + 1) / 2)), dim3(64), 0, s, a);
+        return hipGetLastError();
+    }
+    const size_t lds = pair_lds(a.m, a.k);
+    if (lds > kBlockLdsMax) return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_project_pair<NTG>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const unsigned gx = (unsigned)((a.n + kBlkRows - 1) / kBlkRows);
+    hipLaunchKernelGGL(k_project_pair<NTG>, dim3(gx), dim3(kThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair(const BlockProjectArgs& a, hipStream_t s, bool pack) {
+    switch (4 * a.r / 16) {
+        case 1: return launch_pair_ntg<1>(a, s, pack);
+        case 3: return launch_pair_ntg<3>(a, s, pack);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_pack_block(const BlockProjectArgs& a, hipStream_t s) {
     const int kc_max = 2 * a.r;
     if (kc_max > 64 || a.k < 1 || a.k > a.kmax) return hipErrorInvalidValue;
+    if (use_pairs(a)) return launch_pair(a, s, true);
     if (kc_max <= 16) return launch_pack_nt<1>(a, s);
     if (kc_max <= 32) return launch_pack_nt<2>(a, s);
     if (kc_max <= 48) return launch_pack_nt<3>(a, s);
@@ -646,6 +904,7 @@ hipError_t launch_pack_block(const BlockProjectArgs& a, hipStream_t s) {
 hipError_t launch_project_block(const BlockProjectArgs& a, hipStream_t s) {
     const int kc_max = 2 * a.r;
     if (kc_max > 64 || a.k < 1 || a.k > a.kmax || a.ld % kBlkRows) return hipErrorInvalidValue;
+    if (use_pairs(a)) return launch_pair(a, s, false);
     if (kc_max <= 16) return launch_block_nt<1>(a, s);
     if (kc_max <= 32) return launch_block_nt<2>(a, s);
     if (kc_max <= 48) return launch_block_nt<3>(a, s);

@@ -260,3 +260,56 @@ def test_block_modes_large_windows(m, r, kb):
             stat, lam, sig = wins[w]
             ref, perm = check_eigs(stat, lam, sig, frames[:, te - m:te + 1], m, r)
             check_phi(phis[w].T, ref, perm, lam.size, 2e-4)
+
+
+@pytest.mark.parametrize("H,W,m,r", [(97, 134, 32, 12), (100, 200, 64, 12), (50, 100, 31, 4)])
+def test_block_fp32_window_pairs(H, W, m, r):
+    """FP32 ranks r = 4, 12 (2r = 8 mod 16) project two windows per product.  Odd
+    blocks end with a window of its own, and the block in which the window
+    fills pairs unsolved windows with solved ones: every window against the
+    oracle, unsolved windows and columns past r_eff left untouched."""
+    dmd = _dmd()
+    n = H * W
+    blocks = [16, 16, 7, 16, 1, 11, 16, 5]
+    frames = gen.BlobVideo(height=H, width=W, blob_sigma=4.0).frames(0, sum(blocks))
+    X = torch.from_numpy(frames.T.copy()).cuda()
+    with dmd.Stream(n, m, r, max_block=16) as s:
+        run_blocks(s, X, frames, blocks, m, r, phi_tol=2e-4)
+
+
+def test_block_fp32_pairs_rank_deficient():
+    """Noiseless modal data has rank 10; with r = 12 every window uses
+    r_eff = 10 (both windows of a pair): modes 0..9 against the oracle of
+    the same rank, modes 10, 11 left untouched."""
+    dmd = _dmd()
+    n, m, r, kb = 6000, 32, 12, 7
+    g = gen.ModalStream(n=n, noise=0.0)
+    T = m + 1 + 3 * kb
+    frames = g.frames(0, T).astype(np.float32)
+    X = torch.from_numpy(frames.T.copy()).cuda()
+    sentinel = 7.0 + 7.0j
+    with dmd.Stream(n, m, r, max_block=kb) as s:
+        t = 0
+        while t < m + 1:
+            k = min(kb, m + 1 - t)
+            s.push_block(X[t:t + k])
+            t += k
+        checked = 0
+        while t + kb <= T:
+            s.push_block(X[t:t + kb])
+            t += kb
+            wins, rc = s.block_eigs()
+            assert rc == dmd.W_RANK
+            phis = s.block_modes(torch.full((kb, r, n), sentinel, dtype=torch.complex64, device="cuda"))
+            phis = phis.cpu().numpy()
+            for w, (stat, lam, sig) in enumerate(wins):
+                te = t - kb + w
+                assert stat == dmd.W_RANK and lam.size == 10, (w, stat, lam.size)
+                Wf = oracle.as_fp64(frames[:, te - m:te + 1])
+                ref = oracle.exact_dmd(Wf[:, :m], Wf[:, 1:], r, r_eff=10)
+                err, perm = metrics.eig_relerr(lam, ref.lam)
+                assert err.max() < 1e-6, (w, err.max())
+                check_phi(phis[w].T, ref, perm, 10, 2e-4)
+                assert np.all(phis[w][10:] == sentinel)
+                checked += 1
+        assert checked == 3 * kb
