@@ -1745,6 +1745,8 @@ DMD_API int dmd_batch_tick(dmd_batch_t* b, int32_t count, dmd_stream_t* const* s
                 size_t lru = 0;
                 for (size_t i = 1; i < b->tick_graphs.size(); ++i)
                     if (b->tick_graphs[i].last_use < b->tick_graphs[lru].last_use) lru = i;
+                // the evicted graph may still run: destroy it only after the last tick
+                if (b->has_last) HIP_TRY(hipEventSynchronize(b->ev_last));
                 HIP_TRY(hipGraphExecDestroy(b->tick_graphs[lru].exec));
                 HIP_TRY(hipGraphDestroy(b->tick_graphs[lru].graph));
                 b->tick_graphs.erase(b->tick_graphs.begin() + (long)lru);

@@ -175,53 +175,65 @@ __device__ void gram_slab(const T* __restrict__ x, T* __restrict__ ring, int64_t
             }
     }
 
-    __shared__ double red[kWaves][kGroup];
+    // Column groups: the slabs of the next group are loaded before the
+    // current group's products and wavefront sums, so loads stay in flight
+    // while the wavefront reduces; each wavefront's sums wait in LDS and the
+    // waves are summed once at the end (one barrier per slab).
+    constexpr int G = ITER * N >= 16 ? 2 : kGroup;  // columns per group (registers: two groups in flight)
+    __shared__ double red[kWaves][kMaxM + 2];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-
-    for (int j0 = 0; j0 <= nkept; j0 += kGroup) {
-        double acc[kGroup];
+    auto load_group = [&](int j0, T (&cv)[G][ITER][N]) {
 #pragma unroll
-        for (int u = 0; u < kGroup; ++u) acc[u] = 0.0;
-        T cv[kGroup][ITER][N];
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u) {
+        for (int u = 0; u < G; ++u) {
             const int j = j0 + u;
             if (j < nkept) {
                 const T* col = ring + (int64_t)slot_of(oldest, keep0 + j, slots) * ld;
                 load_slab<T, ITER>(col, base, n, in_range, cv[u]);
             }
         }
+    };
+    T cv[2][G][ITER][N];
+    load_group(0, cv[0]);
+    for (int j0 = 0; j0 <= nkept; j0 += 2 * G) {
 #pragma unroll
-        for (int u = 0; u < kGroup; ++u) {
-            const int j = j0 + u;
-            if (j < nkept) {
+        for (int h = 0; h < 2; ++h) {
+            const int jg = j0 + h * G;
+            if (jg > nkept) break;
+            if (jg + G <= nkept) load_group(jg + G, cv[h ^ 1]);
+            double acc[G];
 #pragma unroll
-                for (int it = 0; it < ITER; ++it)
+            for (int u = 0; u < G; ++u) acc[u] = 0.0;
 #pragma unroll
-                    for (int k = 0; k < N; ++k)
-                        acc[u] = fma((double)cv[u][it][k], (double)xv[it][k], acc[u]);
-            } else if (j == nkept) {
+            for (int u = 0; u < G; ++u) {
+                const int j = jg + u;
+                if (j < nkept) {
 #pragma unroll
-                for (int it = 0; it < ITER; ++it)
+                    for (int it = 0; it < ITER; ++it)
 #pragma unroll
-                    for (int k = 0; k < N; ++k)
-                        acc[u] = fma((double)xv[it][k], (double)xv[it][k], acc[u]);
+                        for (int k = 0; k < N; ++k)
+                            acc[u] = fma((double)cv[h][u][it][k], (double)xv[it][k], acc[u]);
+                } else if (j == nkept) {
+#pragma unroll
+                    for (int it = 0; it < ITER; ++it)
+#pragma unroll
+                        for (int k = 0; k < N; ++k)
+                            acc[u] = fma((double)xv[it][k], (double)xv[it][k], acc[u]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                const double v = wave_sum(acc[u]);
+                if (lane == 0 && jg + u <= nkept) red[wave][jg + u] = v;
             }
         }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j <= nkept; j += kThreads) {
+        double s = red[0][j];
 #pragma unroll
-        for (int u = 0; u < kGroup; ++u) {
-            const double v = wave_sum(acc[u]);
-            if (lane == 0) red[wave][u] = v;
-        }
-        __syncthreads();
-        if (threadIdx.x < kGroup && j0 + (int)threadIdx.x <= nkept) {
-            double s = red[0][threadIdx.x];
-#pragma unroll
-            for (int w = 1; w < kWaves; ++w) s += red[w][threadIdx.x];
-            partials[(int64_t)(j0 + threadIdx.x) * nblk + blk] = s;
-        }
-        __syncthreads();
+        for (int w = 1; w < kWaves; ++w) s += red[w][j];
+        partials[(int64_t)j * nblk + blk] = s;
     }
 }
 
