@@ -41,7 +41,9 @@
  *     the calling thread's last error is returned by dmd_last_error().
  *   * "stream" arguments are hipStream_t values passed as void* (NULL = the
  *     null stream).  Work on one handle is serialised in call order across
- *     all streams it is given.
+ *     all streams it is given, with two exceptions that read only what the
+ *     next push leaves alone: dmd_stream_modes of a dense stream and
+ *     dmd_stream_block_modes may run beside the push that follows them.
  *   * Device pointers are HIP device allocations of the current device of
  *     the handle; host pointers are ordinary host memory.
  *   * The library owns every device buffer it allocates (ring of snapshots,
@@ -333,7 +335,12 @@ int dmd_stream_restore(dmd_stream_t* h, const void* buf, int64_t bytes, void* st
  * n x r_eff complex, leading dimension ld >= n, column order = eigenvalue
  * order).  complex128 for DMD_F64 streams or DMD_PREC_FP64, else complex64.
  * For DMD_C64_CSR streams rows outside the window's union support are zero.
- * Stream-ordered; does not wait.  DMD_E_NOT_READY if no solve was enqueued. */
+ * Dense streams: every solve leaves a copy of its state and mode
+ * coefficients, and the projection reads that copy and the solve's window
+ * only, so that on another stream than the pushes it runs beside the next
+ * push (its Gram update and solves overlap it); the push after that, and
+ * every other later call, is ordered after it.  Stream-ordered; does not
+ * wait.  DMD_E_NOT_READY if no solve was enqueued. */
 int dmd_stream_modes(dmd_stream_t* h, void* phi, int64_t ld, void* stream);
 
 /* POD modes U = X V Sigma^-1 (n x r_eff, leading dimension ld >= n; double for

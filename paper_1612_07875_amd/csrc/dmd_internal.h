@@ -207,6 +207,10 @@ struct ProjectArgs {
     int buildup;           // partial windows (window_cols): X_sub has window_cols columns
 };
 hipError_t launch_project(const ProjectArgs& a, hipStream_t s);
+// Copies a solve's state and its mode coefficients (bytes, a multiple of 16)
+// into a snapshot that later projections read.
+hipError_t launch_snapshot(const DevState* st, DevState* st_out, const void* B, void* B_out, size_t bytes,
+                           hipStream_t s);
 // Grouped FP32 projections of many streams in one launch.
 hipError_t launch_project_grouped(const ProjectArgs* items, const int* blk_start, int nitems, int total_blocks,
                                   hipStream_t s);

@@ -164,6 +164,17 @@ struct dmd_stream {
     bool proj_pending[2] = {false, false};
     int64_t block_seq = 0;        // block pushes so far
     int last_packed = -1;         // parity packed by the latest push, -1 if none
+    // Dense streams: each solve leaves a copy of its state and of its mode
+    // coefficients in snapshot parity snap_seq & 1, so that dmd_stream_modes
+    // of one solve can run beside the next push (which rewrites both).
+    DevState* snap_st = nullptr;  // two DevStates
+    char* snap_B = nullptr;       // two copies of Bphi
+    size_t snap_B_bytes = 0;
+    int64_t snap_seq = 0;
+    int snap_par = -1;            // parity of the latest solve's snapshot, -1 if stale
+    hipEvent_t ev_sproj[2] = {nullptr, nullptr};
+    hipStream_t sproj_stream[2] = {nullptr, nullptr};
+    bool sproj_pending[2] = {false, false};
     // Spatial -> Fourier ingest (sparse streams): grid, support and tables
     int four_H = 0, four_W = 0, four_nkeep = 0, four_nkx = 0;
     int32_t* f_idx = nullptr;     // flattened support indices, increasing
@@ -199,11 +210,32 @@ hipError_t begin(dmd_stream* h, hipStream_t s) {
         hipError_t e = hipStreamWaitEvent(s, h->ev_last, 0);
         if (e != hipSuccess) return e;
     }
-    for (int p = 0; p < 2; ++p)
+    for (int p = 0; p < 2; ++p) {
         if (h->proj_pending[p] && h->proj_stream[p] != s) {
             hipError_t e = hipStreamWaitEvent(s, h->ev_proj[p], 0);
             if (e != hipSuccess) return e;
         }
+        if (h->sproj_pending[p] && h->sproj_stream[p] != s) {
+            hipError_t e = hipStreamWaitEvent(s, h->ev_sproj[p], 0);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+// A single push whose solve will write snapshot parity p: after everything
+// but the modes of the previous solve (parity 1 - p), which read the window
+// of that solve (not the slot this push writes) and its snapshot only.
+hipError_t begin_single(dmd_stream* h, hipStream_t s, int p) {
+    if (h->has_last && h->last_stream != s) {
+        hipError_t e = hipStreamWaitEvent(s, h->ev_last, 0);
+        if (e != hipSuccess) return e;
+    }
+    for (int q = 0; q < 2; ++q)
+        if (h->proj_pending[q] && h->proj_stream[q] != s) {
+            hipError_t e = hipStreamWaitEvent(s, h->ev_proj[q], 0);
+            if (e != hipSuccess) return e;
+        }
+    if (h->sproj_pending[p] && h->sproj_stream[p] != s) return hipStreamWaitEvent(s, h->ev_sproj[p], 0);
     return hipSuccess;
 }
 // A block push of parity p: after everything but the projection of the
@@ -214,6 +246,11 @@ hipError_t begin_block(dmd_stream* h, hipStream_t s, int p) {
         hipError_t e = hipStreamWaitEvent(s, h->ev_last, 0);
         if (e != hipSuccess) return e;
     }
+    for (int q = 0; q < 2; ++q)
+        if (h->sproj_pending[q] && h->sproj_stream[q] != s) {
+            hipError_t e = hipStreamWaitEvent(s, h->ev_sproj[q], 0);
+            if (e != hipSuccess) return e;
+        }
     if (h->proj_pending[p] && h->proj_stream[p] != s) return hipStreamWaitEvent(s, h->ev_proj[p], 0);
     return hipSuccess;
 }
@@ -242,13 +279,15 @@ void free_all(dmd_stream* h) {
                     h->Bbg, h->bpartial, h->gblock, h->bflag, h->sh_dev, h->sh_V, h->sh_At, h->sh_W, h->sh_work,
                     h->sh_Vfull, h->sh_Bphi, h->sh_Bpod, h->cfrag, h->bdesc, h->solve_tbl,
                     h->f_idx, h->f_ky, h->f_col, h->f_kx, h->f_twW, h->f_twH, h->f_R, h->f_val,
-                    h->upos, h->ulist, h->ucount, h->ublock};
+                    h->upos, h->ulist, h->ucount, h->ublock, h->snap_st, h->snap_B};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (h->res_host) (void)hipHostFree(h->res_host);
     if (h->sh_host) (void)hipHostFree(h->sh_host);
     if (h->ev_last) (void)hipEventDestroy(h->ev_last);
     for (hipEvent_t e : h->ev_proj)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : h->ev_sproj)
         if (e) (void)hipEventDestroy(e);
     if (h->ev_solved) (void)hipEventDestroy(h->ev_solved);
 }
@@ -353,12 +392,21 @@ void fill_project_args(const dmd_stream* h, dmd::ProjectArgs& a, void* out, int6
 int enqueue_solve(dmd_stream* h, hipStream_t s) {
     h->last_block_k = 0;
     h->last_packed = -1;
+    h->snap_par = -1;
     dmd::SolveArgs a;
     fill_solve_args(h, a);
     HIP_TRY(timed("solve_sym", s, [&] {
         return h->use_trid ? dmd::launch_solve_trid(a, s) : dmd::launch_solve_sym(a, s);
     }));
     HIP_TRY(timed("solve_eig", s, [&] { return dmd::launch_solve_eig(a, s); }));
+    if (h->snap_st) {
+        // every caller has waited for the modes of the solve before last (this parity)
+        const int par = (int)(h->snap_seq & 1);
+        HIP_TRY(dmd::launch_snapshot(reinterpret_cast<const DevState*>(h->res_dev), h->snap_st + par, h->Bphi,
+                                     h->snap_B + par * h->snap_B_bytes, h->snap_B_bytes, s));
+        h->snap_par = par;
+        ++h->snap_seq;
+    }
     HIP_TRY(hipEventRecord(h->ev_solved, s));
     h->solve_enqueued = true;
     return DMD_OK;
@@ -522,6 +570,11 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
     ALLOC(h->work, sizeof(double) * cw * 4 * (size_t)M * (M + 1));
     ALLOC(h->Vfull, sizeof(double) * cw * (size_t)m * m);
     ALLOC(h->Bphi, coef * 2 * (size_t)m * r);
+    if (!h->cplx) {
+        h->snap_B_bytes = (coef * 2 * (size_t)m * r + 255) / 256 * 256;
+        ALLOC(h->snap_st, 2 * sizeof(DevState));
+        ALLOC(h->snap_B, 2 * h->snap_B_bytes);
+    }
     ALLOC(h->Bpod, coef * cw * (size_t)m * r);
     ALLOC(h->Bbg, coef * 2 * (size_t)m);
     h->sh_stride = (h->L.bytes + 255) / 256 * 256;
@@ -579,6 +632,7 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
         hipError_t e = hipEventCreateWithFlags(&h->ev_last, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_solved, hipEventDisableTiming);
         for (int p = 0; p < 2 && e == hipSuccess; ++p) e = hipEventCreateWithFlags(&h->ev_proj[p], hipEventDisableTiming);
+        for (int p = 0; p < 2 && e == hipSuccess; ++p) e = hipEventCreateWithFlags(&h->ev_sproj[p], hipEventDisableTiming);
         if (e == hipSuccess) e = hipDeviceSynchronize();
         if (e != hipSuccess) rc = hip_fail(e, "event/sync");
     }
@@ -598,8 +652,10 @@ DMD_API int dmd_stream_destroy(dmd_stream_t* h) {
     if (!h) return DMD_OK;
     DeviceGuard g(h->device);
     if (h->has_last) (void)hipEventSynchronize(h->ev_last);
-    for (int p = 0; p < 2; ++p)
+    for (int p = 0; p < 2; ++p) {
         if (h->proj_pending[p]) (void)hipEventSynchronize(h->ev_proj[p]);
+        if (h->sproj_pending[p]) (void)hipEventSynchronize(h->ev_sproj[p]);
+    }
     free_all(h);
     delete h;
     return DMD_OK;
@@ -608,6 +664,10 @@ DMD_API int dmd_stream_destroy(dmd_stream_t* h) {
 DMD_API int dmd_stream_sync(dmd_stream_t* h) {
     if (int rc = check_handle(h)) return rc;
     DeviceGuard g(h->device);
+    for (int p = 0; p < 2; ++p) {  // projections that run beside later pushes
+        if (h->proj_pending[p]) HIP_TRY(hipEventSynchronize(h->ev_proj[p]));
+        if (h->sproj_pending[p]) HIP_TRY(hipEventSynchronize(h->ev_sproj[p]));
+    }
     DevState st;
     if (int rc = read_state(h, &st)) return rc;
     if (st.rejected_nonfinite > h->reported_nonfinite) {
@@ -641,6 +701,7 @@ DMD_API int dmd_stream_reset(dmd_stream_t* h, void* stream) {
     h->solve_enqueued = false;
     h->last_block_k = 0;
     h->last_packed = -1;
+    h->snap_par = -1;
     HIP_TRY(end(h, s));
     return DMD_OK;
 }
@@ -652,7 +713,8 @@ DMD_API int dmd_stream_push(dmd_stream_t* h, const void* x, void* stream) {
     if ((uintptr_t)x % h->elem_bytes) return fail(DMD_E_INVAL, "snapshot not %d-byte aligned", h->elem_bytes);
     DeviceGuard g(h->device);
     hipStream_t s = as_stream(stream);
-    HIP_TRY(begin(h, s));
+    if (h->opts.auto_solve && h->snap_st) HIP_TRY(begin_single(h, s, (int)(h->snap_seq & 1)));
+    else HIP_TRY(begin(h, s));
     DevState* st = reinterpret_cast<DevState*>(h->res_dev);
     int nblk = 0;
     hipError_t e = timed("gram_columns", s, [&] {
@@ -669,6 +731,7 @@ DMD_API int dmd_stream_push(dmd_stream_t* h, const void* x, void* stream) {
     if (e != hipSuccess) return hip_fail(e, "gram push launch");
     h->last_block_k = 0;
     h->last_packed = -1;
+    h->snap_par = -1;
     if (h->opts.auto_solve)
         if (int rc = enqueue_solve(h, s)) return rc;
     HIP_TRY(end(h, s));
@@ -693,6 +756,7 @@ DMD_API int dmd_stream_push_csr(dmd_stream_t* h, int32_t nnz, const int32_t* idx
     if (e != hipSuccess) return hip_fail(e, "sparse push launch");
     h->last_block_k = 0;
     h->last_packed = -1;
+    h->snap_par = -1;
     if (h->opts.auto_solve)
         if (int rc = enqueue_solve(h, s)) return rc;
     HIP_TRY(end(h, s));
@@ -756,6 +820,7 @@ DMD_API int dmd_stream_push_block(dmd_stream_t* h, const void* X_new, int64_t ld
     HIP_TRY(timed("gram_block", s, [&] { return dmd::launch_gram_block(a, h->elem_bytes == 8, s); }));
     h->last_block_k = 0;
     h->last_packed = -1;
+    h->snap_par = -1;
     if (h->opts.auto_solve) {
         const dmd::SolveArgs* t = h->solve_tbl + (h->kmax - k);
         const bool lds = h->m + (h->m & 1) <= 64;
@@ -1269,6 +1334,7 @@ DMD_API int dmd_stream_restore(dmd_stream_t* h, const void* buf, int64_t bytes, 
     h->solve_enqueued = false;
     h->last_block_k = 0;
     h->last_packed = -1;
+    h->snap_par = -1;
     if (h->opts.auto_solve)
         if (int rc = enqueue_solve(h, s)) return rc;
     HIP_TRY(end(h, s));
@@ -1282,8 +1348,8 @@ static int project(dmd_stream_t* h, void* out, int64_t ld, void* stream, bool mo
     if (!h->solve_enqueued) return fail(DMD_E_NOT_READY, "no solve has been enqueued");
     DeviceGuard g(h->device);
     hipStream_t s = as_stream(stream);
-    HIP_TRY(begin(h, s));
     if (h->cplx) {
+        HIP_TRY(begin(h, s));
         HIP_TRY(timed("csr_project", s, [&] {
             return dmd::launch_csr_project(reinterpret_cast<const DevState*>(h->res_dev), h->ring_idx, h->ring_val,
                                            h->ring_nnz, h->max_nnz, h->m, modes ? 1 : 0,
@@ -1298,6 +1364,20 @@ static int project(dmd_stream_t* h, void* out, int64_t ld, void* stream, bool mo
     }
     dmd::ProjectArgs a;
     fill_project_args(h, a, out, ld, modes);
+    if (modes && h->snap_par >= 0) {
+        // the latest solve's snapshot: after that solve, beside the next push
+        const int par = h->snap_par;
+        if (h->has_last && h->last_stream != s) HIP_TRY(hipStreamWaitEvent(s, h->ev_last, 0));
+        if (h->sproj_pending[par] && h->sproj_stream[par] != s) HIP_TRY(hipStreamWaitEvent(s, h->ev_sproj[par], 0));
+        a.st = h->snap_st + par;
+        a.B = h->snap_B + par * h->snap_B_bytes;
+        HIP_TRY(timed("project_modes", s, [&] { return dmd::launch_project(a, s); }));
+        HIP_TRY(hipEventRecord(h->ev_sproj[par], s));
+        h->sproj_stream[par] = s;
+        h->sproj_pending[par] = true;
+        return DMD_OK;
+    }
+    HIP_TRY(begin(h, s));
     HIP_TRY(timed(modes ? "project_modes" : "project_pod", s, [&] { return dmd::launch_project(a, s); }));
     HIP_TRY(end(h, s));
     return DMD_OK;
@@ -1367,6 +1447,7 @@ DMD_API int dmd_stream_load_window(dmd_stream_t* h, const void* X, int64_t ldx, 
     DevState* st = reinterpret_cast<DevState*>(h->res_dev);
     h->last_block_k = 0;
     h->last_packed = -1;
+    h->snap_par = -1;
     HIP_TRY(dmd::launch_copy_columns(X, ldx, h->ring, h->ld, h->n, ncols, h->elem_bytes == 8, s));
     HIP_TRY(timed("gram_full", s, [&] {
         return dmd::launch_gram_full(h->ring, h->ld, h->n, h->m, h->slots, h->elem_bytes == 8, h->opts.precision,
@@ -1387,6 +1468,7 @@ DMD_API int dmd_stream_resync(dmd_stream_t* h, void* stream) {
     DevState* st = reinterpret_cast<DevState*>(h->res_dev);
     h->last_block_k = 0;
     h->last_packed = -1;
+    h->snap_par = -1;
     HIP_TRY(timed("gram_full", s, [&] {
         return dmd::launch_gram_full(h->ring, h->ld, h->n, h->m, h->slots, h->elem_bytes == 8, h->opts.precision,
                                      h->m + 1, -1, h->gfull, h->G, st, 2, s);
@@ -1784,6 +1866,7 @@ DMD_API int dmd_batch_tick(dmd_batch_t* b, int32_t count, dmd_stream_t* const* s
         h->solve_enqueued = true;
         h->last_block_k = 0;
         h->last_packed = -1;
+        h->snap_par = -1;
         HIP_TRY(end(h, s));
     }
     b->last_stream = s;
