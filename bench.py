@@ -352,12 +352,16 @@ def roofline_of(kernels, bytes_per, source_of, mfma=None, traffic_key=None):
     return out
 
 
-def single_latency(s, frames, t, L, phi):
+def single_latency(s, frames, t, L, phi, dmd):
+    """Push -> modes latency of L single frames on one stream (nothing else
+    running), and the per-kernel times of those frames."""
     import numpy as np
     import torch
     lat = []
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    dmd.profile_enable(True)
+    dmd.profile_reset()
     for _ in range(L):
         e0.record()
         s.push(frames[t])
@@ -366,11 +370,31 @@ def single_latency(s, frames, t, L, phi):
         e1.synchronize()
         lat.append(e0.elapsed_time(e1))
         t += 1
+    dmd.profile_enable(False)
+    kern = kernel_table(dmd, ("gram_columns", "project_modes", "solve_sym", "solve_eig"))
+    dmd.profile_reset()
     if not lat:
-        return None, t
+        return None, t, kern
     lat = np.array(lat)
     return {"p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4),
-            "frames": int(L)}, t
+            "frames": int(L)}, t, kern
+
+
+def gram_alone_line(kern, n, kb):
+    """HBM rate of the streaming Gram updates timed with nothing beside them
+    (the latency runs): one frame ((m+2) n 4 bytes) and, in block mode, one
+    block of kb frames ((m+1+2kb) n 4 bytes)."""
+    out = {}
+    sizes = [("gram_columns", (M + 2) * n * 4)]
+    if kb is not None:
+        sizes.append(("gram_block", (M + 1 + 2 * kb) * n * 4))
+    for name, nbytes in sizes:
+        if name in kern:
+            us = kern[name]["avg_us"]
+            gbs = nbytes / (us * 1e-6) / 1e9
+            out[name] = {"avg_us": round(us, 2), "algorithmic_GBps": round(gbs, 1),
+                         "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
 
 
 def bench_single(args):
@@ -417,7 +441,8 @@ def bench_single(args):
     dmd.profile_reset()
     print(f"[bench] timed {K} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
 
-    latency, t = single_latency(s, frames, t, L, phi)
+    latency, t, alone = single_latency(s, frames, t, L, phi, dmd)
+    gram_alone = gram_alone_line(alone, n, None)
     lam, sig, rc = s.eigs()
     r_eff = lam.size
     info = s.info()
@@ -436,7 +461,7 @@ def bench_single(args):
         "n": n, "m": M, "r": R, "r_eff": int(r_eff), "frames_per_step": 1,
         "precision": precision_note(args)})
     out.update({"roofline": roofline, "kernels": kernels,
-                "gram_GBps": kernels.get("gram_columns", {}).get("algorithmic_GBps"),
+                "gram_GBps": kernels.get("gram_columns", {}).get("algorithmic_GBps"), "gram_alone": gram_alone,
                 "latency_ms": latency, "jacobi_sweeps": int(info.sweeps), "qr_iters": int(info.qr_iters)})
     return out, host_keep
 
@@ -546,6 +571,8 @@ def bench_block(args):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     blat = []
+    dmd.profile_enable(True)
+    dmd.profile_reset()
     for _ in range(LB):
         e0.record()
         s.push_block(frames[t:t + kb])
@@ -554,7 +581,12 @@ def bench_block(args):
         e1.synchronize()
         blat.append(e0.elapsed_time(e1))
         t += kb
-    latency, t = single_latency(s, frames, t, L, phis[0].T)
+    dmd.profile_enable(False)
+    alone = kernel_table(dmd, ("gram_block", "project_block"))
+    dmd.profile_reset()
+    latency, t, alone1 = single_latency(s, frames, t, L, phis[0].T, dmd)
+    alone.update(alone1)
+    gram_alone = gram_alone_line(alone, n, kb)
     info = s.info()
     s.close()
     roofline = block_roofline(kernels, n, kb, r_effs, args.precision)
@@ -565,7 +597,7 @@ def bench_block(args):
         "precision": precision_note(args)})
     blat = np.array(blat) if blat else None
     out.update({"roofline": roofline, "kernels": kernels,
-                "gram_GBps": kernels.get("gram_block", {}).get("algorithmic_GBps"),
+                "gram_GBps": kernels.get("gram_block", {}).get("algorithmic_GBps"), "gram_alone": gram_alone,
                 "block_latency_ms": ({"p50": round(float(np.percentile(blat, 50)), 3),
                                       "p99": round(float(np.percentile(blat, 99)), 3), "blocks": int(LB)}
                                      if blat is not None else None),
