@@ -459,12 +459,14 @@ int dmd_batch_info(dmd_batch_t* b, int32_t* nstreams, int64_t* used_bytes,
 
 /* Process-wide per-kernel timing for diagnostics and roofline measurement.
  * When enabled, every kernel launch of every handle is bracketed by HIP events
- * recorded on its launch stream.  Kernel names: "gram_columns", "gram_finalize", "solve_sym",
- * "solve_eig", "project_modes", "project_pod", "background", "csr_gram",
- * "csr_project", "gram_full", "fourier" (the ingest's two DFT kernels), for block pushes "gram_block" (block Gram pass, reduction and
- * commit), "block_solve" (all windows' solves), "pack_block" (packing the
- * projection inputs) and "project_block" (all windows' modes), and for batch ticks
- * "batch_gram", "batch_solve", "batch_project" (eager ticks) or "batch_graph" (graph ticks).
+ * recorded on its launch stream.  Kernel names: "gram_columns",
+ * "gram_finalize", "solve_sym", "solve_eig", "project_modes", "project_pod",
+ * "background", "csr_gram", "csr_project", "gram_full", "fourier" (the
+ * ingest's two DFT kernels); for block pushes "gram_block" (block Gram pass,
+ * reduction and commit), "block_solve" (all windows' solves), "pack_block"
+ * (packing the projection inputs) and "project_block" (all windows' modes);
+ * for batch ticks "batch_gram", "batch_solve", "batch_project" (eager ticks)
+ * or "batch_graph" (graph ticks).
  * dmd_profile_read waits for the recorded events and returns the number of
  * launches of `kernel` and their summed duration in milliseconds since the
  * last dmd_profile_reset. */
