@@ -541,7 +541,10 @@ void k_solve_sym_grouped(const SolveArgs* __restrict__ items) {
 // --------------------------------------------------------------------------
 // k_solve_eig: one wavefront, A~ (k x k, k <= 32) in LDS
 // --------------------------------------------------------------------------
-constexpr int LDH = kRMax;
+// Column stride of the k x k (k <= kRMax) matrices in LDS: one more than
+// kRMax, so that a row read across lanes (lane = column) spreads over the
+// LDS banks instead of hitting the same one from every lane.
+constexpr int LDH = kRMax + 1;
 
 
 // Real Schur form of the real upper Hessenberg k x k matrix held in the real
