@@ -1410,23 +1410,27 @@ __device__ void solve_trid_body(const SolveArgs& a) {
     __syncthreads();
 
     // ---- 2. eigenvalues: G lanes per eigenvalue, bracket [-1, 1] split into
-    // G+1 parts per iteration until its width is 4 eps (absolute, ||T|| <= 1)
+    // G+1 parts per iteration until its width is at most eps (absolute,
+    // ||T|| <= 1).  The Sturm counts are FP64 work on one CU, so about 256
+    // lanes (G = 256 / m) finish first: more lanes per eigenvalue save
+    // iterations but cost more in total than they save.
     {
         int np2 = 1;
         while (np2 < n) np2 <<= 1;
-        int G = NT / np2;
+        int G = 256 / np2;
         G = G > 64 ? 64 : (G < 1 ? 1 : G);
         const int gi = tid / G, gl = tid % G;
         const int gshift = (tid & 63) / G * G;  // first lane of the group inside the wavefront
         int iters = 1;
         {
             double w = 2.0;
-            while (w > 4.0 * kEps) {
+            while (w > kEps) {
                 w /= (double)(G + 1);
                 ++iters;
             }
         }
         double lo = -1.0 - 4.0 * kEps, hi = 1.0 + 4.0 * kEps;
+        if (64 * wv < G * n)  // wavefronts with no eigenvalue skip the search
         for (int it = 0; it < iters; ++it) {
             const double x = lo + (hi - lo) * (double)(gl + 1) / (double)(G + 1);
             const bool above = gi < n ? sturm_count(s_d, s_e2, n, x) > gi : true;
