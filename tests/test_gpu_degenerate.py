@@ -83,3 +83,33 @@ def test_geometric_window_smallest_sizes(n, dtype):
         assert abs(lam[0] - rho) < tol, lam
         phi = s.modes().cpu().numpy()[:, 0]
         assert metrics.phase_aligned_relerr(phi / np.linalg.norm(phi), v / np.linalg.norm(v)) < tol
+
+
+def test_sparse_windows_with_empty_snapshots():
+    """Sparse frames with no coefficients (zero snapshots) inside the window:
+    the window's DMD equals the oracle's on the densified frames; a window of
+    empty frames keeps no mode."""
+    import gen
+    import oracle
+    from test_gpu_sparse import check_sparse_window
+    dmd = _dmd()
+    fs = gen.FourierSparse(side=40, nnz=50, redraw=0.1)
+    m, r = 10, 4
+    empty_i = torch.zeros(0, dtype=torch.int32, device="cuda")
+    empty_v = torch.zeros(0, dtype=torch.complex64, device="cuda")
+    dense = []
+    with dmd.Stream(fs.n, m, r, dtype="c64_csr", max_nnz=60) as s:
+        for t in range(m + 6):
+            if t % 5 == 3:
+                s.push_csr(empty_i, empty_v)
+                dense.append(np.zeros(fs.n, dtype=np.complex128))
+            else:
+                idx, val = fs.frame(t)
+                s.push_csr(torch.from_numpy(idx).cuda(), torch.from_numpy(val).cuda())
+                dense.append(oracle.densify(idx, val, fs.n))
+            if t >= m:
+                check_sparse_window(s, np.stack(dense[t - m:t + 1], axis=1), m, r)
+        for _ in range(m + 1):
+            s.push_csr(empty_i, empty_v)
+        lam, sig, rc = s.eigs()
+        assert rc == dmd.W_RANK and lam.size == 0
