@@ -235,10 +235,11 @@ def test_block_full_hd_video():
             check_phi(phis[w].cpu().numpy().T, ref, perm, lam.size, 2e-4)
 
 
-@pytest.mark.parametrize("m,r,kb", [(160, 24, 32), (200, 32, 48)])
+@pytest.mark.parametrize("m,r,kb", [(160, 24, 32), (200, 32, 48), (64, 20, 64), (64, 32, 64)])
 def test_block_modes_large_windows(m, r, kb):
-    """Windows beyond the default shapes (m > 64, k up to 48): every window's
-    modes from the one-pass block projection must match the oracle."""
+    """Windows beyond the default shapes (m > 64, k up to the largest block
+    of 64 frames): the first, a middle and the last window's modes from the
+    one-pass block projection must match the oracle."""
     dmd = _dmd()
     H, W = 100, 130
     n = H * W
