@@ -1,0 +1,81 @@
+"""The serving loop end to end on the GPU: frames of several streams arrive
+at random times, each loop iteration advances every admitted stream with a
+pending frame in one batched tick (with its modes), streams over the HBM
+budget wait until others close.  Every stream's results -- served in the mix,
+admitted late or not -- must equal the same frames pushed through a stream
+of its own, bit for bit (same kernels, same per-stream order), and match
+the oracle."""
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from oracle import metrics
+
+pytestmark = pytest.mark.gpu
+
+SPECS = [(6000, 8, 4), (9000, 16, 8), (4000, 24, 10), (12000, 16, 6), (7000, 8, 3), (5000, 12, 5)]
+
+
+def _dmd():
+    import paper_1612_07875_amd as dmd
+    return dmd
+
+
+def test_served_equals_alone_with_admission_queue():
+    dmd = _dmd()
+    from paper_1612_07875_amd.serve import GPUExecutor, Server, StreamSpec
+    T = {sid: m + 6 for sid, (n, m, r) in enumerate(SPECS)}
+    host = {sid: np.stack([gen.MixStream(stream=500 + sid, n=n, m=0, r=0, kind="video").frame(t)
+                           for t in range(T[sid])]) for sid, (n, m, r) in enumerate(SPECS)}
+    frames = {sid: torch.from_numpy(h).cuda() for sid, h in host.items()}
+    # footprints: the budget admits the first four streams only
+    foot = []
+    for n, m, r in SPECS:
+        with dmd.Stream(n, m, r) as s:
+            foot.append(int(s.info().device_bytes))
+    budget = sum(foot[:4]) + 1024
+    ex = GPUExecutor(frames, hbm_budget=budget, modes=True)
+    srv = Server(ex)
+    admitted = [srv.open(sid, StreamSpec(n, m, r)) for sid, (n, m, r) in enumerate(SPECS)]
+    assert admitted == [True, True, True, True, False, False]
+    rng = np.random.default_rng(3)
+    arrivals = sorted((float(rng.uniform(0.0, 0.05)), sid) for sid in range(len(SPECS)) for _ in range(T[sid]))
+    srv.run(arrivals)
+    results = {}
+
+    def grab(sid):
+        s = ex.streams[sid]
+        lam, sig, rc = s.eigs()
+        results[sid] = (lam, sig, ex.modes[sid].cpu().numpy()[:, :lam.size], s.gram())
+
+    for sid in range(4):
+        grab(sid)
+    for sid in (4, 5):
+        assert sid not in ex.streams                     # still waiting for room
+    srv.close(0)
+    srv.close(1)                                          # room for the two waiting streams
+    assert 4 in ex.streams and 5 in ex.streams
+    srv.run([])                                           # their queued frames
+    for sid in (4, 5):
+        grab(sid)
+    ex.shutdown()
+    torch.cuda.synchronize()
+    for sid, (n, m, r) in enumerate(SPECS):
+        with dmd.Stream(n, m, r) as s:
+            for t in range(T[sid]):
+                s.push(frames[sid][t])
+            lam, sig, _ = s.eigs()
+            phi = s.modes().cpu().numpy()[:, :lam.size]
+            G = s.gram()
+        a = results[sid]
+        assert np.array_equal(a[0], lam) and np.array_equal(a[1], sig), sid
+        assert np.array_equal(a[2], phi), sid
+        assert np.array_equal(a[3], G), sid
+        W = oracle.as_fp64(host[sid][-(m + 1):].T)
+        ref = oracle.exact_dmd(W[:, :m], W[:, 1:], r)
+        err, _ = metrics.eig_relerr(lam, ref.lam)
+        kap2 = (ref.sigma[0] / ref.sigma[:lam.size]) ** 2
+        assert err.max() < max(1e-8, 1e-15 * kap2.max()), (sid, err.max())
