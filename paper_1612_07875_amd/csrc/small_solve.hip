@@ -1317,7 +1317,8 @@ __device__ void solve_trid_body(const SolveArgs& a) {
     __shared__ double s_d[kMaxM], s_e[kMaxM], s_e2[kMaxM], s_lam[kMaxM];
     __shared__ S s_tau[kMaxM], s_v0[kMaxM], s_v1[kMaxM], s_p[kMaxM];
     __shared__ double s_sig[kMaxM];
-    __shared__ int s_perm[kMaxM], s_sel[kRMax];
+    __shared__ int s_perm[kMaxM], s_sel[kRMax], s_tw[kRMax];
+    __shared__ double s_zsc[kRMax];
     __shared__ double s_scale;
 
     // storage: A (n x ld) in LDS for small windows, else in the workspace;
@@ -1463,13 +1464,19 @@ __device__ void solve_trid_body(const SolveArgs& a) {
     }
     __syncthreads();
 
-    // ---- 3. eigenvectors of T by twisted factorizations, one lane per vector
+    // ---- 3. eigenvectors of T by twisted factorizations.  The forward
+    // L D L^T (wavefront 0, lane v) and backward U D U^T (wavefront 1, lane v)
+    // factorizations of T - lambda_v I run side by side; the twist index
+    // (argmin |gamma_k|, lowest k on ties) is a wavefront reduction; the two
+    // one-term recurrences from the twist run side by side again; the norm is
+    // summed in the order of a single serial pass (up, then down), so the
+    // vectors do not depend on how the work is split.
+    double* Lm = LU;                   // Lm[i * nv + v], i < n-1
+    double* Um = LU + (size_t)n * nv;  // Um[i * nv + v], 1 <= i < n
+    const double tiny = 0x1p-900;
     if (tid < nv) {
         const int v = tid;
         const double lam = s_lam[s_sel[v]];
-        double* Lm = LU;                   // Lm[i * nv + v], i < n-1
-        double* Um = LU + (size_t)n * nv;  // Um[i * nv + v], 1 <= i < n
-        const double tiny = 0x1p-900;
         double Dp = s_d[0] - lam;
         for (int i = 0; i + 1 < n; ++i) {
             if (Dp == 0.0) Dp = tiny;
@@ -1477,6 +1484,9 @@ __device__ void solve_trid_body(const SolveArgs& a) {
             Lm[(size_t)i * nv + v] = l;
             Dp = s_d[i + 1] - lam - l * s_e[i];
         }
+    } else if (tid >= 64 && tid < 64 + nv) {
+        const int v = tid - 64;
+        const double lam = s_lam[s_sel[v]];
         double Dm = s_d[n - 1] - lam;
         for (int i = n - 1; i >= 1; --i) {
             if (Dm == 0.0) Dm = tiny;
@@ -1484,10 +1494,14 @@ __device__ void solve_trid_body(const SolveArgs& a) {
             Um[(size_t)i * nv + v] = u;
             Dm = s_d[i - 1] - lam - u * s_e[i - 1];
         }
-        // twist index: argmin |gamma_k|, gamma_k = (d_k - lam) - L_{k-1} e_{k-1} - U_{k+1} e_k
+    }
+    __syncthreads();
+    // twist index: argmin |gamma_k|, gamma_k = (d_k - lam) - L_{k-1} e_{k-1} - U_{k+1} e_k
+    for (int v = wv; v < nv; v += NT / 64) {
+        const double lam = s_lam[s_sel[v]];
         double best = 1e308;
         int tw = 0;
-        for (int k = 0; k < n; ++k) {
+        for (int k = lane; k < n; k += 64) {
             double g = s_d[k] - lam;
             if (k > 0) g -= Lm[(size_t)(k - 1) * nv + v] * s_e[k - 1];
             if (k + 1 < n) g -= Um[(size_t)(k + 1) * nv + v] * s_e[k];
@@ -1496,23 +1510,56 @@ __device__ void solve_trid_body(const SolveArgs& a) {
                 tw = k;
             }
         }
-        // z_tw = 1, z_i = -L_i z_{i+1} (i < tw), z_{i+1} = -U_{i+1} z_i (i >= tw); into Z, normalized
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double ob = __shfl_xor(best, off, 64);
+            const int ot = __shfl_xor(tw, off, 64);
+            if (ob < best || (ob == best && ot < tw)) {
+                best = ob;
+                tw = ot;
+            }
+        }
+        if (lane == 0) s_tw[v] = tw;
+    }
+    __syncthreads();
+    // z_tw = 1, z_i = -L_i z_{i+1} (i < tw; wavefront 0), z_{i+1} = -U_{i+1} z_i (i >= tw; wavefront 1)
+    if (tid < nv) {
+        const int v = tid, tw = s_tw[v];
         S* zc = Z + (size_t)v * ld;
-        double z = 1.0, nrm2 = 1.0;
+        double z = 1.0;
         zc[tw] = SC::one();
         for (int i = tw - 1; i >= 0; --i) {
             z = -Lm[(size_t)i * nv + v] * z;
-            nrm2 += z * z;
             zc[i] = SC::fromc(mkc(z));
         }
-        z = 1.0;
+    } else if (tid >= 64 && tid < 64 + nv) {
+        const int v = tid - 64, tw = s_tw[v];
+        S* zc = Z + (size_t)v * ld;
+        double z = 1.0;
         for (int i = tw; i + 1 < n; ++i) {
             z = -Um[(size_t)(i + 1) * nv + v] * z;
-            nrm2 += z * z;
             zc[i + 1] = SC::fromc(mkc(z));
         }
-        const double sc = rsqrt_acc(nrm2);
-        for (int i = 0; i < n; ++i) zc[i] = zc[i] * sc;
+    }
+    __syncthreads();
+    if (tid < nv) {
+        const int v = tid, tw = s_tw[v];
+        const S* zc = Z + (size_t)v * ld;
+        double nrm2 = 1.0;
+        for (int i = tw - 1; i >= 0; --i) {
+            const double z = SC::re(zc[i]);
+            nrm2 += z * z;
+        }
+        for (int i = tw; i + 1 < n; ++i) {
+            const double z = SC::re(zc[i + 1]);
+            nrm2 += z * z;
+        }
+        s_zsc[v] = rsqrt_acc(nrm2);
+    }
+    __syncthreads();
+    for (int idx = tid; idx < n * nv; idx += NT) {
+        const int i = idx % n, v = idx / n;
+        S* zc = Z + (size_t)v * ld;
+        zc[i] = zc[i] * s_zsc[v];
     }
     __syncthreads();
     // the eigenvectors move into LDS (over the multipliers) for the rest of the work
