@@ -455,6 +455,14 @@ int dmd_batch_tick(dmd_batch_t* b, int32_t count, dmd_stream_t* const* streams,
 int dmd_batch_info(dmd_batch_t* b, int32_t* nstreams, int64_t* used_bytes,
                    int64_t* budget);
 
+/* ------------------------------------------------------------ environment */
+
+/* DMD_GRAM_ITER = 1, 2 or 4 (read at every push): 16-byte loads per thread
+ * and window column in one workgroup of the one-column Gram update, instead
+ * of the default chosen from n (the largest that still gives one workgroup
+ * per CU).  Results differ from the default only in the order of the FP64
+ * partial sums. */
+
 /* ------------------------------------------------------------ kernel timing */
 
 /* Process-wide per-kernel timing for diagnostics and roofline measurement.
