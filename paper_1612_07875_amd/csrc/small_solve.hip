@@ -80,6 +80,12 @@ __device__ __forceinline__ double rcp_fast(double x) {
     const double y = __builtin_amdgcn_rcp(x);
     return fma(y, fma(-x, y, 1.0), y);
 }
+// 1/x to full FP64 accuracy (estimate plus two Newton steps).
+__device__ __forceinline__ double rcp_acc(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(y, fma(-x, y, 1.0), y);
+    return fma(y, fma(-x, y, 1.0), y);
+}
 
 // Rotation (c, s) with c^2 + s^2 = 1 to working precision that annihilates
 // the off-diagonal of the real 2x2 [[a, g], [g, b]] (g > 0): t = tan(phi) is
@@ -611,12 +617,16 @@ __device__ void real_schur(cplx* H, cplx* Z, int k, int lane, int max_iter, doub
                 z = kk + 2 <= nn ? h(kk + 2, kk - 1) : 0.0;
             }
             const bool three = kk + 2 <= nn;
-            const double nrm = sqrt(x * x + y * y + z * z);
+            // (the bulge chase is a chain of dependent FP64 steps: the norm and
+            // 2 / v^T v come from the hardware estimates plus Newton steps,
+            // shorter chains than the correctly rounded square root and division)
+            const double s2 = x * x + y * y + z * z;
+            const double nrm = s2 > 0.0 ? s2 * rsqrt_acc(s2) : 0.0;
             // reflector P = I - tau v v^T, v = (x - alpha, y, z), P (x, y, z) = (alpha, 0, 0)
             const double alpha = x > 0.0 ? -nrm : nrm;
             const double v0 = x - alpha;
             const double vtv = v0 * v0 + y * y + z * z;
-            const double tau = vtv > 0.0 ? 2.0 / vtv : 0.0;
+            const double tau = vtv > 0.0 ? 2.0 * rcp_acc(vtv) : 0.0;
             __syncthreads();
             if (tau != 0.0) {
                 // rows kk .. kk+2 over columns jlo .. k-1 (lane = column)
