@@ -1109,21 +1109,36 @@ __device__ void solve_eig_body(const SolveArgs& a) {
         a.amp[2 * lane] = s_rhs[lane].re;
         a.amp[2 * lane + 1] = s_rhs[lane].im;
     }
-    if (lane == 0) {
-        double best = 0.0;
-        int bi = -1;
-        for (int q = 0; q < k; ++q) {
-            const cplx lq = s_ls[q];
+    // background mode: lane q evaluates |log lambda_q|, then the smallest
+    // (lowest q on ties) over the lanes with lambda_q != 0; mode 0 if none
+    {
+        bool ok = false;
+        double d = 0.0;
+        if (lane < k) {
+            const cplx lq = s_ls[lane];
             const double mod = cabs(lq);
-            if (!(mod > 0.0)) continue;
-            const double d = hypot(log(mod), atan2(lq.im, lq.re));
-            if (bi < 0 || d < best) {
-                best = d;
-                bi = q;
+            if (mod > 0.0) {
+                ok = true;
+                d = hypot(log(mod), atan2(lq.im, lq.re));
             }
         }
-        if (bi < 0) bi = 0;
-        s_bg = bi;
+        int bi = lane;
+        for (int off = 32; off >= 1; off >>= 1) {
+            const bool ook = __shfl_xor((int)ok, off, 64) != 0;
+            const double od = __shfl_xor(d, off, 64);
+            const int oi = __shfl_xor(bi, off, 64);
+            const bool take = ook && (!ok || od < d || (od == d && oi < bi));
+            if (take) {
+                ok = true;
+                d = od;
+                bi = oi;
+            }
+        }
+        if (lane == 0) s_bg = ok ? bi : 0;
+    }
+    __syncthreads();
+    if (lane == 0) {
+        const int bi = s_bg;
         st->bg_index = bi;
         // lambda^m = |lambda|^m e^{i m arg lambda}
         const cplx lb = s_ls[bi];
@@ -1148,14 +1163,9 @@ __device__ void solve_eig_body(const SolveArgs& a) {
             }
             vrow[p] = v;
         }
-        for (int q = 0; q < k; ++q) {
-            cplx acc0 = mkc(0.0), acc1 = mkc(0.0);
-#pragma unroll
-            for (int p = 0; p < kRMax; p += 2) {
-                if (p < k) acc0 = acc0 + vrow[p] * Y[p + q * LDH];
-                if (p + 1 < k) acc1 = acc1 + vrow[p + 1] * Y[p + 1 + q * LDH];
-            }
-            const cplx acc = acc0 + acc1;
+        // two columns q at a time: four independent accumulation chains (the
+        // sums of each column keep their order)
+        auto emit = [&](int q, const cplx& acc) {
             if (q == bgq && a.Bbg) {
                 // background coefficients beta_i = C[i][bg] b_bg lambda_bg^m
                 const cplx bt = acc * fbg;
@@ -1177,6 +1187,23 @@ __device__ void solve_eig_body(const SolveArgs& a) {
                 B[o] = (float)acc.re;
                 B[o + 1] = (float)acc.im;
             }
+        };
+        for (int q = 0; q < k; q += 2) {
+            const int q1 = q + 1 < k ? q + 1 : q;
+            cplx a0 = mkc(0.0), a1 = mkc(0.0), b0 = mkc(0.0), b1 = mkc(0.0);
+#pragma unroll
+            for (int p = 0; p < kRMax; p += 2) {
+                if (p < k) {
+                    a0 = a0 + vrow[p] * Y[p + q * LDH];
+                    b0 = b0 + vrow[p] * Y[p + q1 * LDH];
+                }
+                if (p + 1 < k) {
+                    a1 = a1 + vrow[p + 1] * Y[p + 1 + q * LDH];
+                    b1 = b1 + vrow[p + 1] * Y[p + 1 + q1 * LDH];
+                }
+            }
+            emit(q, a0 + a1);
+            if (q + 1 < k) emit(q + 1, b0 + b1);
         }
     }
     if (lane == 0) {
@@ -1203,8 +1230,9 @@ void k_solve_eig_grouped(const SolveArgs* __restrict__ items) {
 // dependent steps instead of O(m) per Jacobi sweep, for large windows:
 //   1. Householder reduction of xtx to a real symmetric tridiagonal T
 //      (Hermitian input: complex reflectors, T still real);
-//   2. all eigenvalues of T by multisection: NT / m lanes per eigenvalue
-//      evaluate Sturm counts at equally spaced points of its bracket;
+//   2. all eigenvalues of T by multisection: 256 / m lanes per eigenvalue
+//      (m rounded up to a power of two) evaluate Sturm counts at equally
+//      spaced points of its bracket;
 //   3. eigenvectors of T for the r largest |eigenvalues| by twisted
 //      factorizations (forward L D L^T and backward U D U^T of T - lambda I,
 //      twist where |gamma_k| is smallest, then the two one-term recurrences),
