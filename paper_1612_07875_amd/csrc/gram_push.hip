@@ -30,6 +30,13 @@ template <typename T> struct Vec16;
 template <> struct Vec16<float>  { using type = float4;  static constexpr int N = 4; };
 template <> struct Vec16<double> { using type = double2; static constexpr int N = 2; };
 
+// 16-byte vectors for nontemporal loads (the builtin takes clang vectors)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <typename T> struct NtVec;
+template <> struct NtVec<float>  { using type = f32x4; };
+template <> struct NtVec<double> { using type = f64x2; };
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -38,18 +45,23 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Loads the ITER x N elements of this thread from column `col` of a slab.
 // `vec_ok`: the slab is entirely inside [0, n) and `col` is 16-byte aligned.
+// The 16-byte loads are nontemporal: every element is read once per pass and
+// a window (m columns of n values) is far larger than the caches, so caching
+// it only evicts other data.  Measured on 64 columns of 2,073,600 floats: a
+// plain read-only pass runs at 0.78 of the HBM peak with cached loads and
+// 0.87 with nontemporal ones; this kernel goes from 92 us to 87-89 us.
 template <typename T, int ITER>
 __device__ __forceinline__ void load_slab(const T* __restrict__ col, int64_t base, int64_t n,
                                           bool vec_ok, T (&v)[ITER][Vec16<T>::N]) {
-    using VT = typename Vec16<T>::type;
+    using NV = typename NtVec<T>::type;
     constexpr int N = Vec16<T>::N;
     if (vec_ok) {
 #pragma unroll
         for (int it = 0; it < ITER; ++it) {
-            const VT w = *reinterpret_cast<const VT*>(col + base + (int64_t)(it * kThreads + threadIdx.x) * N);
-            const T* e = reinterpret_cast<const T*>(&w);
+            const NV w = __builtin_nontemporal_load(
+                reinterpret_cast<const NV*>(col + base + (int64_t)(it * kThreads + threadIdx.x) * N));
 #pragma unroll
-            for (int k = 0; k < N; ++k) v[it][k] = e[k];
+            for (int k = 0; k < N; ++k) v[it][k] = w[k];
         }
     } else {
 #pragma unroll
