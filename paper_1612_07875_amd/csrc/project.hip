@@ -122,7 +122,8 @@ __device__ void project_body(const ProjectArgs& a, int blk, T* stage) {
             const bool cin = col < m;
             const TX* cp = ring + (int64_t)slot_of(oldest, a.first + (cin ? col : 0), a.slots) * a.ld;
 #pragma unroll
-            for (int rt = 0; rt < 4; ++rt) av[buf][g][rt] = (cin && rin[rt]) ? (T)cp[row0 + 16 * rt + li] : T(0);
+            for (int rt = 0; rt < 4; ++rt)
+                av[buf][g][rt] = (cin && rin[rt]) ? (T)__builtin_nontemporal_load(&cp[row0 + 16 * rt + li]) : T(0);
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const int c = 16 * nt + li;
@@ -150,6 +151,9 @@ __device__ void project_body(const ProjectArgs& a, int blk, T* stage) {
         mma_group(1);
     }
 
+    // window columns are read and modes written nontemporally: each is
+    // touched once per call, and the solves of the next push, which may run
+    // beside this kernel, keep their data cached
     T* out = reinterpret_cast<T*>(a.out);
     T* sw = stage + wave * 64 * OLD;
     const int64_t row = row0 + lane;  // the row this lane stores
@@ -170,8 +174,8 @@ __device__ void project_body(const ProjectArgs& a, int blk, T* stage) {
                     const int c = 16 * nt + cc;
                     if (c < kcols) {
                         const int64_t o = 2 * (row + (int64_t)(c >> 1) * a.ldo);
-                        out[o] = sw[lane * OLD + cc];
-                        out[o + 1] = sw[lane * OLD + cc + 1];
+                        __builtin_nontemporal_store(sw[lane * OLD + cc], &out[o]);
+                        __builtin_nontemporal_store(sw[lane * OLD + cc + 1], &out[o + 1]);
                     }
                 }
             } else {
@@ -270,8 +274,8 @@ __device__ void project_body_bf3(const ProjectArgs& a, int blk, float* stage) {
                     const int c = 16 * nt + cc;
                     if (c < kcols) {
                         const int64_t o = 2 * (row + (int64_t)(c >> 1) * a.ldo);
-                        out[o] = sw[lane * OLD + cc];
-                        out[o + 1] = sw[lane * OLD + cc + 1];
+                        __builtin_nontemporal_store(sw[lane * OLD + cc], &out[o]);
+                        __builtin_nontemporal_store(sw[lane * OLD + cc + 1], &out[o + 1]);
                     }
                 }
             } else {
@@ -519,7 +523,10 @@ void k_project_block(BlockProjectArgs a) {
         // i.e. the real (li even) or imaginary (li odd) part of complex column
         // 8 nt + li/2.  One swap with the neighbouring lane gives the even lane
         // rows v = 0, 1 and the odd lane rows v = 2, 3 as whole complex values:
-        // two consecutive rows, one 16-byte store.
+        // two consecutive rows, one 16-byte store.  The stores are
+        // nontemporal: the modes are not read again here, and streaming them
+        // past the caches keeps the window columns and the solves' data of
+        // the next block, which run beside this kernel, cached.
         float2* out = a.out + (int64_t)w * a.ldw;
         const bool odd = li & 1;
         const int r_eff = kc >> 1;
@@ -537,7 +544,8 @@ void k_project_block(BlockProjectArgs a) {
                     const int64_t row = row0 + 16 * rt + 4 * lk + (odd ? 2 : 0);
                     float2* o = out + row + (int64_t)j * a.ldo;
                     if constexpr (decltype(fast)::value) {
-                        if (j < r_eff) *reinterpret_cast<float4*>(o) = val;
+                        if (j < r_eff)
+                            __builtin_nontemporal_store(v4f{val.x, val.y, val.z, val.w}, reinterpret_cast<v4f*>(o));
                     } else if (j < r_eff && row < a.n) {
                         o[0] = float2{val.x, val.y};
                         if (row + 1 < a.n) o[1] = float2{val.z, val.w};
@@ -815,7 +823,8 @@ void k_project_pair(BlockProjectArgs a) {
                     const int64_t row = row0 + 16 * rt + 4 * lk + (odd ? 2 : 0);
                     float2* o = out + row + (int64_t)j * a.ldo;
                     if constexpr (decltype(full)::value) {
-                        if (j < r_eff) *reinterpret_cast<float4*>(o) = val;
+                        if (j < r_eff)
+                            __builtin_nontemporal_store(v4f{val.x, val.y, val.z, val.w}, reinterpret_cast<v4f*>(o));
                     } else if (j < r_eff && row < a.n) {
                         o[0] = float2{val.x, val.y};
                         if (row + 1 < a.n) o[1] = float2{val.z, val.w};
