@@ -536,6 +536,37 @@ def block_roofline(kernels, n, kb, r_effs, precision):
         mfma, {"project_block": "project_block_bf16x3"} if precision == "bf16x3" else None)
 
 
+def gram_back_to_back(frames, n, dmd, reps=20):
+    """The one-frame Gram pass (`k_gram_columns` + finalize) over consecutive
+    pushes with the solves switched off: the kernel's own HBM rate with
+    nothing between its launches, against (m+2) n 4 bytes per launch."""
+    import torch
+    s = dmd.Stream(n, M, R, dtype="f32", auto_solve=False)
+    try:
+        t = 0
+        for _ in range(M + 1):
+            s.push(frames[t])
+            t += 1
+        torch.cuda.synchronize()
+        dmd.profile_enable(True)
+        dmd.profile_reset()
+        for _ in range(reps):
+            s.push(frames[t % len(frames)])
+            t += 1
+        torch.cuda.synchronize()
+        dmd.profile_enable(False)
+        cnt, ms = dmd.profile_read("gram_columns")
+        dmd.profile_reset()
+    finally:
+        s.close()
+    if not cnt:
+        return None
+    us = 1000.0 * ms / cnt
+    gbs = (M + 2) * n * 4 / (us * 1e-6) / 1e9
+    return {"avg_us": round(us, 2), "algorithmic_GBps": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "launches": int(cnt)}
+
+
 def background_alone(s, n, dmd, reps=10):
     """Background subtraction of the newest snapshot (foreground and |l|),
     timed alone after single-frame pushes: its HBM rate against the roofline,
@@ -616,6 +647,8 @@ def bench_block(args):
     background = background_alone(s, n, dmd) if L > 0 else None
     info = s.info()
     s.close()
+    if L > 0:
+        gram_alone["gram_columns_back_to_back"] = gram_back_to_back(frames, n, dmd)
     roofline = block_roofline(kernels, n, kb, r_effs, args.precision)
     out = result_line(kb * K / elapsed, K, Wu, elapsed, "f32", {
         "workload": f"blob video 1920x1080 FP32 (n=2073600), m=64, r=20; block mode: step = one push of "
