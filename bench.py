@@ -352,11 +352,21 @@ def roofline_of(kernels, bytes_per, source_of, mfma=None, traffic_key=None):
     return out
 
 
+LAT_WARM = 3  # untimed single frames before the latency frames
+
+
 def single_latency(s, frames, t, L, phi, dmd):
     """Push -> modes latency of L single frames on one stream (nothing else
-    running), and the per-kernel times of those frames."""
+    running), after LAT_WARM untimed ones, and the per-kernel times of those
+    L frames."""
     import numpy as np
     import torch
+    if L > 0:
+        for _ in range(LAT_WARM):
+            s.push(frames[t])
+            s.modes(phi)
+            t += 1
+        torch.cuda.synchronize()
     lat = []
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -406,7 +416,7 @@ def bench_single(args):
 
     n = H * W
     K, Wu, L = args.steps, args.warmup, args.latency_frames
-    T = M + 1 + Wu + K + L
+    T = M + 1 + Wu + K + L + LAT_WARM
     keep = M + 1 + (args.cpu_windows if not args.no_cpu_baseline else 0)
     frames, host_keep = make_frames(T, keep)
 
@@ -606,7 +616,7 @@ def bench_block(args):
     K, Wu, L = args.steps, args.warmup, args.latency_frames
     LB = args.latency_blocks
     fill = M + 1
-    T = fill + (Wu + K + LB) * kb + L
+    T = fill + (Wu + K + LB) * kb + L + LAT_WARM
     keep = M + 1 + (args.cpu_windows if not args.no_cpu_baseline else 0)
     frames, host_keep = make_frames(T, keep)
 
@@ -662,7 +672,8 @@ def bench_block(args):
                                       "p99": round(float(np.percentile(blat, 99)), 3), "blocks": int(LB)}
                                      if blat is not None else None),
                 "latency_ms": latency, "latency_note": "latency_ms: single-frame pushes (push -> modes) on "
-                                                       "the same stream after the timed blocks",
+                                                       "the same stream after the timed blocks and "
+                                                       f"{LAT_WARM} untimed single frames",
                 "background_alone": background,
                 "jacobi_sweeps": int(info.sweeps), "qr_iters": int(info.qr_iters)})
     if split is not None:
