@@ -158,6 +158,13 @@ int dmd_opts_init(dmd_opts_t* opts);
 int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t* opts,
                       dmd_stream_t** out);
 
+/* Device memory in bytes that dmd_stream_create(n, m, r, opts) would allocate
+ * (the device_bytes of dmd_stream_info right after creation), for admission
+ * by HBM footprint before anything is allocated.  Host only: allocates
+ * nothing and needs no device.  Same argument checks and errors as
+ * dmd_stream_create (DMD_E_INVAL, DMD_E_UNSUPPORTED); *bytes is 0 on error. */
+int dmd_stream_footprint(int64_t n, int32_t m, int32_t r, const dmd_opts_t* opts, int64_t* bytes);
+
 /* Wait for all work of the handle, then free everything it owns.  NULL is a no-op. */
 int dmd_stream_destroy(dmd_stream_t* h);
 
@@ -170,8 +177,14 @@ int dmd_stream_reset(dmd_stream_t* h, void* stream);
 
 /* ------------------------------------------------------------ ingest (Sec. 3.1) */
 
-/* Append one dense snapshot (n elements of the stream's dtype, device memory,
- * 4-byte aligned for F32, 8-byte for F64).  Enqueues on `stream`:
+/* Append one dense snapshot (n elements of the stream's dtype, 4-byte aligned
+ * for F32, 8-byte for F64) -- the new column that Sec. 3 appends on the right
+ * of the window while the oldest leaves on the left.  x may be device memory
+ * of the stream's device (read in place) or host memory, pageable or pinned
+ * (copied on `stream` into a staging buffer of n elements that the first such
+ * push allocates and the handle owns; device_bytes grows by it).  Either way
+ * the caller keeps x valid until the stream reaches the push (a later
+ * synchronising call).  Enqueues on `stream`:
  *   the copy of x into the ring, its n-length inner products with every
  *   snapshot that stays in the window and with itself (FP64 accumulation,
  *   fixed reduction order: bitwise reproducible), the Gram update (oldest
@@ -183,8 +196,10 @@ int dmd_stream_reset(dmd_stream_t* h, void* stream);
  * Errors: DMD_E_INVAL (NULL, wrong dtype, misaligned), DMD_E_DEVICE. */
 int dmd_stream_push(dmd_stream_t* h, const void* x, void* stream);
 
-/* Append one sparse complex snapshot: nnz entries, idx (int32, device) strictly
- * increasing in [0, n), val (complex64, device).  Only for DMD_C64_CSR streams;
+/* Append one sparse complex snapshot: nnz entries, idx (int32) strictly
+ * increasing in [0, n), val (complex64); device or host memory as for
+ * dmd_stream_push (host data staged in buffers of max_nnz entries allocated
+ * by the first such push).  Only for DMD_C64_CSR streams;
  * 0 <= nnz <= max_nnz.  Index validity is checked on the device: a snapshot
  * with unsorted or out-of-range indices is rejected like a non-finite one
  * (DMD_E_INVAL at the next synchronising call).  Otherwise as dmd_stream_push. */

@@ -62,3 +62,26 @@ def max_rel_entry(A_hat, A, scale=None) -> float:
     A = np.asarray(A)
     s = np.max(np.abs(A)) if scale is None else scale
     return float(np.max(np.abs(np.asarray(A_hat) - A)) / s)
+
+
+def eig_sensitivity(ref) -> np.ndarray:
+    """First-order relative sensitivity of each DMD eigenvalue of `ref` (a
+    DMDResult) to an absolute perturbation of the window's inner products of
+    size sigma_1^2, i.e. |d lambda_i| / |lambda_i| <= eps * kappa_i to first
+    order when every Gram entry moves by at most eps * sigma_1^2.
+
+    The method of snapshots forms A~ = Sigma^-1 V^* X^* X' V Sigma^-1 from the
+    Gram (Sec. 3.1, Algorithm 2), so a Gram perturbation dG moves entry (j, k)
+    of A~ by about dG_jk / (sigma_j sigma_k); with right eigenvectors W and
+    left eigenvectors Y = W^-1 (rows), first-order perturbation theory of a
+    simple eigenvalue gives
+        |d lambda_i| <= sum_jk |Y_ij| |dA~_jk| |W_ki|
+                     <= eps sigma_1^2 (sum_j |Y_ij| / sigma_j) (sum_k |W_ki| / sigma_k).
+    Returned in the order of ref.lam."""
+    k = int(ref.r_eff)
+    s = np.asarray(ref.sigma, dtype=np.float64)[:k]
+    W = np.asarray(ref.W)
+    Y = np.linalg.inv(W)
+    left = np.abs(Y) @ (1.0 / s)
+    right = (1.0 / s) @ np.abs(W)
+    return s[0] ** 2 * left * right / np.abs(np.asarray(ref.lam))

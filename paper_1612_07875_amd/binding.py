@@ -67,6 +67,7 @@ _I32P = ctypes.POINTER(ctypes.c_int32)
 SIGNATURES = {
     "dmd_opts_init": [ctypes.POINTER(Opts)],
     "dmd_stream_create": [_I64, _I32, _I32, ctypes.POINTER(Opts), ctypes.POINTER(_P)],
+    "dmd_stream_footprint": [_I64, _I32, _I32, ctypes.POINTER(Opts), ctypes.POINTER(_I64)],
     "dmd_stream_destroy": [_P],
     "dmd_stream_sync": [_P],
     "dmd_stream_reset": [_P, _P],
@@ -166,6 +167,35 @@ def _stream_ptr(stream) -> int:
     return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
 
 
+def make_opts(dtype: str = "f32", precision: str = "default", auto_solve: bool = True,
+              rcond: Optional[float] = None, tol: float = 0.0, max_nnz: int = 0, max_sweeps: int = 0,
+              max_qr_iter: int = 0, warm_start: bool = False, max_block: int = 1,
+              eig_solver: str = "default", buildup: bool = False) -> Opts:
+    """dmd_opts_t from keyword options (defaults from dmd_opts_init)."""
+    o = Opts()
+    check(load().dmd_opts_init(ctypes.byref(o)))
+    o.dtype = DTYPES[dtype]
+    o.precision = PRECISIONS[precision]
+    o.max_nnz = max_nnz
+    o.max_sweeps = max_sweeps
+    o.max_qr_iter = max_qr_iter
+    o.auto_solve = 1 if auto_solve else 0
+    o.rcond = -1.0 if rcond is None else float(rcond)
+    o.tol = float(tol)
+    o.warm_start = 1 if warm_start else 0
+    o.max_block = int(max_block)
+    o.eig_solver = EIG_SOLVERS[eig_solver]
+    o.buildup = 1 if buildup else 0
+    return o
+
+
+def footprint(n: int, m: int, r: int, **opts) -> int:
+    """Device bytes a Stream(n, m, r, **opts) would allocate (nothing is allocated)."""
+    b = ctypes.c_int64(0)
+    check(load().dmd_stream_footprint(int(n), int(m), int(r), ctypes.byref(make_opts(**opts)), ctypes.byref(b)))
+    return int(b.value)
+
+
 class Stream:
     """One streaming-DMD window on the current GPU (see dmd_stream_create)."""
 
@@ -176,20 +206,9 @@ class Stream:
         if not torch.cuda.is_available():
             raise RuntimeError("libdmdstream needs a HIP GPU; none is available")
         lib = load()
-        o = Opts()
-        check(lib.dmd_opts_init(ctypes.byref(o)))
-        o.dtype = DTYPES[dtype]
-        o.precision = PRECISIONS[precision]
-        o.max_nnz = max_nnz
-        o.max_sweeps = max_sweeps
-        o.max_qr_iter = max_qr_iter
-        o.auto_solve = 1 if auto_solve else 0
-        o.rcond = -1.0 if rcond is None else float(rcond)
-        o.tol = float(tol)
-        o.warm_start = 1 if warm_start else 0
-        o.max_block = int(max_block)
-        o.eig_solver = EIG_SOLVERS[eig_solver]
-        o.buildup = 1 if buildup else 0
+        o = make_opts(dtype=dtype, precision=precision, auto_solve=auto_solve, rcond=rcond, tol=tol,
+                      max_nnz=max_nnz, max_sweeps=max_sweeps, max_qr_iter=max_qr_iter, warm_start=warm_start,
+                      max_block=max_block, eig_solver=eig_solver, buildup=buildup)
         h = _P()
         check(lib.dmd_stream_create(int(n), int(m), int(r), ctypes.byref(o), ctypes.byref(h)))
         self._h = h
@@ -233,14 +252,16 @@ class Stream:
 
     # ---------------------------------------------------------------- ingest
     def push(self, x: torch.Tensor, stream=None) -> int:
-        if not (x.is_cuda and x.dtype == self.elem and x.numel() == self.n and x.is_contiguous()):
-            raise ValueError(f"snapshot must be a contiguous {self.elem} CUDA tensor of {self.n} elements")
+        """x: contiguous tensor of n elements on the GPU or in host memory
+        (host data is staged on the device by the library)."""
+        if not (x.dtype == self.elem and x.numel() == self.n and x.is_contiguous()):
+            raise ValueError(f"snapshot must be a contiguous {self.elem} tensor of {self.n} elements")
         return check(load().dmd_stream_push(self._h, x.data_ptr(), _stream_ptr(stream)))
 
     def push_csr(self, idx: torch.Tensor, val: torch.Tensor, stream=None) -> int:
-        if not (idx.is_cuda and idx.dtype == torch.int32 and val.is_cuda and val.dtype == torch.complex64
+        if not (idx.dtype == torch.int32 and val.dtype == torch.complex64
                 and idx.numel() == val.numel() and idx.is_contiguous() and val.is_contiguous()):
-            raise ValueError("idx must be int32 and val complex64, contiguous CUDA tensors of equal length")
+            raise ValueError("idx must be int32 and val complex64, contiguous tensors of equal length")
         return check(load().dmd_stream_push_csr(self._h, idx.numel(), idx.data_ptr(), val.data_ptr(),
                                                 _stream_ptr(stream)))
 

@@ -65,10 +65,16 @@ void k_csr_gram(const int32_t* __restrict__ ring_idx, const float2* __restrict__
     const int c = blockIdx.x;
     const int e0 = (int)((int64_t)nz * c / kChunks), e1 = (int)((int64_t)nz * (c + 1) / kChunks);
     const int64_t base = (int64_t)slot * max_nnz;
+    // The new snapshot's own product reads its values directly: its indices
+    // are checked only by the finalize kernel, so they may still be out of
+    // range here.  With valid indices the scatter vector holds exactly these
+    // values, so the sum is the same either way.  The kept columns' indices
+    // were checked when they were pushed or restored.
+    const bool self = j == nkept;
     double re = 0.0, im = 0.0;
     for (int e = e0 + threadIdx.x; e < e1; e += kThreads) {
         const float2 a = ring_val[base + e];
-        const float2 b = scatter[ring_idx[base + e]];
+        const float2 b = self ? a : scatter[ring_idx[base + e]];
         // conj(a) * b in FP64 (products of FP32 values are exact)
         re = fma((double)a.x, (double)b.x, re);
         re = fma((double)a.y, (double)b.y, re);

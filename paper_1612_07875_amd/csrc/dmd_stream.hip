@@ -197,6 +197,12 @@ struct dmd_stream {
     int32_t reported_nonfinite = 0;
     int32_t reported_index = 0;
     int64_t device_bytes = 0;
+    bool dry = false;             // sizing only (dmd_stream_footprint): count bytes, allocate nothing
+    // Snapshots pushed from host memory are copied here first (allocated by
+    // the first such push): dense n elements; sparse max_nnz indices + values.
+    void* stage = nullptr;
+    int32_t* stage_idx = nullptr;
+    float2* stage_val = nullptr;
 };
 
 namespace {
@@ -263,6 +269,10 @@ hipError_t end(dmd_stream* h, hipStream_t s) {
 template <typename P>
 int dev_alloc(dmd_stream* h, P** p, size_t bytes) {
     if (bytes == 0) bytes = 256;
+    if (h->dry) {
+        h->device_bytes += (int64_t)bytes;
+        return DMD_OK;
+    }
     void* q = nullptr;
     hipError_t e = hipMalloc(&q, bytes);
     if (e != hipSuccess) return fail(DMD_E_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
@@ -279,7 +289,8 @@ void free_all(dmd_stream* h) {
                     h->Bbg, h->bpartial, h->gblock, h->bflag, h->sh_dev, h->sh_V, h->sh_At, h->sh_W, h->sh_work,
                     h->sh_Vfull, h->sh_Bphi, h->sh_Bpod, h->cfrag, h->bdesc, h->solve_tbl,
                     h->f_idx, h->f_ky, h->f_col, h->f_kx, h->f_twW, h->f_twH, h->f_R, h->f_val,
-                    h->upos, h->ulist, h->ucount, h->ublock, h->snap_st, h->snap_B};
+                    h->upos, h->ulist, h->ucount, h->ublock, h->snap_st, h->snap_B,
+                    h->stage, h->stage_idx, h->stage_val};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (h->res_host) (void)hipHostFree(h->res_host);
@@ -290,6 +301,33 @@ void free_all(dmd_stream* h) {
     for (hipEvent_t e : h->ev_sproj)
         if (e) (void)hipEventDestroy(e);
     if (h->ev_solved) (void)hipEventDestroy(h->ev_solved);
+}
+
+// Whether the kernels of h's device can read p directly: device memory of
+// that device or managed memory.  Anything else (pageable or pinned host
+// memory, another device's memory) is copied to a staging buffer first.
+bool device_readable(const dmd_stream* h, const void* p) {
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();  // unknown to HIP: pageable host memory
+        return false;
+    }
+    if (a.type == hipMemoryTypeManaged || a.isManaged) return true;
+    return a.type == hipMemoryTypeDevice && a.device == h->device;
+}
+
+// Stream-ordered copy of `bytes` from p into *stage (allocated on first use),
+// returning the staged address in *out; p itself when the kernels can read it.
+template <typename P>
+int stage_input(dmd_stream* h, P** stage, size_t cap_bytes, const void* p, size_t bytes, hipStream_t s,
+                const void** out) {
+    *out = p;
+    if (bytes == 0 || device_readable(h, p)) return DMD_OK;
+    if (!*stage)
+        if (int rc = dev_alloc(h, stage, cap_bytes)) return rc;
+    HIP_TRY(hipMemcpyAsync(*stage, p, bytes, hipMemcpyDefault, s));
+    *out = *stage;
+    return DMD_OK;
 }
 
 int check_handle(dmd_stream* h) {
@@ -464,10 +502,17 @@ DMD_API const char* dmd_last_error(void) { return g_err.c_str(); }
 
 DMD_API const char* dmd_version(void) { return "dmdstream 0.1 (gfx950)"; }
 
-DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t* opts,
-                              dmd_stream_t** out) {
-    if (!out) return fail(DMD_E_INVAL, "null output pointer");
-    *out = nullptr;
+namespace {
+// Creates a stream, or with `footprint` set only validates the arguments and
+// adds up the device memory the stream would own (nothing is allocated and
+// no device is needed).
+int create_impl(int64_t n, int32_t m, int32_t r, const dmd_opts_t* opts, dmd_stream_t** out,
+                int64_t* footprint) {
+    const bool dry = footprint != nullptr;
+    if (!dry) {
+        if (!out) return fail(DMD_E_INVAL, "null output pointer");
+        *out = nullptr;
+    }
     dmd_opts_t o;
     dmd_opts_init(&o);
     if (opts) {
@@ -525,7 +570,8 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
     h->use_trid = o.eig_solver == DMD_EIG_TRIDIAG || (o.eig_solver == DMD_EIG_DEFAULT && !o.warm_start);
     h->ld = (n + 63) / 64 * 64;
     h->L = ResultsLayout::make(m, r);
-    if (hipGetDevice(&h->device) != hipSuccess) {
+    h->dry = dry;
+    if (!dry && hipGetDevice(&h->device) != hipSuccess) {
         delete h;
         return fail(DMD_E_DEVICE, "no HIP device");
     }
@@ -551,7 +597,7 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
         ALLOC(h->ulist, sizeof(int32_t) * (size_t)h->ucap);
         ALLOC(h->ucount, 2 * sizeof(int));
         ALLOC(h->ublock, sizeof(float2) * (size_t)h->ucap * m);
-        if (rc == DMD_OK && hipMemset(h->upos, 0xFF, sizeof(int32_t) * (size_t)n) != hipSuccess)
+        if (rc == DMD_OK && !dry && hipMemset(h->upos, 0xFF, sizeof(int32_t) * (size_t)n) != hipSuccess)
             rc = fail(DMD_E_DEVICE, "hipMemset(index map)");
     } else {
         ALLOC(h->ring, (size_t)h->slots * h->ld * h->elem_bytes);
@@ -592,19 +638,25 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
         h->cfrag_elems = dmd::project_block_frag_bytes(m, h->kmax) / sizeof(uint4);
         ALLOC(h->cfrag, 2 * h->cfrag_elems * sizeof(uint4));
         ALLOC(h->bdesc, 2 * sizeof(dmd::BlockDesc));
-        if (rc == DMD_OK) {
+        if (rc == DMD_OK && !dry) {
             hipError_t e = hipHostMalloc((void**)&h->sh_host, ns * h->sh_stride,
                                          hipHostMallocMapped | hipHostMallocCoherent);
             if (e != hipSuccess) rc = fail(DMD_E_NOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
             else std::memset(h->sh_host, 0, ns * h->sh_stride);
         }
-        if (rc == DMD_OK) {
+        if (rc == DMD_OK && !dry) {
             hipError_t e = hipHostGetDevicePointer((void**)&h->sh_host_dev, h->sh_host, 0);
             if (e != hipSuccess) rc = hip_fail(e, "hipHostGetDevicePointer");
         }
     }
     if (!h->cplx) ALLOC(h->solve_tbl, sizeof(dmd::SolveArgs) * (size_t)h->kmax);
 #undef ALLOC
+    if (dry) {
+        *footprint = h->device_bytes;
+        delete h;
+        g_err.clear();
+        return rc;
+    }
     if (rc == DMD_OK) {
         hipError_t e = hipHostMalloc((void**)&h->res_host, h->L.bytes, hipHostMallocMapped | hipHostMallocCoherent);
         if (e != hipSuccess) rc = fail(DMD_E_NOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
@@ -646,6 +698,18 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
     *out = h;
     g_err.clear();
     return DMD_OK;
+}
+}  // namespace
+
+DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t* opts,
+                              dmd_stream_t** out) {
+    return create_impl(n, m, r, opts, out, nullptr);
+}
+
+DMD_API int dmd_stream_footprint(int64_t n, int32_t m, int32_t r, const dmd_opts_t* opts, int64_t* bytes) {
+    if (!bytes) return fail(DMD_E_INVAL, "null bytes");
+    *bytes = 0;
+    return create_impl(n, m, r, opts, nullptr, bytes);
 }
 
 DMD_API int dmd_stream_destroy(dmd_stream_t* h) {
@@ -715,6 +779,10 @@ DMD_API int dmd_stream_push(dmd_stream_t* h, const void* x, void* stream) {
     hipStream_t s = as_stream(stream);
     if (h->opts.auto_solve && h->snap_st) HIP_TRY(begin_single(h, s, (int)(h->snap_seq & 1)));
     else HIP_TRY(begin(h, s));
+    // host memory: staged on `s` (the previous push that read the staging
+    // buffer is ordered before this copy by begin / the stream itself)
+    if (int rc = stage_input(h, &h->stage, (size_t)h->ld * h->elem_bytes, x, (size_t)h->n * h->elem_bytes, s, &x))
+        return rc;
     DevState* st = reinterpret_cast<DevState*>(h->res_dev);
     int nblk = 0;
     hipError_t e = timed("gram_columns", s, [&] {
@@ -748,6 +816,18 @@ DMD_API int dmd_stream_push_csr(dmd_stream_t* h, int32_t nnz, const int32_t* idx
     DeviceGuard g(h->device);
     hipStream_t s = as_stream(stream);
     HIP_TRY(begin(h, s));
+    if (nnz > 0) {
+        const void* pi = idx;
+        const void* pv = val;
+        if (int rc = stage_input(h, &h->stage_idx, sizeof(int32_t) * (size_t)h->max_nnz, idx,
+                                 sizeof(int32_t) * (size_t)nnz, s, &pi))
+            return rc;
+        if (int rc = stage_input(h, &h->stage_val, sizeof(float2) * (size_t)h->max_nnz, val,
+                                 sizeof(float2) * (size_t)nnz, s, &pv))
+            return rc;
+        idx = static_cast<const int32_t*>(pi);
+        val = pv;
+    }
     DevState* st = reinterpret_cast<DevState*>(h->res_dev);
     hipError_t e = timed("csr_gram", s, [&] {
         return dmd::launch_csr_push(idx, static_cast<const float2*>(val), nnz, h->n, h->ring_idx, h->ring_val,
@@ -1283,7 +1363,9 @@ DMD_API int dmd_stream_restore(dmd_stream_t* h, const void* buf, int64_t bytes, 
     if (!h->cplx) {
         if (hd.data_bytes != (int64_t)hd.count * h->n * h->elem_bytes) return fail(DMD_E_INVAL, "inconsistent checkpoint");
     } else {
-        nnz.assign(reinterpret_cast<const int32_t*>(data), reinterpret_cast<const int32_t*>(data) + hd.count);
+        if (hd.data_bytes < (int64_t)sizeof(int32_t) * hd.count) return fail(DMD_E_INVAL, "inconsistent checkpoint");
+        nnz.resize(hd.count);
+        if (hd.count > 0) std::memcpy(nnz.data(), data, sizeof(int32_t) * hd.count);
         int64_t b = sizeof(int32_t) * (int64_t)hd.count;
         for (int j = 0; j < hd.count; ++j) {
             if (nnz[j] < 0 || nnz[j] > h->max_nnz)
@@ -1291,6 +1373,21 @@ DMD_API int dmd_stream_restore(dmd_stream_t* h, const void* buf, int64_t bytes, 
             b += (int64_t)nnz[j] * (sizeof(int32_t) + sizeof(float2));
         }
         if (b != hd.data_bytes) return fail(DMD_E_INVAL, "inconsistent checkpoint");
+        // the indices become addresses in the sparse kernels (scatter, index
+        // map, projection rows): the rule of dmd_stream_push_csr applies
+        const char* p = data + sizeof(int32_t) * hd.count;
+        for (int j = 0; j < hd.count; ++j) {
+            int32_t prev = -1;
+            for (int e = 0; e < nnz[j]; ++e) {
+                int32_t i;
+                std::memcpy(&i, p + sizeof(int32_t) * (size_t)e, sizeof(i));
+                if (i <= prev || (int64_t)i >= h->n)
+                    return fail(DMD_E_INVAL, "checkpoint snapshot %d: index %d at entry %d not strictly increasing in [0, n)",
+                                j, i, e);
+                prev = i;
+            }
+            p += (sizeof(int32_t) + sizeof(float2)) * (size_t)nnz[j];
+        }
     }
     DeviceGuard g(h->device);
     hipStream_t s = as_stream(stream);

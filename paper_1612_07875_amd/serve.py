@@ -174,39 +174,77 @@ class Server:
             admitted=len(self.active), refused_at_first=self.refused, latencies_ms=list(lat))
 
 
+def stream_footprint(spec: StreamSpec, modes: bool, footprint_fn) -> int:
+    """HBM bytes one admitted stream holds: what the library allocates for it
+    (footprint_fn(n, m, r, precision=...), nothing allocated) plus, when the
+    modes are kept, the executor's resident n x r complex64 mode buffer."""
+    lib = int(footprint_fn(spec.n, spec.m, spec.r, precision=spec.precision))
+    celem = 16 if spec.precision == "fp64" else 8   # complex128 or complex64 modes
+    return lib + (celem * spec.n * spec.r if modes else 0)
+
+
 class GPUExecutor:
     """Executor backed by libdmdstream: one Stream per sid in one Batch.
     Frame `index` of stream `sid` is read from frames[sid][index % len].
     With modes=True every update also projects the window's DMD modes into a
     resident per-stream buffer (in the stream's precision).  graphs > 0 runs
-    each tick as one HIP graph launch (tick shapes cached, see Batch)."""
+    each tick as one HIP graph launch (tick shapes cached, see Batch).
+
+    Admission: a stream is admitted while the executor's total footprint
+    (library memory plus mode buffers, counted before anything is allocated)
+    stays within hbm_budget (0: 90 % of the device memory free at start); a
+    stream that does not fit, or whose allocation fails, is refused and waits
+    in the server's queue."""
 
     def __init__(self, frames: Dict[int, "object"], hbm_budget: int = 0, max_streams: int = 1024,
                  modes: bool = False, graphs: int = 0):
         import torch
-        from .binding import Batch, DMDError, Stream, E_NOMEM
+        from .binding import Batch, DMDError, Stream, E_NOMEM, footprint
         self.torch = torch
         self.Stream = Stream
         self.DMDError = DMDError
         self.E_NOMEM = E_NOMEM
+        self.footprint = footprint
         self.frames = frames
-        self.batch = Batch(max_streams=max_streams, hbm_budget=hbm_budget, graphs=graphs)
+        if hbm_budget <= 0:
+            free, _ = torch.cuda.mem_get_info()
+            hbm_budget = int(0.9 * free)
+        self.budget = int(hbm_budget)
+        self.used = 0
+        self.charged = {}
+        # the executor holds the budget (it also counts the mode buffers), so
+        # the batch itself admits whatever the executor passes on
+        self.batch = Batch(max_streams=max_streams, hbm_budget=1 << 62, graphs=graphs)
         self.streams = {}
         self.want_modes = modes
         self.modes = {}
 
     def open(self, sid, spec) -> bool:
-        s = self.Stream(spec.n, spec.m, spec.r, precision=spec.precision)
+        need = stream_footprint(spec, self.want_modes, self.footprint)
+        if self.used + need > self.budget:
+            return False
+        try:
+            s = self.Stream(spec.n, spec.m, spec.r, precision=spec.precision)
+        except self.DMDError as e:
+            if e.code == self.E_NOMEM:
+                return False
+            raise
         try:
             self.batch.attach(s)
+            if self.want_modes:
+                self.modes[sid] = self.torch.zeros((spec.r, spec.n), dtype=s.mode_dtype, device="cuda").T
         except self.DMDError as e:
             s.close()
             if e.code == self.E_NOMEM:
                 return False
             raise
+        except self.torch.cuda.OutOfMemoryError:
+            self.batch.detach(s)
+            s.close()
+            return False
         self.streams[sid] = s
-        if self.want_modes:
-            self.modes[sid] = self.torch.zeros((spec.r, spec.n), dtype=s.mode_dtype, device="cuda").T
+        self.used += need
+        self.charged[sid] = need
         return True
 
     def close(self, sid) -> None:
@@ -214,6 +252,7 @@ class GPUExecutor:
         self.modes.pop(sid, None)
         self.batch.detach(s)
         s.close()
+        self.used -= self.charged.pop(sid)
 
     def tick(self, items):
         ss = [self.streams[sid] for sid, _ in items]

@@ -135,3 +135,29 @@ def test_create_rejects_bad_solver_options_without_gpu(solver, warm, msg):
     h = ctypes.c_void_p()
     assert lib.dmd_stream_create(1000, 8, 4, ctypes.byref(o), ctypes.byref(h)) == dmd.E_INVAL
     assert msg in dmd.last_error()
+
+
+def test_footprint_is_host_only_and_adds_up_the_ring():
+    """dmd_stream_footprint sizes a stream without a device: it grows with the
+    ring (slots x roundup(n, 64) x element size) and checks like create."""
+    n, m, r = 2_073_600, 64, 20
+    ld = (n + 63) // 64 * 64
+    f32 = dmd.footprint(n, m, r)
+    f64 = dmd.footprint(n, m, r, dtype="f64")
+    ring32 = (m + 2) * ld * 4
+    assert ring32 < f32 < ring32 + 64 * 1024 * 1024
+    # the FP64 ring is twice as large; workspaces grow by less than the ring
+    assert f64 - f32 >= ring32
+    # one more slot of n elements for every extra window column
+    assert dmd.footprint(n, m + 1, r) - f32 >= ld * 4
+    # a block stream keeps 2 max_block spare slots
+    assert dmd.footprint(n, m, r, max_block=32) - f32 >= (2 * 32 - 1) * ld * 4
+    sp = dmd.footprint(262144, 128, 24, dtype="c64_csr", max_nnz=2621)
+    assert sp < 64 * 1024 * 1024
+    lib = dmd.load()
+    b = ctypes.c_int64(7)
+    assert lib.dmd_stream_footprint(100, 8, 9, None, ctypes.byref(b)) == dmd.E_INVAL
+    assert b.value == 0 and "r must be" in dmd.last_error()
+    assert lib.dmd_stream_footprint(100, 8, 2, None, None) == dmd.E_INVAL
+    with pytest.raises(dmd.DMDError):
+        dmd.footprint(100, 300, 4)

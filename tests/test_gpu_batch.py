@@ -27,7 +27,21 @@ MIX = [  # (n, m, r, kind)
     (9000, 128, 24, "flow"),
     (131072, 24, 12, "video"),
     (50000, 33, 10, "flow"),
+    (1_500_001, 16, 8, "video"),   # large slab form of the Gram pass, ragged tail
 ]
+
+
+def eig_bound(ref):
+    """Per-eigenvalue bound on the relative error of lambda_i, in ref's order.
+
+    The method of snapshots works from the FP64 Gram, whose entries carry
+    rounding of order u sigma_1^2 (u = 2^-52), and the oracle takes the SVD
+    route; metrics.eig_sensitivity gives each eigenvalue's first-order
+    sensitivity kappa_i to such a perturbation.  On the CPU the oracle's own
+    Gram route (StreamingMoS) and SVD route differ by at most 0.46 u kappa_i
+    over these mixes; 32 u kappa_i leaves a margin of 70 for the GPU's
+    different summation order."""
+    return 1e-13 + 32 * 2.0 ** -52 * metrics.eig_sensitivity(ref)
 
 
 def make_gen(i, n, kind):
@@ -79,12 +93,13 @@ def test_batch_equals_alone_bitwise_and_oracle():
         ref = oracle.exact_dmd(W[:, :m], W[:, 1:], r)
         assert k == ref.r_eff
         # the method of snapshots squares the condition number: tolerances
-        # grow with (sigma_1 / sigma_k)^2 (the oracle's own MoS and SVD
-        # routes differ by that much on the flow streams' weakest waves)
+        # grow with (sigma_1 / sigma_k)^2 for sigma_k and with each
+        # eigenvalue's own sensitivity for lambda_i
         kap2 = (ref.sigma[0] / ref.sigma[:k]) ** 2
         assert np.all(metrics.sigma_relerr(sig, ref.sigma[:k]) <= 1e-11 + 1e-13 * kap2)
         err, perm = metrics.eig_relerr(lam, ref.lam)
-        assert err.max() < max(1e-6, 1e-15 * kap2.max()), (i, err.max())
+        bound = eig_bound(ref)[perm]
+        assert np.all(err <= bound), (i, err, bound)
     batch.close()
     for s in streams:
         s.close()

@@ -155,3 +155,42 @@ def test_restore_rejects_bad_checkpoints():
             with pytest.raises(dmd.DMDError) as ei:
                 b.restore(blob)
             assert ei.value.code == dmd.E_INVAL
+
+
+def test_restore_rejects_bad_sparse_indices():
+    """A sparse checkpoint whose indices break the push rule (strictly
+    increasing in [0, n)) is refused on the host before any device copy, and
+    the stream keeps its window."""
+    import struct
+    dmd = _dmd()
+    fs = gen.FourierSparse(side=32, nnz=40, redraw=0.05)
+    m, r = 6, 3
+    with dmd.Stream(fs.n, m, r, dtype="c64_csr", max_nnz=48) as a:
+        for t in range(m + 2):
+            idx, val = fs.frame(t)
+            a.push_csr(torch.from_numpy(idx).cuda(), torch.from_numpy(val).cuda())
+        blob = bytearray(a.save())
+        G0 = a.gram()
+        # header: magic[8], version, dtype, n (int64), m, r, count, max_nnz,
+        # four counters, gram_bytes, data_bytes (int64)
+        hdr = struct.calcsize("<8sii q 4i 4i qq")
+        count = struct.unpack_from("<i", blob, 8 + 4 + 4 + 8 + 8)[0]
+        gram_bytes = struct.unpack_from("<q", blob, hdr - 16)[0]
+        data = hdr + gram_bytes
+        nnz = struct.unpack_from(f"<{count}i", blob, data)
+        second = data + 4 * count + 12 * nnz[0]   # indices of window snapshot 1
+        for e, value in ((nnz[1] - 1, fs.n), (0, -1), (3, struct.unpack_from("<i", blob, second + 4 * 2)[0]),
+                         (nnz[1] - 1, 2**31 - 1)):
+            bad = bytearray(blob)
+            struct.pack_into("<i", bad, second + 4 * e, value)
+            with dmd.Stream(fs.n, m, r, dtype="c64_csr", max_nnz=48) as b:
+                with pytest.raises(dmd.DMDError) as ei:
+                    b.restore(bytes(bad))
+                assert ei.value.code == dmd.E_INVAL
+            with pytest.raises(dmd.DMDError) as ei:
+                a.restore(bytes(bad))
+            assert ei.value.code == dmd.E_INVAL
+            assert np.array_equal(a.gram(), G0)
+        with dmd.Stream(fs.n, m, r, dtype="c64_csr", max_nnz=48) as b:
+            b.restore(bytes(blob))                 # the unmodified checkpoint is accepted
+            assert np.array_equal(b.gram(), G0)

@@ -83,12 +83,17 @@ def test_sparse_rejects_bad_indices_and_keeps_window():
             s.sync()
         assert ei.value.code == dmd.E_INVAL
         assert np.array_equal(s.gram(), G0)
-        oob = idx.copy()
-        oob[-1] = fs.n + 5                       # out of range
-        s.push_csr(torch.from_numpy(oob).cuda(), torch.from_numpy(val).cuda())
-        with pytest.raises(dmd.DMDError):
-            s.sync()
-        assert np.array_equal(s.gram(), G0)
+        # out of range past n, negative, and the largest int32: the pushed
+        # snapshot's own product never reads the scatter vector at its
+        # indices, so none of these addresses memory outside it
+        for pos, value in ((-1, fs.n + 5), (0, -1), (-1, 2**31 - 1), (5, -2**31)):
+            oob = idx.copy()
+            oob[pos] = value
+            s.push_csr(torch.from_numpy(oob).cuda(), torch.from_numpy(val).cuda())
+            with pytest.raises(dmd.DMDError) as ei:
+                s.sync()
+            assert ei.value.code == dmd.E_INVAL
+            assert np.array_equal(s.gram(), G0)
         dense.append(push_frame(s, fs, m + 1))   # a good push still works afterwards
         check_sparse_window(s, np.stack(dense[1:], axis=1), m, r)
 

@@ -110,3 +110,20 @@ def test_backlog_raises_latency_but_keeps_order():
     st = srv.run([(0.0, 0)] * 10)                     # burst of 10 frames of one stream
     assert [t[0][1] for t in ex.ticks] == list(range(10))
     assert st.max_ms == pytest.approx(10.0, abs=0.5)  # the last waits for 9 earlier ticks
+
+
+def test_stream_footprint_counts_library_and_mode_buffers():
+    """Admission charges what the library allocates plus the resident modes
+    (n x r complex64, complex128 for FP64 projections), before allocating."""
+    from paper_1612_07875_amd.serve import stream_footprint
+    calls = []
+
+    def lib_bytes(n, m, r, precision="default"):
+        calls.append((n, m, r, precision))
+        return 1000 * m
+
+    spec = StreamSpec(n=500, m=16, r=8)
+    assert stream_footprint(spec, False, lib_bytes) == 16000
+    assert stream_footprint(spec, True, lib_bytes) == 16000 + 8 * 500 * 8
+    assert stream_footprint(StreamSpec(500, 16, 8, precision="fp64"), True, lib_bytes) == 16000 + 16 * 500 * 8
+    assert calls[0] == (500, 16, 8, "default")
