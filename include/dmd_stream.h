@@ -396,6 +396,24 @@ int dmd_stream_load_window(dmd_stream_t* h, const void* X, int64_t ldx, int32_t 
  * the ring (MFMA Gram kernel, stream's precision), e.g. to compare precisions. */
 int dmd_stream_resync(dmd_stream_t* h, void* stream);
 
+/* Stateless whole Gram of a window (Algorithm 1's first step; Sec. 2.1
+ * step 1): G = X^* X for the k = ncols columns of X, without a stream
+ * handle.  X: device, n x k column-major FP32 (dtype DMD_F32) or FP64
+ * (DMD_F64), leading dimension ldx >= n, 16-byte aligned with ldx * element
+ * size a multiple of 16; 1 <= k <= 257.  G: device, k x k FP64 column-major,
+ * leading dimension ldg >= k, both triangles written (rows/columns past k and
+ * the padding untouched).  precision: the products of the MFMA Gram kernel
+ * (DMD_PREC_FP64 or DMD_F64 data: FP64 products and sums; DMD_PREC_FP32 /
+ * DEFAULT with FP32 data: FP32 products and in-tile sums; DMD_PREC_BF16X3:
+ * split-BF16 products, FP32 in-tile sums); row-split tiles are always summed
+ * in FP64 in a fixed order (bitwise reproducible).  Stream-ordered on
+ * `stream`: the kernel's partial tiles (16.4 MB at most) are allocated with
+ * hipMallocAsync and freed with hipFreeAsync on it; X and G belong to the
+ * caller.  Errors: DMD_E_INVAL (NULL, sizes, alignment), DMD_E_UNSUPPORTED
+ * (BF16X3 with FP64 data), DMD_E_NOMEM, DMD_E_DEVICE. */
+int dmd_window_gram(const void* X, int64_t ldx, int64_t n, int32_t ncols, int32_t dtype,
+                    int32_t precision, double* G, int64_t ldg, void* stream);
+
 /* ------------------------------------------------------------ introspection */
 
 typedef struct {

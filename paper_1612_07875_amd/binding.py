@@ -93,6 +93,7 @@ SIGNATURES = {
     "dmd_stream_background": [_P, _P, _P, _P],
     "dmd_stream_load_window": [_P, _P, _I64, _I32, _P],
     "dmd_stream_resync": [_P, _P],
+    "dmd_window_gram": [_P, _I64, _I64, _I32, _I32, _I32, _P, _I64, _P],
     "dmd_stream_info": [_P, ctypes.POINTER(Info)],
     "dmd_batch_opts_init": [ctypes.POINTER(BatchOpts)],
     "dmd_batch_create": [ctypes.POINTER(BatchOpts), ctypes.POINTER(_P)],
@@ -194,6 +195,25 @@ def footprint(n: int, m: int, r: int, **opts) -> int:
     b = ctypes.c_int64(0)
     check(load().dmd_stream_footprint(int(n), int(m), int(r), ctypes.byref(make_opts(**opts)), ctypes.byref(b)))
     return int(b.value)
+
+
+def window_gram(X: torch.Tensor, precision: str = "default", out: Optional[torch.Tensor] = None,
+                stream=None) -> torch.Tensor:
+    """G = X^* X (FP64, k x k on the device) of the columns of X, given as a
+    (k, n) CUDA tensor whose rows are the snapshots (column-major n x k)."""
+    if not (X.is_cuda and X.dim() == 2 and X.stride(1) == 1 and X.dtype in (torch.float32, torch.float64)):
+        raise ValueError("X must be a (k, n) float32/float64 CUDA tensor with unit stride along n")
+    k = X.shape[0]
+    if out is None:
+        out = torch.empty((k, k), dtype=torch.float64, device=X.device)
+    if not (out.is_cuda and out.dtype == torch.float64 and out.dim() == 2 and out.stride(1) == 1
+            and out.shape[0] >= k and out.shape[1] >= k):
+        raise ValueError("out must be a float64 CUDA tensor of at least k x k with unit inner stride")
+    dt = DTYPES["f32"] if X.dtype == torch.float32 else DTYPES["f64"]
+    # out is row-major (k, ldg): read as column-major it is G^T = G
+    check(load().dmd_window_gram(X.data_ptr(), X.stride(0), X.shape[1], k, dt, PRECISIONS[precision],
+                                 out.data_ptr(), out.stride(0), _stream_ptr(stream)))
+    return out
 
 
 class Stream:

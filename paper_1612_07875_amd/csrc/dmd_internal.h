@@ -73,6 +73,9 @@ enum : int32_t {
     ST_E_NONFINITE = -4, ST_E_CONVERGENCE = -5
 };
 
+// Sets the calling thread's last-error message (dmd_last_error) and returns code.
+int api_fail(int code, const char* fmt, ...);
+
 // Maximum sizes supported by the kernels.
 constexpr int kMaxM = 256;   // window columns
 constexpr int kMaxR = 64;    // truncation rank
@@ -327,5 +330,12 @@ hipError_t launch_copy_columns(const void* X, int64_t ldx, void* ring, int64_t l
                                int elem_f64, hipStream_t s);
 int gram_full_tiles(int m);
 int gram_full_splits(int m);
+
+// Stateless whole Gram of ncols columns of X (column-major, leading dimension
+// ldx, 16-byte aligned columns) into G (leading dimension ldg), with the
+// kernel's partial tiles in `partial` (window_gram_scratch_bytes(ncols)).
+size_t window_gram_scratch_bytes(int32_t ncols);
+hipError_t launch_window_gram(const void* X, int64_t ldx, int64_t n, int32_t ncols, int elem_f64, int32_t precision,
+                              double* G, int64_t ldg, double* partial, hipStream_t s);
 
 }  // namespace dmd

@@ -33,6 +33,21 @@ int fail(int code, const char* fmt, ...) {
     return code;
 }
 
+}  // namespace
+
+// Error reporting for entry points defined in other source files.
+int dmd::api_fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+namespace {
+
 int hip_fail(hipError_t e, const char* what) {
     return fail(DMD_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }

@@ -161,3 +161,16 @@ def test_footprint_is_host_only_and_adds_up_the_ring():
     assert lib.dmd_stream_footprint(100, 8, 2, None, None) == dmd.E_INVAL
     with pytest.raises(dmd.DMDError):
         dmd.footprint(100, 300, 4)
+
+
+def test_window_gram_rejects_bad_arguments_without_gpu():
+    lib = dmd.load()
+    g = ctypes.c_void_p(256)       # never dereferenced: every call below fails its checks
+    assert lib.dmd_window_gram(None, 64, 64, 4, 0, 0, g, 4, None) == dmd.E_INVAL
+    assert lib.dmd_window_gram(g, 64, 64, 0, 0, 0, g, 4, None) == dmd.E_INVAL
+    assert lib.dmd_window_gram(g, 64, 64, 258, 0, 0, g, 300, None) == dmd.E_INVAL
+    assert lib.dmd_window_gram(g, 63, 64, 4, 0, 0, g, 4, None) == dmd.E_INVAL
+    assert lib.dmd_window_gram(g, 64, 64, 4, 2, 0, g, 4, None) == dmd.E_INVAL
+    assert lib.dmd_window_gram(g, 64, 64, 4, 1, 2, g, 4, None) == dmd.E_UNSUPPORTED
+    assert lib.dmd_window_gram(g, 65, 65, 4, 0, 0, g, 4, None) == dmd.E_INVAL   # column stride not 16 B
+    assert "16-byte" in dmd.last_error()

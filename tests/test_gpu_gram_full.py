@@ -134,3 +134,48 @@ def test_precision_study_travelling_waves(prec, tol, need):
     # the generating eigenvalues e^{+-i w} are recovered where sigma is resolved
     lam_err, perm = metrics.eig_relerr(lam, w.true_eigs())
     assert np.median(lam_err) < 1e-2
+
+
+@pytest.mark.parametrize("dtype,prec,tol", [
+    ("f64", "default", 1e-12), ("f32", "fp64", 1e-12), ("f32", "default", 2e-5), ("f32", "bf16x3", 2e-4),
+])
+@pytest.mark.parametrize("n,k", [(9000, 33), (70001, 65), (5000, 257), (333, 1)])
+def test_stateless_window_gram(dtype, prec, tol, n, k):
+    """dmd_window_gram: G = X^* X of a caller's matrix (no stream handle),
+    every entry within the precision's bound of the oracle; it equals the
+    Gram a stream computes when it loads the same window (same kernel, same
+    row splits), bit for bit."""
+    dmd = _dmd()
+    v = gen.BlobVideo(height=(n + 127) // 128, width=128, n=n, blob_sigma=5.0)
+    F = v.frames(0, k).astype(np.float32 if dtype == "f32" else np.float64)
+    X = torch.from_numpy(F.T.copy()).cuda()
+    G = dmd.window_gram(X, precision=prec).cpu().numpy()
+    ref = oracle.gram(F)
+    assert np.array_equal(G, G.T)
+    assert gram_err(G, ref) < tol, gram_err(G, ref)
+    if k >= 3:
+        with dmd.Stream(n, k - 1, 1, dtype=dtype, precision=prec, auto_solve=False) as s:
+            s.load_window(X)
+            assert np.array_equal(s.gram(), G)
+
+
+def test_stateless_window_gram_padding_and_errors():
+    dmd = _dmd()
+    from paper_1612_07875_amd import binding
+    n, k = 4096, 20
+    X = torch.rand((k, n), dtype=torch.float64, device="cuda")
+    out = torch.full((k + 3, k + 5), -7.0, dtype=torch.float64, device="cuda")
+    dmd.window_gram(X, out=out)
+    o = out.cpu().numpy()
+    np.testing.assert_array_equal(o[k:, :], -7.0)           # padding untouched
+    np.testing.assert_array_equal(o[:k, k:], -7.0)
+    assert gram_err(o[:k, :k], oracle.gram(X.cpu().numpy().T)) < 1e-12
+    lib = dmd.load()
+    G = torch.empty((k, k), dtype=torch.float64, device="cuda")
+    Xs = X[:, 1:]                                            # columns not 16-byte aligned
+    assert lib.dmd_window_gram(Xs.data_ptr(), n, n - 1, k, 1, 0, G.data_ptr(), k, None) == dmd.E_INVAL
+    assert lib.dmd_window_gram(X.data_ptr(), n, n, 258, 1, 0, G.data_ptr(), 258, None) == dmd.E_INVAL
+    assert lib.dmd_window_gram(X.data_ptr(), n, n, k, 1, 2, G.data_ptr(), k, None) == dmd.E_UNSUPPORTED
+    assert lib.dmd_window_gram(X.data_ptr(), n, n, k, 1, 0, G.data_ptr(), k - 1, None) == dmd.E_INVAL
+    assert lib.dmd_window_gram(None, n, n, k, 1, 0, G.data_ptr(), k, None) == dmd.E_INVAL
+    assert binding.DTYPES["f64"] == 1
