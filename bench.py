@@ -16,6 +16,16 @@ Every window update runs the whole hot path through the C ABI:
   Sec. 5) whose k windows are all solved (side by side) and projected; the
   value counts k window updates per step.
 --mode single: one step = one frame.
+--mode modal: plain streaming DMD in FP64: n = 4096 real snapshots of five
+  damped modes plus noise, m = 32, r = 10, 64 frames (32 windows); the 64
+  frames are streamed again after a reset until >= 1,000 window updates are
+  timed; one step = one push + FP64 solves + FP64 modes; per-frame latency
+  p50/p99 over the same updates.
+--mode waves: the precision-study workload: n = 2^20 travelling waves, m = 256,
+  r = 32, FP32 data (and a second leg with the same values as FP64 data);
+  one step = one push + FP64 solves + modes; also the whole-window Gram
+  (Algorithm 1's first step, 257 columns) timed in FP64, FP32 and split-BF16
+  MFMA products against the matrix-core roofline of each.
 --mode sparse: the sparse (Fourier-coefficient) configuration: 512 x 512
   complex64 coefficients at 1 % (2,621 per frame, lowest wavenumbers, 5 %
   redrawn per frame), m = 128, r = 24; one step = one sparse push + solves +
@@ -47,7 +57,7 @@ COPY_BYTES = 1 << 30
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--mode", choices=("block", "single", "sparse"), default="block",
+    ap.add_argument("--mode", choices=("block", "single", "sparse", "modal", "waves"), default="block",
                     help="block: k frames per step (multi-column update, every window solved and projected); "
                          "single: one frame per step")
     ap.add_argument("--block", type=int, default=32, help="frames per block in block mode (1..64)")
@@ -98,9 +108,9 @@ def copy_probe():
 
 def defaults(args):
     if args.steps is None:
-        args.steps = 20 if args.mode == "block" else 100
+        args.steps = {"block": 20, "modal": 1024, "waves": 60}.get(args.mode, 100)
     if args.warmup is None:
-        args.warmup = 2 if args.mode == "block" else 10
+        args.warmup = {"block": 2, "modal": 32}.get(args.mode, 10)
     if not 1 <= args.block <= 64:
         raise SystemExit("--block must be in [1, 64]")
     return args
@@ -126,30 +136,80 @@ def traffic_for(kernel: str, source: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(frames_host, windows: int):
-    """The FP64 oracle (exact DMD by LAPACK SVD, with modes) on a bounded sample."""
-    import numpy as np
-    import oracle
-
+def host_cpu():
+    """BLAS threads the oracle uses, the host's logical CPU count and CPU model."""
     try:
         from threadpoolctl import threadpool_info
         threads = max((p.get("num_threads", 1) for p in threadpool_info()), default=1)
     except Exception:
         threads = os.cpu_count() or 1
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return int(threads), int(os.cpu_count() or 1), model
+
+
+def cpu_baseline(frames_host, windows: int, m=None, r=None, n=None):
+    """The FP64 oracle (exact DMD by LAPACK SVD, with modes) on a bounded
+    sample: the paper's non-streaming CPU baseline (Sec. 4, "CPU")."""
+    import numpy as np
+    import oracle
+
+    m = M if m is None else m
+    r = R if r is None else r
+    n = frames_host.shape[1] if n is None else n
+    threads, nproc, model = host_cpu()
     t0 = time.perf_counter()
     for w in range(windows):
-        F = frames_host[w:w + M + 1]
-        X = np.ascontiguousarray(F[:M].T)
+        F = frames_host[w:w + m + 1]
+        X = np.ascontiguousarray(F[:m].T)
         Xp = np.ascontiguousarray(F[1:].T)
-        oracle.exact_dmd(X, Xp, R)
+        oracle.exact_dmd(X, Xp, r)
     dt = time.perf_counter() - t0
     return {
         "value": windows / dt,
         "unit": "window updates/s",
-        "cores": int(threads),
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"{windows} windows of the same workload (n={H * W}, m={M}, r={R}); "
+        "sample": f"{windows} windows of the same workload (n={n}, m={m}, r={r}); "
                   f"FP64 exact DMD by LAPACK thin SVD with modes; {dt:.1f} s",
+        "nproc": nproc, "cpu_model": model,
+    }
+
+
+def cpu_baseline_streaming(frames_host, frames: int, m=None, r=None, n=None):
+    """The oracle's streaming method of snapshots in FP64 (Algorithms 1-2: one
+    new Gram column per frame, eigh, A~, eig, modes): the paper's streaming
+    CPU baseline (Sec. 4, "SCPU"), timed per frame after its window fills."""
+    import oracle
+
+    m = M if m is None else m
+    r = R if r is None else r
+    n = frames_host.shape[1] if n is None else n
+    threads, nproc, model = host_cpu()
+    s = oracle.StreamingMoS(m, r)
+    for t in range(m + 1):
+        s.push(frames_host[t])
+    s.dmd()
+    t0 = time.perf_counter()
+    for t in range(m + 1, m + 1 + frames):
+        s.push(frames_host[t])
+        s.dmd()
+    dt = time.perf_counter() - t0
+    return {
+        "value": frames / dt,
+        "unit": "window updates/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{frames} streamed frames of the same workload (n={n}, m={m}, r={r}) after the window "
+                  f"filled; FP64 streaming method of snapshots (new Gram column, eigh, A~, eig, modes); {dt:.1f} s",
+        "nproc": nproc, "cpu_model": model,
     }
 
 
@@ -752,6 +812,189 @@ def bench_sparse(args):
     return out, None
 
 
+def bench_modal(args):
+    """Plain streaming DMD in FP64 (n = 4096, m = 32, r = 10, 64 frames):
+    latency-bound; every timed update is one of the 32 windows of the 64
+    frames (the stream is reset and the frames streamed again)."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1612_07875_amd as dmd
+
+    n, m, r, T = 4096, 32, 10, 64
+    g = gen.ModalStream(n=n, noise=1e-3)
+    host = np.ascontiguousarray(g.frames(0, T).T)          # (T, n) FP64
+    frames = torch.from_numpy(host).cuda()
+    per_pass = T - m                                         # window updates per pass
+    passes = max(1, -(-args.steps // per_pass))
+    warm = max(1, -(-args.warmup // per_pass))
+    s = dmd.Stream(n, m, r, dtype="f64")
+    phi = torch.zeros((r, n), dtype=torch.complex128, device="cuda").T
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def fill():
+        s.reset()
+        for t in range(m):
+            s.push(frames[t])
+        torch.cuda.synchronize()
+
+    for _ in range(warm):
+        fill()
+        for t in range(m, T):
+            s.push(frames[t])
+            s.modes(phi)
+        torch.cuda.synchronize()
+    # throughput: the steady-state updates of each pass back to back
+    dmd.profile_enable(True)
+    dmd.profile_reset()
+    elapsed = 0.0
+    for _ in range(passes):
+        fill()
+        t0 = time.perf_counter()
+        for t in range(m, T):
+            s.push(frames[t])
+            s.modes(phi)
+        torch.cuda.synchronize()
+        elapsed += time.perf_counter() - t0
+    dmd.profile_enable(False)
+    kernels = kernel_table(dmd, ("gram_columns", "gram_finalize", "solve_sym", "solve_eig", "project_modes"))
+    dmd.profile_reset()
+    K = passes * per_pass
+    # latency: push -> modes of each update, one at a time
+    lat = []
+    for _ in range(passes):
+        fill()
+        for t in range(m, T):
+            e0.record()
+            s.push(frames[t])
+            s.modes(phi)
+            e1.record()
+            e1.synchronize()
+            lat.append(e0.elapsed_time(e1))
+    lam, sig, _ = s.eigs()
+    r_eff = int(lam.size)
+    s.close()
+    lat = np.array(lat)
+    roofline = roofline_of(
+        kernels, {"gram_columns": (m + 2) * n * 8, "project_modes": m * n * 8 + n * r_eff * 16},
+        {"gram_columns": "gram_push.hip", "project_modes": "project.hip"})
+    out = result_line(K / elapsed, K, warm * per_pass, elapsed, "f64", {
+        "workload": "modal stream FP64: n=4096, five damped complex modes + N(0, 1e-3^2) noise, m=32, r=10, "
+                    "64 frames (32 windows) streamed again after a reset; step = push + FP64 solves + FP64 modes",
+        "n": n, "m": m, "r": r, "r_eff": r_eff, "frames_per_step": 1,
+        "precision": "FP64 data, Gram, solves and projections"})
+    out.update({"roofline": roofline, "kernels": kernels,
+                "roofline_note": "latency-bound: the 1.08 MB window stays in cache; the single-CU FP64 solves set "
+                                 "the step",
+                "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                               "p99": round(float(np.percentile(lat, 99)), 4), "frames": int(lat.size)}})
+    return out, host, (m, r)
+
+
+def bench_waves(args):
+    """The precision-study workload streamed: n = 2^20 travelling waves,
+    m = 256, r = 32; FP32 data and the same values as FP64 data.  Plus the
+    whole-window Gram (257 columns) in each product precision."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1612_07875_amd as dmd
+
+    n, m, r = 1 << 20, 256, 32
+    K, Wu = args.steps, args.warmup
+    T = m + 1 + Wu + K
+    w = gen.TravelingWaves(n=n, n_waves=8)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        host = np.stack(list(ex.map(w.frame, range(T))))      # (T, n) FP32
+    print(f"[bench] generated {T} frames in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    def leg(dtype):
+        X = torch.from_numpy(host).to(device="cuda", dtype=torch.float32 if dtype == "f32" else torch.float64)
+        s = dmd.Stream(n, m, r, dtype=dtype)
+        phi = torch.zeros((r, n), dtype=s.mode_dtype, device="cuda").T
+        sp, sm = bench_streams(torch)
+        sp.wait_stream(torch.cuda.current_stream())
+        sm.wait_stream(torch.cuda.current_stream())
+        for t in range(m + 1 + Wu):
+            s.push(X[t], stream=sp)
+            if t > m:
+                s.modes(phi, stream=sm)
+        torch.cuda.synchronize()
+        dmd.profile_enable(True)
+        dmd.profile_reset()
+        t1 = time.perf_counter()
+        for t in range(m + 1 + Wu, T):
+            s.push(X[t], stream=sp)
+            s.modes(phi, stream=sm)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        dmd.profile_enable(False)
+        kern = kernel_table(dmd, ("gram_columns", "gram_finalize", "solve_sym", "solve_eig", "project_modes"))
+        dmd.profile_reset()
+        lam, _, _ = s.eigs()
+        s.close()
+        del X
+        torch.cuda.synchronize()
+        return el, kern, int(lam.size)
+
+    el32, kern32, re32 = leg("f32")
+    el64, kern64, re64 = leg("f64")
+    eb = 4
+    roofline = roofline_of(
+        kern32, {"gram_columns": (m + 2) * n * eb, "project_modes": m * n * eb + n * re32 * 8},
+        {"gram_columns": "gram_push.hip", "project_modes": "project.hip"},
+        {"project_modes": (2.0 * n * m * 2 * re32, FP32_MFMA_TFLOPS, "fp32")})
+    g64 = kern64.get("gram_columns", {})
+    if g64:
+        g64["algorithmic_bytes"] = (m + 2) * n * 8
+        g64["algorithmic_GBps"] = round(g64["algorithmic_bytes"] / (g64["avg_us"] * 1e-6) / 1e9, 1)
+    # whole-window Gram (257 columns) per product precision, back to back
+    Xw = torch.from_numpy(host[:m + 1]).cuda()
+    Xw64 = Xw.double()
+    G = torch.empty((m + 1, m + 1), dtype=torch.float64, device="cuda")
+    k = m + 1
+    flops = float(n) * k * (k + 1)                          # the k (k + 1) / 2 distinct entries, 2 n flops each
+    whole = {}
+    for name, X_, prec, peak, mult in (("fp64", Xw64, "default", 78.6, 1.0), ("fp32", Xw, "default",
+                                        FP32_MFMA_TFLOPS, 1.0), ("bf16x3", Xw, "bf16x3", BF16_MFMA_TFLOPS, 3.0)):
+        dmd.window_gram(X_, precision=prec, out=G)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        a.record()
+        for _ in range(reps):
+            dmd.window_gram(X_, precision=prec, out=G)
+        b.record()
+        b.synchronize()
+        us = a.elapsed_time(b) * 1000.0 / reps
+        nbytes = k * n * X_.element_size()
+        whole[name] = {"avg_us": round(us, 1), "algorithmic_flops": flops * mult,
+                       "achieved_TFLOPs": round(flops * mult / (us * 1e-6) / 1e12, 2), "peak_TFLOPs": peak,
+                       "frac_of_mfma_peak": round(flops * mult / (us * 1e-6) / 1e12 / peak, 4),
+                       "algorithmic_GBps": round(nbytes / (us * 1e-6) / 1e9, 1),
+                       "frac_of_hbm_peak": round(nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+    del Xw, Xw64
+    out = result_line(K / el32, K, Wu, el32, "f32", {
+        "workload": "travelling waves n=2^20 FP32 (8 waves, amplitudes 10^(-k/2)), m=256, r=32; step = push + "
+                    "FP64 solves + FP32 modes (modes of frame t beside the push of t+1)",
+        "n": n, "m": m, "r": r, "r_eff": re32, "frames_per_step": 1,
+        "precision": "FP64 Gram accumulation, FP64 solves, FP32 modes"})
+    out.update({"roofline": roofline, "kernels": kern32,
+                "gram_GBps": kern32.get("gram_columns", {}).get("algorithmic_GBps"),
+                "fp64_data": {"value": round(K / el64, 2), "unit": "window updates/s",
+                              "ms_per_step": round(1000.0 * el64 / K, 4), "r_eff": re64, "kernels": kern64},
+                "whole_gram": whole,
+                "whole_gram_note": "dmd_window_gram of the first 257 frames (1.08 GB FP32 / 2.16 GB FP64), "
+                                   "10 calls back to back; algorithmic flops n k (k+1), three times that for "
+                                   "split-BF16"})
+    return out, host, (m, r)
+
+
 def precision_note(args):
     modes = "FP32 modes" if args.precision == "fp32" else "BF16x3 modes (FP32 accumulation)"
     return "FP64 Gram accumulation, FP64 solves, " + modes
@@ -794,15 +1037,25 @@ def main():
     import torch
 
     torch.cuda.set_device(0)
+    mr = None
     if args.mode == "single":
         out, host_keep = bench_single(args)
     elif args.mode == "sparse":
         out, host_keep = bench_sparse(args)
+    elif args.mode == "modal":
+        out, host_keep, mr = bench_modal(args)
+    elif args.mode == "waves":
+        out, host_keep, mr = bench_waves(args)
     else:
         out, host_keep = bench_block(args)
     if not args.no_cpu_baseline and host_keep is not None:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(np.stack(host_keep), args.cpu_windows)
+        F = np.stack(host_keep) if isinstance(host_keep, list) else host_keep
+        m, r = mr if mr is not None else (M, R)
+        wins = {"modal": 32, "waves": 1}.get(args.mode, args.cpu_windows)
+        frames = min(F.shape[0] - m - 1, {"modal": 31, "waves": 2}.get(args.mode, args.cpu_windows))
+        out["cpu_baseline"] = cpu_baseline(F, min(wins, F.shape[0] - m), m, r)
+        out["cpu_baseline_streaming"] = cpu_baseline_streaming(F, frames, m, r)
     print(json.dumps(out), flush=True)
 
 

@@ -51,3 +51,19 @@ def test_gram_alone_rates():
     assert line["gram_block"]["algorithmic_GBps"] == pytest.approx((bench.M + 1 + 2 * kb) * n * 4 / 390e-6 / 1e9,
                                                                    rel=1e-3)
     assert "gram_block" not in bench.gram_alone_line({"gram_columns": {"avg_us": 109.0}}, n, None)
+
+
+def test_cpu_baselines_report_cores_and_model():
+    """Both CPU baselines (the SVD-route oracle per window, and the streaming
+    method of snapshots per frame) on a small sample: positive rates, the
+    threads used, the host's CPU count and model."""
+    import numpy as np
+    rng = np.random.default_rng(0)
+    F = rng.standard_normal((12, 500))              # (frames, n)
+    a = bench.cpu_baseline(F, 3, m=6, r=3)
+    b = bench.cpu_baseline_streaming(F, 4, m=6, r=3)
+    for x in (a, b):
+        assert x["value"] > 0 and x["unit"] == "window updates/s" and x["kind"] == "oracle"
+        assert x["cores"] >= 1 and x["nproc"] >= 1
+        assert "n=500, m=6, r=3" in x["sample"]
+    assert "streaming" in b["sample"]
