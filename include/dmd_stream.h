@@ -414,6 +414,49 @@ int dmd_stream_resync(dmd_stream_t* h, void* stream);
 int dmd_window_gram(const void* X, int64_t ldx, int64_t n, int32_t ncols, int32_t dtype,
                     int32_t precision, double* G, int64_t ldg, void* stream);
 
+/* ------------------------------------------------------------ launch-shape tuning */
+
+/* Launch shapes of a dense stream shape, chosen by measurement. */
+typedef struct {
+    int32_t gram_iter;   /* one-frame Gram pass: 16-byte loads per thread and column in a
+                            workgroup's slab of rows (1, 2 or 4; fewer, larger slabs) */
+    int32_t proj_form;   /* block projection (FP32 block streams): 0 built-in rule,
+                            1 one product per window, 2 two windows per product */
+    double gram_us;      /* measured one-frame Gram pass (push without solves) of the choice */
+    double step_us;      /* measured pipelined block step of the chosen form, 0 if not timed */
+    int32_t reserved[4];
+} dmd_tuning_t;
+
+/* Measure and record the launch shapes for streams of shape (n, m, r, opts)
+ * (dense dtypes; no sparse tuning).  Runs on `stream` with streams and
+ * buffers of its own, filled with uniform random numbers (up to a block's
+ * modes, k r n complex64 values, for block streams):
+ *   * the one-frame Gram pass in each slab form, as back-to-back pushes;
+ *   * for FP32 block streams (max_block > 1) whose 2r = 8 (mod 16) lets two
+ *     windows fill whole 16-column tiles: the block step (push_block with
+ *     its solves on `stream`, block_modes on a second stream, overlapping
+ *     the next push) with one product per window and with window pairs;
+ * and keeps the fastest (the built-in rule's choice unless another is more
+ * than 2 % faster) in the process-wide table.  Streams created afterwards
+ * with the same key -- dtype, precision, n to within 1/8 octave, m, r,
+ * max_block -- use it; existing streams keep their shapes.  The table is
+ * loaded once from the file named by the environment variable
+ * DMD_TUNE_CACHE, if set.  Synchronous.  Errors: those of
+ * dmd_stream_create, DMD_E_UNSUPPORTED (sparse), DMD_E_NOMEM, DMD_E_DEVICE. */
+int dmd_tune(int64_t n, int32_t m, int32_t r, const dmd_opts_t* opts, dmd_tuning_t* out, void* stream);
+
+/* The table's entry for this shape; DMD_E_NOT_READY if there is none (streams
+ * then use the built-in rules). */
+int dmd_tune_lookup(int64_t n, int32_t m, int32_t r, const dmd_opts_t* opts, dmd_tuning_t* out);
+
+/* Write the table to a text file (one entry per line), or merge one into it.
+ * A malformed file is refused whole (DMD_E_INVAL). */
+int dmd_tune_save(const char* path);
+int dmd_tune_load(const char* path);
+
+/* Empty the table. */
+int dmd_tune_clear(void);
+
 /* ------------------------------------------------------------ introspection */
 
 typedef struct {
@@ -424,6 +467,8 @@ typedef struct {
     int32_t sweeps;         /* Jacobi sweeps of the latest solve */
     int32_t qr_iters;       /* Hessenberg-QR iterations of the latest solve */
     int64_t device_bytes;   /* device memory owned by the handle */
+    int32_t gram_iter;      /* launch shapes fixed at creation (see dmd_tuning_t); 0 for sparse */
+    int32_t proj_form;
 } dmd_info_t;
 
 /* Wait for the handle's work and describe it. */

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "dmd_stream.h"
+
 namespace dmd {
 
 // Device-resident state of one stream.  It lives at the start of the results
@@ -89,13 +91,19 @@ constexpr int kMaxR = 64;    // truncation rank
 // Per-workgroup partial sums (ingest fused), then a fixed-order reduction
 // kernel that rejects non-finite results or writes the new Gram row/column
 // and advances the window.
+// `iter` (1, 2 or 4) is the slab form: 16-byte loads per thread and column
+// in one workgroup's slab of rows (fixed per stream, see gram_iter_rule).
 template <typename T>
 hipError_t launch_gram_columns(const T* x, T* ring, int64_t ld, int64_t n, int m, int slots,
-                               double* partials, int nblk_cap, const DevState* st,
+                               double* partials, int nblk_cap, const DevState* st, int iter,
                                int* nblk_used, hipStream_t s);
 hipError_t launch_gram_finalize(double* G, const double* partials, int nblk, int m, int slots,
                                 DevState* st, hipStream_t s);
 int gram_push_blocks(int64_t n, int elem_bytes);
+// The slab form chosen when neither the tuning table nor DMD_GRAM_ITER
+// names one, and the workgroups of a slab form.
+int gram_iter_rule(int64_t n, int elem_bytes);
+int gram_blocks(int64_t n, int elem_bytes, int iter);
 
 // One stream's share of a grouped (batched) push: FP32 data.
 struct GramItem {
@@ -108,10 +116,9 @@ struct GramItem {
     DevState* st;
 };
 // Gram pass and finalize for many streams in two launches; the blocks of item
-// i are blk_start[i] .. blk_start[i+1]-1, with (iter, nblk) from gram_item_shape.
+// i are blk_start[i] .. blk_start[i+1]-1, each item in its stream's slab form.
 hipError_t launch_gram_grouped(const GramItem* items, const int* blk_start, int nitems, int total_blocks,
                                hipStream_t s);
-void gram_item_shape(int64_t n, int* iter, int* nblk);
 
 // Sparse complex snapshot: ingest into the CSR ring (with index checks),
 // Hermitian inner products through a dense scatter vector, fixed-order
@@ -250,6 +257,7 @@ struct BlockProjectArgs {
     float2* out;
     int64_t ldo, ldw;
     int bf16x3;                    // products as three BF16 MFMAs (DMD_PREC_BF16X3), else FP32
+    int form;                      // 0: rule, 1: one product per window, 2: window pairs where they apply
     int out16;                     // out, ldo and ldw allow 16-byte stores of two rows
     uint4* cfrag;                  // project_block_frag_bytes(m, kmax): packed coefficients
     BlockDesc* desc;               // packed ring position and ranks
@@ -337,5 +345,26 @@ int gram_full_splits(int m);
 size_t window_gram_scratch_bytes(int32_t ncols);
 hipError_t launch_window_gram(const void* X, int64_t ldx, int64_t n, int32_t ncols, int elem_f64, int32_t precision,
                               double* G, int64_t ldg, double* partial, hipStream_t s);
+
+// ------------------------------------------------------------------ tuning
+// Launch shapes chosen by measurement (dmd_tune) for a stream shape; a stream
+// created later with the same key takes them (else the built-in rules).
+struct TuneKey {
+    int dtype, precision, nbucket, m, r, kmax;
+    bool operator==(const TuneKey& o) const {
+        return dtype == o.dtype && precision == o.precision && nbucket == o.nbucket && m == o.m && r == o.r &&
+               kmax == o.kmax;
+    }
+};
+struct TuneVal {
+    int gram_iter;     // 0: rule
+    int proj_form;     // 0: rule, 1: per window, 2: window pairs
+    double gram_us;    // measured one-frame Gram pass of the choice
+    double step_us;    // measured pipelined block step of the choice (0: not measured)
+};
+TuneKey tune_key(int64_t n, int m, int r, const dmd_opts_t& o);
+bool tune_lookup(const TuneKey& k, TuneVal* v);
+void stream_get_shapes(const dmd_stream* h, int* gram_iter, int* proj_form);
+void stream_set_shapes(dmd_stream* h, int gram_iter, int proj_form);
 
 }  // namespace dmd

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -213,6 +214,10 @@ struct dmd_stream {
     int32_t reported_index = 0;
     int64_t device_bytes = 0;
     bool dry = false;             // sizing only (dmd_stream_footprint): count bytes, allocate nothing
+    // Launch shapes fixed at creation (DMD_GRAM_ITER, the tuning table, or
+    // the rules), so that a stream's results never change mid-stream:
+    int gram_iter = 0;            // slab form of the one-frame Gram pass (1, 2, 4)
+    int proj_form = 0;            // block projection: 0 rule, 1 per window, 2 window pairs
     // Snapshots pushed from host memory are copied here first (allocated by
     // the first such push): dense n elements; sparse max_nnz indices + values.
     void* stage = nullptr;
@@ -591,6 +596,17 @@ int create_impl(int64_t n, int32_t m, int32_t r, const dmd_opts_t* opts, dmd_str
         return fail(DMD_E_DEVICE, "no HIP device");
     }
 
+    if (!h->cplx) {
+        dmd::TuneVal tv{};
+        const bool tuned = dmd::tune_lookup(dmd::tune_key(n, m, r, o), &tv);
+        h->gram_iter = tuned && tv.gram_iter ? tv.gram_iter : dmd::gram_iter_rule(n, h->elem_bytes);
+        h->proj_form = tuned ? tv.proj_form : 0;
+        if (const char* e = getenv("DMD_GRAM_ITER")) {  // explicit override (tests, experiments)
+            const int v = atoi(e);
+            if (v == 1 || v == 2 || v == 4) h->gram_iter = v;
+        }
+    }
+
     int rc = DMD_OK;
     const int cw = h->cplx ? 2 : 1;
     const int M = m + (m & 1);
@@ -721,6 +737,16 @@ DMD_API int dmd_stream_create(int64_t n, int32_t m, int32_t r, const dmd_opts_t*
     return create_impl(n, m, r, opts, out, nullptr);
 }
 
+// Launch shapes of a stream (the tuner times candidates on streams of its own).
+void dmd::stream_get_shapes(const dmd_stream* h, int* gram_iter, int* proj_form) {
+    *gram_iter = h->gram_iter;
+    *proj_form = h->proj_form;
+}
+void dmd::stream_set_shapes(dmd_stream* h, int gram_iter, int proj_form) {
+    h->gram_iter = gram_iter;
+    h->proj_form = proj_form;
+}
+
 DMD_API int dmd_stream_footprint(int64_t n, int32_t m, int32_t r, const dmd_opts_t* opts, int64_t* bytes) {
     if (!bytes) return fail(DMD_E_INVAL, "null bytes");
     *bytes = 0;
@@ -804,9 +830,10 @@ DMD_API int dmd_stream_push(dmd_stream_t* h, const void* x, void* stream) {
         if (h->elem_bytes == 8)
             return dmd::launch_gram_columns<double>(static_cast<const double*>(x), static_cast<double*>(h->ring),
                                                     h->ld, h->n, h->m, h->slots, h->partials, h->nblk_cap, st,
-                                                    &nblk, s);
+                                                    h->gram_iter, &nblk, s);
         return dmd::launch_gram_columns<float>(static_cast<const float*>(x), static_cast<float*>(h->ring), h->ld,
-                                               h->n, h->m, h->slots, h->partials, h->nblk_cap, st, &nblk, s);
+                                               h->n, h->m, h->slots, h->partials, h->nblk_cap, st, h->gram_iter,
+                                               &nblk, s);
     });
     if (e == hipSuccess)
         e = timed("gram_finalize", s,
@@ -877,6 +904,7 @@ void fill_block_project_args(dmd_stream* h, dmd::BlockProjectArgs& a, int k, int
     a.Bphi_sets = static_cast<const float*>(h->sh_Bphi);
     a.bphi_stride = (int64_t)set_sizes(h).Bphi / sizeof(float);
     a.bf16x3 = h->opts.precision == DMD_PREC_BF16X3;
+    a.form = h->proj_form;
     a.cfrag = h->cfrag + (size_t)par * h->cfrag_elems;
     a.desc = h->bdesc + par;
 }
@@ -1607,6 +1635,8 @@ DMD_API int dmd_stream_info(dmd_stream_t* h, dmd_info_t* info) {
     info->sweeps = st.sweeps;
     info->qr_iters = st.qr_iters;
     info->device_bytes = h->device_bytes;
+    info->gram_iter = h->gram_iter;
+    info->proj_form = h->proj_form;
     return DMD_OK;
 }
 
@@ -1875,7 +1905,8 @@ DMD_API int dmd_batch_tick(dmd_batch_t* b, int32_t count, dmd_stream_t* const* s
         it.m = h->m;
         it.slots = h->slots;
         it.x_aligned = ((uintptr_t)snapshots[i] % 16) == 0;
-        dmd::gram_item_shape(h->n, &it.iter, &it.nblk);
+        it.iter = h->gram_iter;
+        it.nblk = dmd::gram_blocks(h->n, h->elem_bytes, h->gram_iter);
         it.partials = h->partials;
         it.G = h->G;
         it.st = reinterpret_cast<DevState*>(h->res_dev);

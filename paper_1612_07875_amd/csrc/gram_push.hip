@@ -15,8 +15,6 @@
 // each 64-wide wavefront, waves summed in index order, then workgroup
 // partials summed in a fixed order by a small finalize kernel.  No
 // floating-point atomics are used, so every run is bitwise identical.
-#include <cstdlib>
-
 #include "dmd_internal.h"
 
 namespace dmd {
@@ -284,17 +282,6 @@ void k_gram_columns_grouped(const GramItem* __restrict__ items, const int* __res
     }
 }
 
-template <typename T> int iter_for(int64_t n) {
-    // The largest slab (up to 4 x 16-byte loads per thread and column) that
-    // still gives at least 256 workgroups, one per CU: big slabs keep many
-    // requests in flight and leave few partial sums for the finalize kernel.
-    constexpr int N = Vec16<T>::N;
-    const int64_t per_iter = (int64_t)kThreads * N;
-    if (n >= per_iter * 4 * 256) return 4;
-    if (n >= per_iter * 2 * 256) return 2;
-    return 1;
-}
-
 template <typename T> int blocks_for(int64_t n, int iter) {
     const int64_t slab = (int64_t)kThreads * Vec16<T>::N * iter;
     return (int)((n + slab - 1) / slab);
@@ -307,14 +294,24 @@ int gram_push_blocks(int64_t n, int elem_bytes) {
     return elem_bytes == 8 ? blocks_for<double>(n, 1) : blocks_for<float>(n, 1);
 }
 
+int gram_iter_rule(int64_t n, int elem_bytes) {
+    // The largest slab (up to 4 x 16-byte loads per thread and column) that
+    // still gives at least 256 workgroups, one per CU: big slabs keep many
+    // requests in flight and leave few partial sums for the finalize kernel.
+    const int64_t per_iter = (int64_t)kThreads * (16 / elem_bytes);
+    if (n >= per_iter * 4 * 256) return 4;
+    if (n >= per_iter * 2 * 256) return 2;
+    return 1;
+}
+
+int gram_blocks(int64_t n, int elem_bytes, int iter) {
+    return elem_bytes == 8 ? blocks_for<double>(n, iter) : blocks_for<float>(n, iter);
+}
+
 template <typename T>
 hipError_t launch_gram_columns(const T* x, T* ring, int64_t ld, int64_t n, int m, int slots, double* partials,
-                               int nblk_cap, const DevState* st, int* nblk_used, hipStream_t s) {
-    int iter = iter_for<T>(n);
-    if (const char* e = getenv("DMD_GRAM_ITER")) {
-        const int v = atoi(e);
-        if (v == 1 || v == 2 || v == 4) iter = v;
-    }
+                               int nblk_cap, const DevState* st, int iter, int* nblk_used, hipStream_t s) {
+    if (iter != 1 && iter != 2 && iter != 4) return hipErrorInvalidValue;
     const int nblk = blocks_for<T>(n, iter);
     if (nblk > nblk_cap) return hipErrorInvalidValue;
     *nblk_used = nblk;
@@ -334,20 +331,6 @@ hipError_t launch_gram_finalize(double* G, const double* partials, int nblk, int
     return hipGetLastError();
 }
 
-static int stream_iter(int64_t n) {
-    int iter = iter_for<float>(n);
-    if (const char* e = getenv("DMD_GRAM_ITER")) {
-        const int v = atoi(e);
-        if (v == 1 || v == 2 || v == 4) iter = v;
-    }
-    return iter;
-}
-
-void gram_item_shape(int64_t n, int* iter, int* nblk) {
-    *iter = stream_iter(n);
-    *nblk = blocks_for<float>(n, *iter);
-}
-
 hipError_t launch_gram_grouped(const GramItem* items, const int* blk_start, int nitems, int total_blocks,
                                hipStream_t s) {
     hipLaunchKernelGGL(k_gram_columns_grouped, dim3(total_blocks), dim3(kThreads), 0, s, items, blk_start,
@@ -359,8 +342,8 @@ hipError_t launch_gram_grouped(const GramItem* items, const int* blk_start, int 
 }
 
 template hipError_t launch_gram_columns<float>(const float*, float*, int64_t, int64_t, int, int, double*, int,
-                                               const DevState*, int*, hipStream_t);
+                                               const DevState*, int, int*, hipStream_t);
 template hipError_t launch_gram_columns<double>(const double*, double*, int64_t, int64_t, int, int, double*, int,
-                                                const DevState*, int*, hipStream_t);
+                                                const DevState*, int, int*, hipStream_t);
 
 }  // namespace dmd

@@ -628,6 +628,9 @@ void k_pack_coef(BlockProjectArgs a) {
 // the CUs and run after it instead of beside it (measured: the per-window
 // form with two windows of fragments in flight wins there).
 constexpr int kPairMaxTiles = 3;
+// With the pair form asked for by the stream's tuned shape (measured in the
+// pipeline by dmd_tune), up to five tiles (r = 20).
+constexpr int kPairMaxTilesTuned = 5;
 
 struct PairShape {
     int nfull;  // whole 8-step chunks
@@ -637,12 +640,15 @@ __host__ __device__ inline PairShape pair_shape(int m) {
     const int nsteps = (m + 1 + 3) / 4;
     return PairShape{nsteps / 8, nsteps % 8};
 }
-// Whether the pair form applies: FP32, 2r = 8 mod 16, at most kPairMaxTiles
-// tiles, at least one whole chunk and at most one tail step.
+// Whether the pair form applies: FP32, 2r = 8 mod 16, at least one whole
+// chunk and at most one tail step, and at most kPairMaxTiles tiles (the rule,
+// form 0) or kPairMaxTilesTuned (form 2); never for form 1.
 bool use_pairs(const BlockProjectArgs& a) {
+    if (a.bf16x3 || a.form == 1) return false;
     const int tiles = 4 * a.r / 16;
     const PairShape ps = pair_shape(a.m);
-    return !a.bf16x3 && (2 * a.r) % 16 == 8 && tiles <= kPairMaxTiles && ps.nfull >= 1 && ps.tail <= 1;
+    if ((2 * a.r) % 16 != 8 || ps.nfull < 1 || ps.tail > 1) return false;
+    return tiles <= (a.form == 2 ? kPairMaxTilesTuned : kPairMaxTiles);
 }
 size_t pair_lds(int m, int k) {
     const PairShape ps = pair_shape(m);
@@ -858,7 +864,8 @@ hipError_t launch_block_nt(const BlockProjectArgs& a, hipStream_t s) {
 size_t project_block_frag_bytes(int m, int kmax) {
     const PairShape ps = pair_shape(m);
     const size_t per_window = (size_t)kmax * ((m + 31) / 32) * 4 * 64 * 32;
-    const size_t pairs = (size_t)((kmax + 1) / 2) * (8 * ps.nfull + ps.tail) * kPairMaxTiles * 64 * sizeof(float);
+    const size_t pairs =
+        (size_t)((kmax + 1) / 2) * (8 * ps.nfull + ps.tail) * kPairMaxTilesTuned * 64 * sizeof(float);
     return per_window > pairs ? per_window : pairs;
 }
 
@@ -896,6 +903,7 @@ hipError_t launch_pair(const BlockProjectArgs& a, hipStream_t s, bool pack) {
     switch (4 * a.r / 16) {
         case 1: return launch_pair_ntg<1>(a, s, pack);
         case 3: return launch_pair_ntg<3>(a, s, pack);
+        case 5: return launch_pair_ntg<5>(a, s, pack);
         default: return hipErrorInvalidValue;
     }
 }
