@@ -54,7 +54,13 @@ class Info(ctypes.Structure):
         ("n", ctypes.c_int64), ("m", ctypes.c_int32), ("r", ctypes.c_int32), ("dtype", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("count", ctypes.c_int32), ("r_eff", ctypes.c_int32),
         ("sweeps", ctypes.c_int32), ("qr_iters", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
+        ("gram_iter", ctypes.c_int32), ("proj_form", ctypes.c_int32),
     ]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("gram_iter", ctypes.c_int32), ("proj_form", ctypes.c_int32), ("gram_us", ctypes.c_double),
+                ("step_us", ctypes.c_double), ("reserved", ctypes.c_int32 * 4)]
 
 
 _P = ctypes.c_void_p
@@ -95,6 +101,11 @@ SIGNATURES = {
     "dmd_stream_resync": [_P, _P],
     "dmd_window_gram": [_P, _I64, _I64, _I32, _I32, _I32, _P, _I64, _P],
     "dmd_stream_info": [_P, ctypes.POINTER(Info)],
+    "dmd_tune": [_I64, _I32, _I32, ctypes.POINTER(Opts), ctypes.POINTER(Tuning), _P],
+    "dmd_tune_lookup": [_I64, _I32, _I32, ctypes.POINTER(Opts), ctypes.POINTER(Tuning)],
+    "dmd_tune_save": [ctypes.c_char_p],
+    "dmd_tune_load": [ctypes.c_char_p],
+    "dmd_tune_clear": [],
     "dmd_batch_opts_init": [ctypes.POINTER(BatchOpts)],
     "dmd_batch_create": [ctypes.POINTER(BatchOpts), ctypes.POINTER(_P)],
     "dmd_batch_destroy": [_P],
@@ -214,6 +225,42 @@ def window_gram(X: torch.Tensor, precision: str = "default", out: Optional[torch
     check(load().dmd_window_gram(X.data_ptr(), X.stride(0), X.shape[1], k, dt, PRECISIONS[precision],
                                  out.data_ptr(), out.stride(0), _stream_ptr(stream)))
     return out
+
+
+def _tuning_dict(t: Tuning) -> dict:
+    return {"gram_iter": int(t.gram_iter), "proj_form": int(t.proj_form), "gram_us": float(t.gram_us),
+            "step_us": float(t.step_us)}
+
+
+def tune(n: int, m: int, r: int, stream=None, **opts) -> dict:
+    """Measure and record the launch shapes of streams of shape (n, m, r, **opts)
+    (see dmd_tune); streams created afterwards with that shape use them."""
+    t = Tuning()
+    check(load().dmd_tune(int(n), int(m), int(r), ctypes.byref(make_opts(**opts)), ctypes.byref(t),
+                          _stream_ptr(stream)))
+    return _tuning_dict(t)
+
+
+def tune_lookup(n: int, m: int, r: int, **opts) -> Optional[dict]:
+    """The tuning table's entry for this shape, or None."""
+    t = Tuning()
+    rc = load().dmd_tune_lookup(int(n), int(m), int(r), ctypes.byref(make_opts(**opts)), ctypes.byref(t))
+    if rc == E_NOT_READY:
+        return None
+    check(rc)
+    return _tuning_dict(t)
+
+
+def tune_save(path: str) -> None:
+    check(load().dmd_tune_save(os.fsencode(path)))
+
+
+def tune_load(path: str) -> None:
+    check(load().dmd_tune_load(os.fsencode(path)))
+
+
+def tune_clear() -> None:
+    check(load().dmd_tune_clear())
 
 
 class Stream:
