@@ -30,6 +30,18 @@ def _dmd():
     return dmd
 
 
+def padded_columns(F):
+    """The columns of F (n x k) as a (k, n) CUDA view whose rows start 16-byte
+    aligned (leading dimension n rounded up to 16 bytes), as the stateless
+    Gram requires; ragged n is then the caller's padding, not a copy."""
+    n, k = F.shape
+    per = 16 // F.dtype.itemsize
+    ld = (n + per - 1) // per * per
+    Xp = torch.zeros((k, ld), dtype=torch.float32 if F.dtype == np.float32 else torch.float64, device="cuda")
+    Xp[:, :n] = torch.from_numpy(F.T.copy()).cuda()
+    return Xp[:, :n]
+
+
 def gram_err(G, ref):
     d = np.sqrt(np.outer(np.abs(np.diag(ref)), np.abs(np.diag(ref))))
     return np.max(np.abs(G - ref) / d)
@@ -148,7 +160,7 @@ def test_stateless_window_gram(dtype, prec, tol, n, k):
     dmd = _dmd()
     v = gen.BlobVideo(height=(n + 127) // 128, width=128, n=n, blob_sigma=5.0)
     F = v.frames(0, k).astype(np.float32 if dtype == "f32" else np.float64)
-    X = torch.from_numpy(F.T.copy()).cuda()
+    X = padded_columns(F)
     G = dmd.window_gram(X, precision=prec).cpu().numpy()
     ref = oracle.gram(F)
     assert np.array_equal(G, G.T)
