@@ -87,6 +87,40 @@ __device__ __forceinline__ double rcp_acc(double x) {
     return fma(y, fma(-x, y, 1.0), y);
 }
 
+// A double from another lane of the same 16-lane row, by a DPP lane pattern
+// (a register move, no trip through the LDS crossbar as __shfl_xor takes).
+template <int CTRL> __device__ __forceinline__ double dpp_f64(double x) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffull), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+// Sum over each aligned group of G lanes (G = 1, 2, 4, .., 64; every lane of
+// the group active), the same value in every lane of the group: neighbour
+// pairs, then pairs of pairs (quad permutations 1,0,3,2 and 2,3,0,1); then
+// the mirror of each 8-lane half-row and of each 16-lane row, which read a
+// lane of the other half whose partial sum equals its own by then; then the
+// 16- and 32-lane halves through __shfl_xor.  Each step adds a value to its
+// partner's in either order, so all lanes end bitwise equal.
+__device__ __forceinline__ double group_sum(double x, int G) {
+    if (G >= 2) x += dpp_f64<0xB1>(x);
+    if (G >= 4) x += dpp_f64<0x4E>(x);
+    if (G >= 8) x += dpp_f64<0x141>(x);
+    if (G >= 16) x += dpp_f64<0x140>(x);
+    if (G >= 32) x += __shfl_xor(x, 16, 64);
+    if (G >= 64) x += __shfl_xor(x, 32, 64);
+    return x;
+}
+__device__ __forceinline__ cplx group_sum(cplx x, int G) { return cplx{group_sum(x.re, G), group_sum(x.im, G)}; }
+__device__ __forceinline__ double wave_sum(double x) { return group_sum(x, 64); }
+__device__ __forceinline__ double wave_max(double x) {
+    x = fmax(x, dpp_f64<0xB1>(x));
+    x = fmax(x, dpp_f64<0x4E>(x));
+    x = fmax(x, dpp_f64<0x141>(x));
+    x = fmax(x, dpp_f64<0x140>(x));
+    x = fmax(x, __shfl_xor(x, 16, 64));
+    return fmax(x, __shfl_xor(x, 32, 64));
+}
 // Rotation (c, s) with c^2 + s^2 = 1 to working precision that annihilates
 // the off-diagonal of the real 2x2 [[a, g], [g, b]] (g > 0): t = tan(phi) is
 // the root of t^2 + 2 theta t - 1 = 0 of smaller modulus, theta = (b-a)/(2g).
@@ -757,7 +791,7 @@ __device__ void solve_eig_body(const SolveArgs& a) {
         const int len = k - c - 1;  // rows c+1 .. k-1
         double tail2 = 0.0;
         if (lane >= 1 && lane < len) tail2 = abs2(H[(c + 1 + lane) + c * LDH]);
-        for (int off = 32; off >= 1; off >>= 1) tail2 += __shfl_xor(tail2, off, 64);
+        tail2 = wave_sum(tail2);
         const cplx x0 = H[(c + 1) + c * LDH];
         const double ax0 = cabs(x0);
         const double alpha = sqrt(ax0 * ax0 + tail2);
@@ -808,7 +842,7 @@ __device__ void solve_eig_body(const SolveArgs& a) {
     // rotation; complex A~ by the single-shift complex QR
     double hmax = 0.0;
     for (int idx = lane; idx < k * k; idx += 64) hmax = fmax(hmax, cabs(H[(idx % k) + (idx / k) * LDH]));
-    for (int off = 32; off >= 1; off >>= 1) hmax = fmax(hmax, __shfl_xor(hmax, off, 64));
+    hmax = wave_max(hmax);
     const double smallnum = (hmax > 0.0 ? hmax : 1.0) * kEps;
 
     int total = 0;
@@ -1288,6 +1322,7 @@ template <> __device__ __forceinline__ double shfl_xor_s<double>(double v, int o
 template <> __device__ __forceinline__ cplx shfl_xor_s<cplx>(cplx v, int off, int width) {
     return cplx{__shfl_xor(v.re, off, width), __shfl_xor(v.im, off, width)};
 }
+
 __device__ __forceinline__ double div_s(double a, double b) { return a / b; }
 __device__ __forceinline__ cplx div_s(cplx a, cplx b) { return cdiv(a, b); }
 
@@ -1305,7 +1340,7 @@ __device__ void householder_col(S* A, int ld, int n, int j, S* vbuf, S* s_tau, d
         const double ax = SC::absv(col[i]);
         xn2 += ax * ax;
     }
-    for (int off = 32; off >= 1; off >>= 1) xn2 += __shfl_xor(xn2, off, 64);
+    xn2 = wave_sum(xn2);
     const S alpha = col[0];
     const double ar = SC::re(alpha), aa = SC::absv(alpha);
     S tau = SC::zero(), scal = SC::zero();
@@ -1397,14 +1432,14 @@ __device__ void solve_trid_body(const SolveArgs& a) {
                 S acc = SC::zero();
                 const S* ci = A22 + (size_t)i * ld;
                 for (int k = gl; k < L; k += G) acc = acc + mulr(SC::cj(ci[k]), v[k]);
-                for (int off = G >> 1; off >= 1; off >>= 1) acc = acc + shfl_xor_s<S>(acc, off, 64);
+                acc = group_sum(acc, G);
                 if (gl == 0) s_p[i] = mulr(tau, acc);
             }
         }
         __syncthreads();
         S pv = SC::zero();
         for (int k = lane; k < L; k += 64) pv = pv + mulr(SC::cj(s_p[k]), v[k]);
-        for (int off = 32; off >= 1; off >>= 1) pv = pv + shfl_xor_s<S>(pv, off, 64);
+        pv = group_sum(pv, 64);
         const S c = mulr(tau, pv) * (-0.5);
         if (wv == 0) {
             const S v0 = v[0], w0 = s_p[0] + mulr(c, v0);
@@ -1616,14 +1651,14 @@ __device__ void solve_trid_body(const SolveArgs& a) {
                 const S* zp = Zs + (size_t)p * n;
                 double dot = 0.0;
                 for (int i = lane; i < n; i += 64) dot += SC::re(zp[i]) * SC::re(zq[i]);
-                for (int off = 32; off >= 1; off >>= 1) dot += __shfl_xor(dot, off, 64);
+                dot = wave_sum(dot);
                 double nn = 0.0;
                 for (int i = lane; i < n; i += 64) {
                     const double zi = SC::re(zq[i]) - dot * SC::re(zp[i]);
                     zq[i] = SC::fromc(mkc(zi));
                     nn += zi * zi;
                 }
-                for (int off = 32; off >= 1; off >>= 1) nn += __shfl_xor(nn, off, 64);
+                nn = wave_sum(nn);
                 const double sc = nn > 0.0 ? rsqrt_acc(nn) : 0.0;
                 for (int i = lane; i < n; i += 64) zq[i] = zq[i] * sc;
             }

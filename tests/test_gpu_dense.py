@@ -10,7 +10,13 @@ Tolerances:
 * sigma_k: the method of snapshots squares the condition number, so FP64
   rounding of the Gram moves sigma_k by ~ u (sigma_1/sigma_k)^2:
   tol_k = 1e-11 + 1e-13 (sigma_1/sigma_k)^2.
-* lambda (matched): 1e-8; W, V, A~: 1e-7 (FP64 solves, well-separated data).
+* lambda (matched), per eigenvalue: 1e-13 + 32 u kappa_i, kappa_i the
+  eigenvalue's first-order sensitivity to a Gram perturbation of size
+  sigma_1^2 (metrics.eig_sensitivity): the method of snapshots solves from
+  the FP64 Gram, whose rounding (u sigma_1^2 per entry) moves lambda_i by up
+  to u kappa_i; the oracle's own Gram and SVD routes differ by at most
+  0.46 u kappa_i on these workloads.  W, V, A~: 1e-7 (FP64 solves,
+  well-separated data).
 * Phi, U with FP64 projections: 1e-8; with FP32 projections (FP32
   coefficients, FP32 accumulation over m terms): 2e-4 relative per column.
 """
@@ -35,6 +41,20 @@ def sigma_tol(sig):
     return 1e-11 + 1e-13 * (sig[0] / sig) ** 2
 
 
+def eig_bound(ref):
+    """Bound on the relative error of each eigenvalue, in ref's order (see the
+    module docstring): 1e-13 + 32 u kappa_i."""
+    return 1e-13 + 32 * 2.0 ** -52 * metrics.eig_sensitivity(ref)
+
+
+def check_lambda(lam, ref):
+    """Matched eigenvalue errors against eig_bound; returns the matching."""
+    err_l, perm = metrics.eig_relerr(lam, ref.lam)
+    bound = eig_bound(ref)[perm]
+    assert np.all(err_l <= bound), (err_l, bound)
+    return err_l, perm
+
+
 def check_window(s, frames_window, m, r, phi_tol, pod=False, check_matrices=True):
     """Compare the GPU's latest solve with the oracle on the given (n, m+1) window."""
     F = oracle.as_fp64(frames_window)
@@ -45,8 +65,7 @@ def check_window(s, frames_window, m, r, phi_tol, pod=False, check_matrices=True
     assert k == ref.r_eff, (k, ref.r_eff)
     err_s = metrics.sigma_relerr(sig, ref.sigma[:k])
     assert np.all(err_s <= sigma_tol(ref.sigma[:k])), err_s
-    err_l, perm = metrics.eig_relerr(lam, ref.lam)
-    assert err_l.max() < 1e-8, err_l.max()
+    err_l, perm = check_lambda(lam, ref)
     if check_matrices:
         sg_all, V, _ = s.svd()
         np.testing.assert_allclose(sg_all[:k], sig, rtol=0, atol=0)
