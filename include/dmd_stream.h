@@ -414,6 +414,23 @@ int dmd_stream_resync(dmd_stream_t* h, void* stream);
 int dmd_window_gram(const void* X, int64_t ldx, int64_t n, int32_t ncols, int32_t dtype,
                     int32_t precision, double* G, int64_t ldg, void* stream);
 
+/* dmd_window_gram without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, checks, kernels and results as
+ * dmd_window_gram (bitwise equal); the kernel's partial tiles go to a fixed
+ * device array of the library (17,203,200 bytes, enough for the largest
+ * window, ncols = 257), one per device, held until the process ends.  Its
+ * address on a device is looked up on the first call there (on the device
+ * that runs `stream`).  No hipMalloc, hipFree or allocating library call.
+ * Every call on one device shares that array: calls that overlap on one
+ * device (different streams, or different host threads) race and may return
+ * wrong results; order them on one stream or synchronize between them.
+ * Errors: as dmd_window_gram (DMD_E_INVAL also for a window whose partial
+ * tiles would exceed the array), and DMD_E_DEVICE if the array's address
+ * cannot be looked up. */
+int dmd_window_gram_noalloc(const void* X, int64_t ldx, int64_t n, int32_t ncols, int32_t dtype,
+                            int32_t precision, double* G, int64_t ldg, void* stream);
+
 /* ------------------------------------------------------------ launch-shape tuning */
 
 /* Launch shapes of a dense stream shape, chosen by measurement. */

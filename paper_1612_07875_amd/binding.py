@@ -100,6 +100,7 @@ SIGNATURES = {
     "dmd_stream_load_window": [_P, _P, _I64, _I32, _P],
     "dmd_stream_resync": [_P, _P],
     "dmd_window_gram": [_P, _I64, _I64, _I32, _I32, _I32, _P, _I64, _P],
+    "dmd_window_gram_noalloc": [_P, _I64, _I64, _I32, _I32, _I32, _P, _I64, _P],
     "dmd_stream_info": [_P, ctypes.POINTER(Info)],
     "dmd_tune": [_I64, _I32, _I32, ctypes.POINTER(Opts), ctypes.POINTER(Tuning), _P],
     "dmd_tune_lookup": [_I64, _I32, _I32, ctypes.POINTER(Opts), ctypes.POINTER(Tuning)],
@@ -209,9 +210,12 @@ def footprint(n: int, m: int, r: int, **opts) -> int:
 
 
 def window_gram(X: torch.Tensor, precision: str = "default", out: Optional[torch.Tensor] = None,
-                stream=None) -> torch.Tensor:
+                stream=None, noalloc: bool = False) -> torch.Tensor:
     """G = X^* X (FP64, k x k on the device) of the columns of X, given as a
-    (k, n) CUDA tensor whose rows are the snapshots (column-major n x k)."""
+    (k, n) CUDA tensor whose rows are the snapshots (column-major n x k).
+    noalloc: call dmd_window_gram_noalloc (the library's fixed scratch instead
+    of a stream-ordered allocation); pass `out` as well for a call that
+    allocates nothing at all."""
     if not (X.is_cuda and X.dim() == 2 and X.stride(1) == 1 and X.dtype in (torch.float32, torch.float64)):
         raise ValueError("X must be a (k, n) float32/float64 CUDA tensor with unit stride along n")
     k = X.shape[0]
@@ -222,8 +226,9 @@ def window_gram(X: torch.Tensor, precision: str = "default", out: Optional[torch
         raise ValueError("out must be a float64 CUDA tensor of at least k x k with unit inner stride")
     dt = DTYPES["f32"] if X.dtype == torch.float32 else DTYPES["f64"]
     # out is row-major (k, ldg): read as column-major it is G^T = G
-    check(load().dmd_window_gram(X.data_ptr(), X.stride(0), X.shape[1], k, dt, PRECISIONS[precision],
-                                 out.data_ptr(), out.stride(0), _stream_ptr(stream)))
+    fn = load().dmd_window_gram_noalloc if noalloc else load().dmd_window_gram
+    check(fn(X.data_ptr(), X.stride(0), X.shape[1], k, dt, PRECISIONS[precision], out.data_ptr(), out.stride(0),
+             _stream_ptr(stream)))
     return out
 
 

@@ -6,8 +6,14 @@
 // The row-split partial tiles of the kernel (splits x upper-triangle tiles x
 // 64 x 64 FP64) are stream-ordered scratch: allocated with hipMallocAsync on
 // the caller's stream and freed after the reduction with hipFreeAsync.
+//
+// The allocation-free variant (dmd_window_gram_noalloc) takes the partial
+// tiles from a fixed device array instead, sized for the largest window the
+// call accepts; its address on each device is looked up once, with that
+// device current, and used for every later call there.
 #include <cstdarg>
 #include <cstdio>
+#include <mutex>
 #include <string>
 
 #include "dmd_internal.h"
@@ -51,7 +57,70 @@ hipError_t launch_window_gram(const void* X, int64_t ldx, int64_t n, int32_t nco
     return launch_gram_full(X, ldx, n, ncols - 1, (int)ldg, elem_f64, precision, ncols, 0, partial, G, nullptr, 0, s);
 }
 
+// Scratch of the allocation-free call: the partial tiles of the largest window
+// (257 columns: 15 upper-triangle tiles x 35 row splits; no smaller window
+// needs more), one copy per device, held until the process ends.  Every
+// partial tile is written in full by each call, so nothing needs clearing.
+// Host code never uses this name as an address: the device address comes
+// from noalloc_scratch() below.
+constexpr size_t kNoAllocTiles = 525;
+constexpr size_t kNoAllocBytes = kNoAllocTiles * 64 * 64 * sizeof(double);  // 17,203,200 bytes
+static __device__ __align__(256) double scratch[kNoAllocTiles * 64 * 64];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// The device address of `scratch` on the device that runs `s`; looked up once
+// per device (with that device current) and kept.
+int noalloc_scratch(hipStream_t s, void** out) {
+    int cur = 0, dev = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return api_fail(DMD_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    dev = cur;
+    if (s) {
+        e = hipStreamGetDevice(s, &dev);
+        if (e != hipSuccess) return api_fail(DMD_E_INVAL, "hipStreamGetDevice: %s", hipGetErrorString(e));
+    }
+    if (dev < 0 || dev >= kMaxDevices) return api_fail(DMD_E_DEVICE, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        if (dev != cur && (e = hipSetDevice(dev)) != hipSuccess)
+            return api_fail(DMD_E_DEVICE, "hipSetDevice(%d): %s", dev, hipGetErrorString(e));
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        const hipError_t eback = dev != cur ? hipSetDevice(cur) : hipSuccess;
+        if (e != hipSuccess || !p)
+            return api_fail(DMD_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        if (eback != hipSuccess)
+            return api_fail(DMD_E_DEVICE, "hipSetDevice(%d): %s", cur, hipGetErrorString(eback));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return DMD_OK;
+}
+
 }  // namespace dmd
+
+DMD_API int dmd_window_gram_noalloc(const void* X, int64_t ldx, int64_t n, int32_t ncols, int32_t dtype,
+                                    int32_t precision, double* G, int64_t ldg, void* stream) {
+    int eb = 0;
+    if (int rc = dmd::check_window_gram(X, ldx, n, ncols, dtype, precision, G, ldg, &eb)) return rc;
+    if (ldg > INT32_MAX) return dmd::api_fail(DMD_E_INVAL, "ldg too large");
+    const size_t need = dmd::window_gram_scratch_bytes(ncols);
+    if (need > dmd::kNoAllocBytes)
+        return dmd::api_fail(DMD_E_INVAL, "%d columns need %zu bytes of scratch; the allocation-free call holds %zu",
+                             ncols, need, dmd::kNoAllocBytes);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    void* partial = nullptr;
+    if (int rc = dmd::noalloc_scratch(s, &partial)) return rc;
+    const hipError_t e =
+        dmd::launch_window_gram(X, ldx, n, ncols, eb == 8, precision, G, ldg, static_cast<double*>(partial), s);
+    if (e != hipSuccess) return dmd::api_fail(DMD_E_DEVICE, "window Gram launch: %s", hipGetErrorString(e));
+    return DMD_OK;
+}
 
 DMD_API int dmd_window_gram(const void* X, int64_t ldx, int64_t n, int32_t ncols, int32_t dtype,
                             int32_t precision, double* G, int64_t ldg, void* stream) {
