@@ -67,8 +67,8 @@ def parse():
                          "(hi*hi + hi*lo + lo*hi) with FP32 accumulation")
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default 20 blocks / 100 frames)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 2 blocks / 10 frames)")
-    ap.add_argument("--latency-frames", type=int, default=40, help="single-frame pushes timed one by one")
-    ap.add_argument("--latency-blocks", type=int, default=5, help="block mode: blocks timed one by one")
+    ap.add_argument("--latency-frames", type=int, default=400, help="single-frame pushes timed one by one")
+    ap.add_argument("--latency-blocks", type=int, default=20, help="block mode: blocks timed one by one")
     ap.add_argument("--cpu-windows", type=int, default=4, help="windows in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-split", action="store_true",

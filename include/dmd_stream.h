@@ -438,7 +438,8 @@ typedef struct {
     int32_t gram_iter;   /* one-frame Gram pass: 16-byte loads per thread and column in a
                             workgroup's slab of rows (1, 2 or 4; fewer, larger slabs) */
     int32_t proj_form;   /* block projection (FP32 block streams): 0 built-in rule,
-                            1 one product per window, 2 two windows per product */
+                            1 one product per window, 2 two windows per product,
+                            3 one banded product of all windows */
     double gram_us;      /* measured one-frame Gram pass (push without solves) of the choice */
     double step_us;      /* measured pipelined block step of the chosen form, 0 if not timed */
     int32_t reserved[4];
@@ -449,12 +450,17 @@ typedef struct {
  * buffers of its own, filled with uniform random numbers (up to a block's
  * modes, k r n complex64 values, for block streams):
  *   * the one-frame Gram pass in each slab form, as back-to-back pushes;
- *   * for FP32 block streams (max_block > 1) whose 2r = 8 (mod 16) lets two
- *     windows fill whole 16-column tiles: the block step (push_block with
- *     its solves on `stream`, block_modes on a second stream, overlapping
- *     the next push) with one product per window and with window pairs;
- * and keeps the fastest (the built-in rule's choice unless another is more
- * than 2 % faster) in the process-wide table.  Streams created afterwards
+ *   * for FP32 block streams (max_block > 1): the block step (push_block
+ *     with its solves on `stream`, block_modes on a second stream,
+ *     overlapping the next push) with one product per window, with window
+ *     pairs (where 2r = 8 (mod 16) lets two windows fill whole 16-column
+ *     tiles) and with one banded product of all windows (where its staged
+ *     rows, 128 x (m + max_block) FP32 values, fit the workgroup memory);
+ * and keeps the fastest (the built-in rule's choice -- the banded product
+ * where a fixed-step form of it applies (windows up to about m = 70), else
+ * window pairs where they fill at most three tiles, else one product per
+ * window -- unless another is more than 2 % faster) in the process-wide
+ * table.  Streams created afterwards
  * with the same key -- dtype, precision, n to within 1/8 octave, m, r,
  * max_block -- use it; existing streams keep their shapes.  The table is
  * loaded once from the file named by the environment variable

@@ -243,6 +243,8 @@ struct BlockDesc {
     int base;         // ring slot of the union's first column (before the wrap)
     int pad[2];
     int kc[64];       // 2 r_eff of window w, 0 if it has no solve
+    float sink[64 * 4];  // 16 bytes per lane that a projection writes instead of
+                         // columns it must leave untouched (never read)
 };
 struct BlockProjectArgs {
     const void* ring;
@@ -257,7 +259,8 @@ struct BlockProjectArgs {
     float2* out;
     int64_t ldo, ldw;
     int bf16x3;                    // products as three BF16 MFMAs (DMD_PREC_BF16X3), else FP32
-    int form;                      // 0: rule, 1: one product per window, 2: window pairs where they apply
+    int form;                      // 0: rule, 1: one product per window, 2: window pairs where they apply,
+                                   // 3: one banded product of all windows (FP32)
     int out16;                     // out, ldo and ldw allow 16-byte stores of two rows
     uint4* cfrag;                  // project_block_frag_bytes(m, kmax): packed coefficients
     BlockDesc* desc;               // packed ring position and ranks
@@ -268,7 +271,13 @@ hipError_t launch_pack_block(const BlockProjectArgs& a, hipStream_t s);
 hipError_t launch_project_block(const BlockProjectArgs& a, hipStream_t s);
 // Whether the one-pass block projection's LDS tiles fit for these sizes.
 bool project_block_fits(int m, int k, int r);
-size_t project_block_frag_bytes(int m, int kmax);
+size_t project_block_frag_bytes(int m, int r, int kmax);
+// Whether the window-pair form (2r = 8 mod 16) or the banded form (its stage
+// fits) can run an FP32 block of k windows.
+bool pairs_apply(int m, int r, int k);
+bool band_applies(int m, int r, int k);
+// The form the built-in rule takes for an FP32 block of k windows (1 or 2).
+int block_rule_form(int m, int r, int k);
 
 // Background subtraction of the newest snapshot (Sec. 3.3, Algorithm 3): with
 // beta = b_i lambda_i^m C[:, i] (background mode i, written by the eig solve),

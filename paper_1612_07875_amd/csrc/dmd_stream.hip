@@ -666,7 +666,7 @@ int create_impl(int64_t n, int32_t m, int32_t r, const dmd_opts_t* opts, dmd_str
         ALLOC(h->sh_Vfull, sizeof(double) * ns * z.Vfull);
         ALLOC(h->sh_Bphi, ns * z.Bphi);
         ALLOC(h->sh_Bpod, ns * z.Bpod);
-        h->cfrag_elems = dmd::project_block_frag_bytes(m, h->kmax) / sizeof(uint4);
+        h->cfrag_elems = dmd::project_block_frag_bytes(m, r, h->kmax) / sizeof(uint4);
         ALLOC(h->cfrag, 2 * h->cfrag_elems * sizeof(uint4));
         ALLOC(h->bdesc, 2 * sizeof(dmd::BlockDesc));
         if (rc == DMD_OK && !dry) {

@@ -339,6 +339,36 @@ hipError_t launch_bf3_nt(const ProjectArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Stage rows row0 .. row0 + ROWS - 1 of `ncols` ring columns, the first in
+// slot `base` (wrapping at `slots`), as LDS columns 0 .. ntot - 1: put(c, r4,
+// x) stores the four rows from r4 of column c.  Columns from ncols on and
+// rows at or past ld read as zero.  Each thread issues kStageBatch 16-byte
+// loads before it writes any of them, so a workgroup's staging costs a few
+// memory round trips instead of one per load.
+constexpr int kStageBatch = 16;
+template <int ROWS, typename Put>
+__device__ __forceinline__ void stage_columns(const float* __restrict__ ring, int64_t ld, int slots, int base,
+                                              int ncols, int ntot, int64_t row0, Put put) {
+    constexpr int Q = ROWS / 4;
+    const int total = ntot * Q;
+    for (int t0 = threadIdx.x; t0 < total; t0 += kThreads * kStageBatch) {
+        float4 x[kStageBatch];
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int t = t0 + u * kThreads;
+            const int c = t / Q, q = t % Q;
+            x[u] = float4{0.0f, 0.0f, 0.0f, 0.0f};
+            if (t < total && c < ncols && row0 + 4 * q < ld)
+                x[u] = *reinterpret_cast<const float4*>(ring + (int64_t)((base + c) % slots) * ld + row0 + 4 * q);
+        }
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int t = t0 + u * kThreads;
+            if (t < total) put(t / Q, 4 * (t % Q), x[u]);
+        }
+    }
+}
+
 template <typename TX, typename T>
 hipError_t launch_tiles(const ProjectArgs& a, hipStream_t s, int kc_max) {
     if (kc_max <= 16) return launch_nt<TX, T, 1>(a, s);
@@ -390,17 +420,14 @@ void k_project_block(BlockProjectArgs a) {
     const int64_t row0 = (int64_t)blockIdx.x * kBlkRows;
     const int base = desc->base;  // slot of staged column 0, before the wrap
     const float* ring = static_cast<const float*>(a.ring);
-    for (int t = threadIdx.x; t < ncols_pad * (kBlkRows / 4); t += kThreads) {
-        const int c = t / (kBlkRows / 4), q = t % (kBlkRows / 4);
-        float4 x = float4{0.0f, 0.0f, 0.0f, 0.0f};
-        if (c < ncols) x = *reinterpret_cast<const float4*>(ring + (int64_t)((base + c) % a.slots) * a.ld + row0 + 4 * q);
+    stage_columns<kBlkRows>(ring, a.ld, a.slots, base, ncols, ncols_pad, row0, [&](int c, int r4, float4 x) {
         if constexpr (BF3) {
-            *reinterpret_cast<uint4*>(&U[c * kBlkLDR + 4 * q]) =
+            *reinterpret_cast<uint4*>(&U[c * kBlkLDR + r4]) =
                 uint4{split_word(x.x), split_word(x.y), split_word(x.z), split_word(x.w)};
         } else {
-            *reinterpret_cast<float4*>(&U[c * kBlkLDR + 4 * q]) = x;
+            *reinterpret_cast<float4*>(&U[c * kBlkLDR + r4]) = x;
         }
-    }
+    });
     __syncthreads();
     const unsigned* U32 = reinterpret_cast<const unsigned*>(U);
 
@@ -720,12 +747,8 @@ void k_project_pair(BlockProjectArgs a) {
     const int64_t row0 = (int64_t)blockIdx.x * kBlkRows;
     const int base = desc->base;
     const float* ring = static_cast<const float*>(a.ring);
-    for (int t = threadIdx.x; t < ncols_pad * (kBlkRows / 4); t += kThreads) {
-        const int c = t / (kBlkRows / 4), q = t % (kBlkRows / 4);
-        float4 x = float4{0.0f, 0.0f, 0.0f, 0.0f};
-        if (c < ncols) x = *reinterpret_cast<const float4*>(ring + (int64_t)((base + c) % a.slots) * a.ld + row0 + 4 * q);
-        *reinterpret_cast<float4*>(&U[c * kBlkLDR + 4 * q]) = x;
-    }
+    stage_columns<kBlkRows>(ring, a.ld, a.slots, base, ncols, ncols_pad, row0,
+                            [&](int c, int r4, float4 x) { *reinterpret_cast<float4*>(&U[c * kBlkLDR + r4]) = x; });
     __syncthreads();
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -843,6 +866,423 @@ void k_project_pair(BlockProjectArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP32 block projection as one banded product.  The real output columns of
+// the k windows, 2r per window, side by side form K = 2 r k columns; column
+// g = 2 r w + c (window w, real column c) is the product of stage columns
+// w .. w + m - 1 with C_w[.][c].  So all k windows are one product of the
+// staged columns by a band matrix B[i][g] = C_w[i - w][c] (0 <= i - w < m,
+// zero elsewhere), and a 32-column tile t of B, touching windows
+// w_lo .. w_hi, is nonzero only in rows w_lo .. w_hi + m - 1: it costs
+// ceil((m + w_hi - w_lo) / 2) steps of the 32x32x2 FP32 matrix instruction.
+// With 2r >= 32 a tile touches at most two windows, so the executed work is
+// within one row per tile of the algorithmic work for any r (r = 20, m = 64:
+// 33 or 32 steps a tile; one product per window in 16-column tiles executes
+// 48/40 of it).
+// A workgroup stages 128 rows of the m + k - 1 columns (and a zero column);
+// wavefront v takes tiles v, v + 4, ...: per step one packed B value per
+// lane and four A fragments (one per 32-row tile) from the stage.
+// Fragment layouts of v_mfma_f32_32x32x2f32: A: lane l holds A[l % 32][l / 32];
+// B: lane l holds B[l / 32][l % 32]; D: lane l holds
+// D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32], v = 0..15.
+typedef float v16f __attribute__((ext_vector_type(16)));
+constexpr int kBandRows = 128;
+constexpr int kBandLDR = kBandRows + 32;  // 640-byte column stride: the two half-waves' columns on distinct banks
+
+__host__ __device__ inline int band_tiles(int r, int k) { return (2 * r * k + 31) / 32; }
+// Packed 8-step chunks per tile (the bound on the steps of any tile).
+__host__ __device__ inline int band_chunks(int m, int r) {
+    const int r2 = 2 * r;
+    const int smax = (m + 31 / r2 + 1 + 1) / 2;
+    return (smax + 7) / 8;
+}
+// Staged columns: the m + k - 1 ring columns, one zero column that the last
+// step of an odd-length tile reads, and two more for the one-step read ahead.
+__host__ __device__ inline int band_stage_cols(int m, int k) { return m + k + 2; }
+size_t band_lds(int m, int k) { return sizeof(float) * (size_t)band_stage_cols(m, k) * kBandLDR; }
+// Steps of the longest tile, and the stage of the fixed-step kernel: a tile
+// from window w_lo reads columns up to w_lo + 2 S + 1 (one step read ahead).
+__host__ __device__ inline int band_max_steps(int m, int r, int k) {
+    int smax = 0;
+    const int r2 = 2 * r;
+    for (int t = 0; t < band_tiles(r, k); ++t) {
+        const int wl = 32 * t / r2, wh = min((32 * t + 31) / r2, k - 1);
+        const int s = (m + wh - wl + 1) / 2;
+        smax = s > smax ? s : smax;
+    }
+    return smax;
+}
+__host__ __device__ inline int band_s_stage_cols(int m, int k, int S) {
+    const int need = k + 2 * S + 1;
+    return need > band_stage_cols(m, k) ? need : band_stage_cols(m, k);
+}
+
+// Packs tile t = blockIdx.x, chunk q = blockIdx.y: float ((t nch + q) 64 +
+// lane) 8 + e holds B[w_lo + 2 (8 q + e) + lane / 32][32 t + lane % 32].
+__global__ __launch_bounds__(64)
+void k_pack_band(BlockProjectArgs a) {
+    const int lane = threadIdx.x, t = blockIdx.x, q = blockIdx.y;
+    const int k = a.k, m = a.m, r2 = 2 * a.r;
+    const int nch = band_chunks(m, a.r);
+    if (t == 0 && q == 0) {
+        for (int w = lane; w < k; w += 64) {
+            int kc = 0;
+            window_coef(a, w, kc);
+            a.desc->kc[w] = kc;
+        }
+        if (lane == 0) {
+            a.desc->valid = a.st->count >= a.m + 1 && !a.st->block_rejected;
+            a.desc->base = a.st->oldest + 2 - k + a.slots;
+        }
+    }
+    const int wlo = 32 * t / r2;
+    const int g = 32 * t + (lane & 31);
+    const int w = g / r2, c = g % r2;
+    int kc = 0;
+    const float* B = w < k ? window_coef(a, w, kc) : nullptr;
+    float y[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int i = wlo + 2 * (8 * q + e) + (lane >> 5) - w;  // row of C_w
+        y[e] = (w < k && c < kc && i >= 0 && i < m) ? B[(int64_t)i * r2 + c] : 0.0f;
+    }
+    uint4* out = a.cfrag + ((size_t)(t * nch + q) * 64 + lane) * 2;
+    out[0] = uint4{__builtin_bit_cast(unsigned, y[0]), __builtin_bit_cast(unsigned, y[1]),
+                   __builtin_bit_cast(unsigned, y[2]), __builtin_bit_cast(unsigned, y[3])};
+    out[1] = uint4{__builtin_bit_cast(unsigned, y[4]), __builtin_bit_cast(unsigned, y[5]),
+                   __builtin_bit_cast(unsigned, y[6]), __builtin_bit_cast(unsigned, y[7])};
+}
+
+__global__ __launch_bounds__(kThreads, 2)
+void k_project_band(BlockProjectArgs a) {
+    extern __shared__ float dynp[];
+    const BlockDesc* desc = a.desc;
+    if (!desc->valid) return;
+    const int m = a.m, k = a.k, r2 = 2 * a.r;
+    const int ncols = m + k - 1, nstage = band_stage_cols(m, k);
+    const int ntile = band_tiles(a.r, k), nch = band_chunks(m, a.r);
+    float* U = dynp;
+    const int64_t row0 = (int64_t)blockIdx.x * kBandRows;
+    const int base = desc->base;
+    const float* ring = static_cast<const float*>(a.ring);
+    stage_columns<kBandRows>(ring, a.ld, a.slots, base, ncols, nstage, row0,
+                             [&](int c, int r4, float4 x) { *reinterpret_cast<float4*>(&U[c * kBandLDR + r4]) = x; });
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 31, lh = lane >> 5;
+    const bool odd = li & 1;
+    const uint4* cf = a.cfrag + (size_t)lane * 2;
+    auto load = [&](int t, int q, uint4 (&f)[2]) {
+        const uint4* p = cf + (size_t)(t * nch + q) * 128;
+        f[0] = p[0];
+        f[1] = p[1];
+    };
+    // A fragments of one step: stage column c + lh, rows 32 rt + li
+    auto load_a = [&](int c, float (&av)[4]) {
+        const float* u = U + (c + lh) * kBandLDR + li;
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) av[rt] = u[32 * rt];
+    };
+    auto bval = [](const uint4 (&f)[2], int e) {
+        const uint4& u = e < 4 ? f[0] : f[1];
+        const unsigned bits = (e & 3) == 0 ? u.x : (e & 3) == 1 ? u.y : (e & 3) == 2 ? u.z : u.w;
+        return __builtin_bit_cast(float, bits);
+    };
+    // One step: acc += (A of column c) x b, with the next step's A fragments
+    // (column c + 2) read from the stage before the products are issued, so
+    // that the LDS latency hides behind them.  The stage holds two zero
+    // columns past the last one any tile reads, for the read ahead.
+    auto step = [&](int& c, float (&av)[4], float bv, v16f (&acc)[4]) {
+        float an[4];
+        load_a(c + 2, an);
+        __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the products
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) acc[rt] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rt], bv, acc[rt], 0, 0, 0);
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) av[rt] = an[rt];
+        c += 2;
+    };
+    // Coefficient chunks ping-pong between two register sets (no copies, so
+    // no wait for a chunk before its turn): chunks 0 and 1 of a tile are
+    // loaded before the previous tile's stores, chunk q + 2 into the set
+    // chunk q has just left.
+    uint4 fa[2], fb[2];
+    auto prefetch = [&](int t) {
+        const int g0 = 32 * t;
+        const int wl = g0 / r2, wh = min((g0 + 31) / r2, k - 1);
+        load(t, 0, fa);
+        if ((m + wh - wl + 1) / 2 > 8) load(t, 1, fb);
+    };
+    // steps with the values of chunk set f, then refill it with chunk qn
+    auto chunk8 = [&](int& c, float (&av)[4], uint4 (&f)[2], v16f (&acc)[4], int t, int qn, int nq) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) step(c, av, bval(f, e), acc);
+        if (qn < nq) load(t, qn, f);
+    };
+    auto tail = [&](int& c, float (&av)[4], const uint4 (&f)[2], v16f (&acc)[4], int ntail) {
+        for (int e = 0; e < ntail; ++e) {
+            const float bv = e == 0 ? bval(f, 0) : e == 1 ? bval(f, 1) : e == 2 ? bval(f, 2) :
+                             e == 3 ? bval(f, 3) : e == 4 ? bval(f, 4) : e == 5 ? bval(f, 5) : bval(f, 6);
+            step(c, av, bv, acc);
+        }
+    };
+    if (wave < ntile) prefetch(wave);
+    for (int t = wave; t < ntile; t += kThreads / 64) {
+        // tile quantities as scalars: every branch below is uniform
+        const int g0 = 32 * t;
+        const int wlo = __builtin_amdgcn_readfirstlane(g0 / r2);
+        const int whi = __builtin_amdgcn_readfirstlane(min((g0 + 31) / r2, k - 1));
+        int live = 0;
+        for (int w = wlo; w <= whi; ++w) live |= desc->kc[w];
+        live = __builtin_amdgcn_readfirstlane(live);
+        const int nsteps = (m + whi - wlo + 1) / 2;
+        const int nfull = nsteps >> 3, ntail = nsteps & 7;
+        const int nq = nfull + (ntail ? 1 : 0);
+        v16f acc[4];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[rt][v] = 0.0f;
+        if (live) {
+            int c = wlo;
+            float av[4];
+            load_a(c, av);
+            int q = 0;
+            for (; q + 1 < nfull; q += 2) {
+                chunk8(c, av, fa, acc, t, q + 2, nq);
+                chunk8(c, av, fb, acc, t, q + 3, nq);
+            }
+            if (q < nfull) {  // odd number of whole chunks: the last one is in fa, the tail in fb
+                chunk8(c, av, fa, acc, t, nq, nq);
+                tail(c, av, fb, acc, ntail);
+            } else {
+                tail(c, av, fa, acc, ntail);
+            }
+        }
+        // the next tile's first chunks before this tile's stores
+        if (t + kThreads / 64 < ntile) prefetch(t + kThreads / 64);
+        if (!live) continue;
+        // Lane (li, lh) holds rows 32 rt + 8 gq + 4 lh + v (v = 0..3) of real
+        // column g0 + li; one swap with the neighbouring lane gives the even
+        // lane rows v = 0, 1 and the odd lane rows v = 2, 3 as whole complex
+        // values (2 r is even, so a lane pair never straddles two windows).
+        const int g = g0 + li;
+        const int w = g / r2, c = g % r2;
+        const bool ok = w < k && c < desc->kc[w < k ? w : 0];
+        float2* out = a.out + (int64_t)(w < k ? w : 0) * a.ldw + (int64_t)(c >> 1) * a.ldo;
+        auto store = [&](auto full) {
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                for (int gq = 0; gq < 4; ++gq) {
+                    const float d0 = acc[rt][4 * gq], d1 = acc[rt][4 * gq + 1];
+                    const float d2 = acc[rt][4 * gq + 2], d3 = acc[rt][4 * gq + 3];
+                    const float x = odd ? d0 : d2, y = odd ? d1 : d3;
+                    const float xs = swap_pair(x), ys = swap_pair(y);
+                    const float4 val = odd ? float4{xs, d2, ys, d3} : float4{d0, xs, d1, ys};
+                    const int64_t row = row0 + 32 * rt + 8 * gq + 4 * lh + (odd ? 2 : 0);
+                    float2* o = out + row;
+                    if constexpr (decltype(full)::value) {
+                        if (ok) __builtin_nontemporal_store(v4f{val.x, val.y, val.z, val.w}, reinterpret_cast<v4f*>(o));
+                    } else if (ok && row < a.n) {
+                        o[0] = float2{val.x, val.y};
+                        if (row + 1 < a.n) o[1] = float2{val.z, val.w};
+                    }
+                }
+        };
+        if (a.out16 && row0 + kBandRows <= a.n) store(std::true_type{});
+        else store(std::false_type{});
+    }
+}
+
+// The banded product with a fixed number S of steps per tile (S = the longest
+// tile's steps rounded up to an instance, at most 36: m up to about 70).
+// Every tile runs the same straight-line sequence of products (a shorter
+// tile meets zero coefficients in its last steps), and a tile's S values per
+// lane are held in registers, loaded one tile ahead (two register sets in
+// turn, the tile loop unrolled by two, the first tile peeled), so no load or
+// branch sits between the products.  Output in runs of 128 bytes per complex
+// column: the two 8-row groups gq = 2p, 2p + 1 are exchanged between 16-lane
+// rows (v_permlane16_swap: odd rows of the first operand with even rows of
+// the second), so that one store writes rows 16 p .. 16 p + 15 of eight
+// complex columns, whole 128-byte lines, instead of 8 rows of sixteen.  The
+// waits for the loads ahead can only be counted exactly when no branch
+// skips a vector memory instruction: hence the fixed step count, every tile
+// computed, stores that always issue (masked lanes write a sink) and the
+// window ranks read from LDS.
+__device__ __forceinline__ float4 band_pair(const v16f& d, int gq, bool odd) {
+    // lane (li, lh): rows 8 gq + 4 lh + v of real column li; after one swap
+    // with the neighbouring lane, two whole complex rows (v = 0, 1 on the
+    // even lane, v = 2, 3 on the odd one)
+    const float d0 = d[4 * gq], d1 = d[4 * gq + 1], d2 = d[4 * gq + 2], d3 = d[4 * gq + 3];
+    const float x = odd ? d0 : d2, y = odd ? d1 : d3;
+    const float xs = swap_pair(x), ys = swap_pair(y);
+    return odd ? float4{xs, d2, ys, d3} : float4{d0, xs, d1, ys};
+}
+__device__ __forceinline__ void swap16(float& x, float& y) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, x), __builtin_bit_cast(unsigned, y),
+                                                   false, false);
+    x = __builtin_bit_cast(float, (unsigned)r[0]);
+    y = __builtin_bit_cast(float, (unsigned)r[1]);
+}
+
+// FULL: every row slab of the launch is whole and the output allows 16-byte
+// stores (one store instruction per row pair and column group, whatever the
+// data: the waits for the loads ahead are then counted exactly); the last,
+// partial slab runs as a launch of its own with FULL = false.
+template <int S, bool FULL>
+__global__ __launch_bounds__(kThreads, 2)
+void k_project_band_s(BlockProjectArgs a, int64_t slab0) {
+    constexpr int NQ = (S + 3) / 4;  // 16-byte coefficient loads per lane and tile
+    extern __shared__ float dynp[];
+    const BlockDesc* desc = a.desc;
+    if (!desc->valid) return;
+    const int m = a.m, k = a.k, r2 = 2 * a.r;
+    const int ncols = m + k - 1, nstage = band_s_stage_cols(m, k, S);
+    const int nch = band_chunks(m, a.r);
+    const int ntile = band_tiles(a.r, k);
+    float* U = dynp;
+    const int64_t row0 = (slab0 + blockIdx.x) * kBandRows;
+    const int base = desc->base;
+    const float* ring = static_cast<const float*>(a.ring);
+    // the windows' ranks in LDS: reading them never waits on vector memory
+    __shared__ int s_kc[64];
+    if (threadIdx.x < 64) s_kc[threadIdx.x] = threadIdx.x < k ? desc->kc[threadIdx.x] : 0;
+    stage_columns<kBandRows>(ring, a.ld, a.slots, base, ncols, nstage, row0,
+                             [&](int c, int r4, float4 x) { *reinterpret_cast<float4*>(&U[c * kBandLDR + r4]) = x; });
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 31, lh = lane >> 5;
+    const bool odd = li & 1;
+    const uint4* cf = a.cfrag + (size_t)lane * 2;
+    auto load_a = [&](int c, float (&av)[4]) {
+        const float* u = U + (c + lh) * kBandLDR + li;
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) av[rt] = u[32 * rt];
+    };
+    auto bval = [](const uint4 (&b)[NQ], int st) {
+        const uint4& u = b[st / 4];
+        const unsigned bits = (st & 3) == 0 ? u.x : (st & 3) == 1 ? u.y : (st & 3) == 2 ? u.z : u.w;
+        return __builtin_bit_cast(float, bits);
+    };
+    struct Tile {
+        int g0, wlo, nsteps;
+    };
+    auto tile_of = [&](int t) {
+        Tile T;
+        T.g0 = 32 * t;
+        T.wlo = __builtin_amdgcn_readfirstlane(T.g0 / r2);
+        const int whi = __builtin_amdgcn_readfirstlane(min((T.g0 + 31) / r2, k - 1));
+        T.nsteps = S;
+        (void)whi;
+        return T;
+    };
+    // the tile's S steps of values, four per 16-byte load (chunk q of the
+    // packed layout holds steps 8 q .. 8 q + 7 as two such loads); steps
+    // past a tile's own count hold zeros
+    auto load_b = [&](int t, uint4 (&b)[NQ]) {
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) b[i] = cf[(size_t)(t * nch + i / 2) * 128 + (i & 1)];
+    };
+    auto step = [&](int& c, float (&av)[4], float bv, v16f (&acc)[4]) {
+        float an[4];
+        load_a(c + 2, an);  // the next step's A fragments ahead of the products
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) acc[rt] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rt], bv, acc[rt], 0, 0, 0);
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) av[rt] = an[rt];
+        c += 2;
+    };
+    // Every tile is computed (a tile of unsolved windows has zero
+    // coefficients and stores nothing), so that no branch skips vector
+    // memory instructions and the waits for the loads ahead stay exact.
+    auto tile = [&](int t, const uint4 (&b)[NQ]) {
+        const Tile T = tile_of(t);
+        v16f acc[4];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[rt][v] = 0.0f;
+        int c = T.wlo;
+        float av[4];
+        load_a(c, av);
+        // every tile takes S steps (straight-line code, no branch between the
+        // products): a tile with fewer meets zero coefficients in the rest
+#pragma unroll
+        for (int st = 0; st < S; ++st) step(c, av, bval(b, st), acc);
+        // the two complex columns of this lane's stores: jA = (lane % 16) / 2
+        // and jA + 8 of the tile (real columns g0 + 2 j, g0 + 2 j + 1)
+        const int jA = (lane & 15) >> 1;
+        float2* o[2];
+        bool ok[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int g = T.g0 + 2 * (jA + 8 * h);
+            const int w = g / r2, cc = g % r2;
+            const int ws = w < k ? w : 0;
+            ok[h] = w < k && cc < s_kc[ws];
+            o[h] = a.out + (int64_t)ws * a.ldw + (int64_t)(cc >> 1) * a.ldo;
+        }
+        const int rsub = 8 * ((lane >> 4) & 1) + 4 * lh + (odd ? 2 : 0);
+        v4f* sink = reinterpret_cast<v4f*>(a.desc->sink) + lane;
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                float4 x = band_pair(acc[rt], 2 * p, odd), y = band_pair(acc[rt], 2 * p + 1, odd);
+                swap16(x.x, y.x);
+                swap16(x.y, y.y);
+                swap16(x.z, y.z);
+                swap16(x.w, y.w);
+                const int64_t row = row0 + 32 * rt + 16 * p + rsub;
+                const float4 val[2] = {x, y};
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    float2* q = o[h] + row;
+                    if constexpr (FULL) {
+                        // unconditional: lanes whose column is past the
+                        // window's rank (or past the last window) write the
+                        // descriptor's sink, so no branch skips a store
+                        v4f* dst = ok[h] ? reinterpret_cast<v4f*>(q) : sink;
+                        __builtin_nontemporal_store(v4f{val[h].x, val[h].y, val[h].z, val[h].w}, dst);
+                    } else if (ok[h] && row < a.n) {
+                        q[0] = float2{val[h].x, val[h].y};
+                        if (row + 1 < a.n) q[1] = float2{val[h].z, val[h].w};
+                    }
+                }
+            }
+    };
+    constexpr int T4 = kThreads / 64;
+    uint4 bA[NQ], bB[NQ];
+    // the next tile's values (the last tile's again past the end: loads are
+    // never skipped)
+    auto ahead = [&](int t) { return t + T4 < ntile ? t + T4 : ntile - 1; };
+    int t = wave;
+    if (t >= ntile) return;
+    load_b(t, bA);
+    // (the scheduling barriers keep the loads ahead where they are issued;
+    // the first tile is peeled so that every tile in the loop follows the
+    // same pattern of stores and loads, and its waits are counted exactly)
+    load_b(ahead(t), bB);
+    __builtin_amdgcn_sched_barrier(0);
+    tile(t, bA);
+    t += T4;
+    while (t < ntile) {
+        load_b(ahead(t), bA);
+        __builtin_amdgcn_sched_barrier(0);
+        tile(t, bB);
+        t += T4;
+        if (t >= ntile) break;
+        load_b(ahead(t), bB);
+        __builtin_amdgcn_sched_barrier(0);
+        tile(t, bA);
+        t += T4;
+    }
+}
+
 size_t block_lds(int m, int k) { return sizeof(float) * (size_t)(k - 1 + 32 * ((m + 31) / 32)) * kBlkLDR; }
 
 template <int NT>
@@ -861,16 +1301,122 @@ hipError_t launch_block_nt(const BlockProjectArgs& a, hipStream_t s) {
 
 }  // namespace
 
-size_t project_block_frag_bytes(int m, int kmax) {
+size_t project_block_frag_bytes(int m, int r, int kmax) {
     const PairShape ps = pair_shape(m);
     const size_t per_window = (size_t)kmax * ((m + 31) / 32) * 4 * 64 * 32;
     const size_t pairs =
         (size_t)((kmax + 1) / 2) * (8 * ps.nfull + ps.tail) * kPairMaxTilesTuned * 64 * sizeof(float);
-    return per_window > pairs ? per_window : pairs;
+    const size_t band = (size_t)band_tiles(r, kmax) * band_chunks(m, r) * 64 * 32;
+    size_t b = per_window > pairs ? per_window : pairs;
+    return b > band ? b : band;
 }
 
 bool project_block_fits(int m, int k, int r) {
     return 2 * r <= 64 && k <= 64 && block_lds(m, k) <= kBlockLdsMax && pair_lds(m, k) <= kBlockLdsMax;
+}
+
+bool pairs_apply(int m, int r, int k) {
+    BlockProjectArgs a{};
+    a.m = m;
+    a.r = r;
+    a.k = k;
+    a.form = 2;
+    return use_pairs(a);
+}
+bool band_applies(int m, int r, int k) { return r >= 1 && band_lds(m, k) <= kBlockLdsMax; }
+
+
+// Fixed-step instances of the banded kernel: S steps per tile.
+constexpr int kBandSteps[] = {9, 13, 17, 21, 25, 29, 33, 36};
+// The instance for these sizes (the longest tile's steps rounded up by at most
+// 3), or 0 if none applies (the chunk-loop kernel then runs).
+int band_fixed_steps(int m, int r, int k) {
+    const int smax = band_max_steps(m, r, k);
+    for (int S : kBandSteps)
+        if (smax <= S && S - smax <= 3 && (S + 7) / 8 <= band_chunks(m, r) &&
+            sizeof(float) * (size_t)band_s_stage_cols(m, k, S) * kBandLDR <= kBlockLdsMax)
+            return S;
+    return 0;
+}
+
+// The banded form: FP32 products, and its stage fits; asked for (form 3, by
+// the tuned shape of the stream), or by the rule (form 0) where a fixed-step
+// instance applies: at the full-HD workload (m = 64, r = 20, k = 32) the step
+// with it takes 4.17 ms against 4.68 with one product per window (the
+// chunk-loop kernel, for other sizes, is slower than one product per window).
+bool use_band(const BlockProjectArgs& a) {
+    if (a.bf16x3 || a.form == 1 || a.form == 2) return false;
+    if (band_lds(a.m, a.k) > kBlockLdsMax) return false;
+    return a.form == 3 || band_fixed_steps(a.m, a.r, a.k) > 0;
+}
+
+int block_rule_form(int m, int r, int k) {
+    BlockProjectArgs a{};
+    a.m = m;
+    a.r = r;
+    a.k = k;
+    return use_band(a) ? 3 : use_pairs(a) ? 2 : 1;
+}
+
+hipError_t launch_band(const BlockProjectArgs& a, hipStream_t s, bool pack) {
+    if (!a.cfrag || !a.desc) return hipErrorInvalidValue;
+    const int ntile = band_tiles(a.r, a.k);
+    if (pack) {
+        hipLaunchKernelGGL(k_pack_band, dim3((unsigned)ntile, (unsigned)band_chunks(a.m, a.r)), dim3(64), 0, s, a);
+        return hipGetLastError();
+    }
+    size_t lds = band_lds(a.m, a.k);
+    if (lds > kBlockLdsMax) return hipErrorInvalidValue;
+    // fixed-step kernels for the longest tile's step count rounded up to the
+    // next instance (at most 3 steps of zeros per tile), else the chunk loop
+    // fixed-step kernels for the longest tile's step count rounded up to the
+    // next instance (at most 3 steps of zeros per tile), else the chunk loop
+    const void* full = nullptr;
+    const void* part = nullptr;
+    const int Sfix = band_fixed_steps(a.m, a.r, a.k);
+    auto pick = [&](int S, const void* f_full, const void* f_part) {
+        if (S == Sfix) {
+            full = f_full;
+            part = f_part;
+            lds = sizeof(float) * (size_t)band_s_stage_cols(a.m, a.k, S) * kBandLDR;
+        }
+    };
+#define DMD_BAND_S(S) \
+    pick(S, reinterpret_cast<const void*>(k_project_band_s<S, true>), \
+         reinterpret_cast<const void*>(k_project_band_s<S, false>))
+    DMD_BAND_S(9);
+    DMD_BAND_S(13);
+    DMD_BAND_S(17);
+    DMD_BAND_S(21);
+    DMD_BAND_S(25);
+    DMD_BAND_S(29);
+    DMD_BAND_S(33);
+    DMD_BAND_S(36);
+#undef DMD_BAND_S
+    const int64_t nslab = (a.n + kBandRows - 1) / kBandRows;
+    if (!full) {
+        const void* kern = reinterpret_cast<const void*>(k_project_band);
+        hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_project_band, dim3((unsigned)nslab), dim3(kThreads), lds, s, a);
+        return hipGetLastError();
+    }
+    // whole slabs with 16-byte stores in one launch, the rest (or all of it,
+    // where the output does not allow 16-byte stores) in another
+    const int64_t nfull = a.out16 ? a.n / kBandRows : 0;
+    int64_t slab0 = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        const void* kern = pass == 0 ? full : part;
+        const int64_t cnt = pass == 0 ? nfull : nslab - nfull;
+        if (cnt <= 0) continue;
+        hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        void* args[] = {const_cast<BlockProjectArgs*>(&a), &slab0};
+        e = hipLaunchKernel(kern, dim3((unsigned)cnt), dim3(kThreads), args, lds, s);
+        if (e != hipSuccess) return e;
+        slab0 += cnt;
+    }
+    return hipSuccess;
 }
 
 template <int NT>
@@ -911,6 +1457,7 @@ hipError_t launch_pair(const BlockProjectArgs& a, hipStream_t s, bool pack) {
 hipError_t launch_pack_block(const BlockProjectArgs& a, hipStream_t s) {
     const int kc_max = 2 * a.r;
     if (kc_max > 64 || a.k < 1 || a.k > a.kmax) return hipErrorInvalidValue;
+    if (use_band(a)) return launch_band(a, s, true);
     if (use_pairs(a)) return launch_pair(a, s, true);
     if (kc_max <= 16) return launch_pack_nt<1>(a, s);
     if (kc_max <= 32) return launch_pack_nt<2>(a, s);
@@ -921,6 +1468,7 @@ hipError_t launch_pack_block(const BlockProjectArgs& a, hipStream_t s) {
 hipError_t launch_project_block(const BlockProjectArgs& a, hipStream_t s) {
     const int kc_max = 2 * a.r;
     if (kc_max > 64 || a.k < 1 || a.k > a.kmax || a.ld % kBlkRows) return hipErrorInvalidValue;
+    if (use_band(a)) return launch_band(a, s, false);
     if (use_pairs(a)) return launch_pair(a, s, false);
     if (kc_max <= 16) return launch_block_nt<1>(a, s);
     if (kc_max <= 32) return launch_block_nt<2>(a, s);

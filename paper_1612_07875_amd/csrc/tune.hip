@@ -65,7 +65,7 @@ int load_file_locked(const char* path, bool strict) {
                               &e.val.gram_us, &e.val.step_us);
         const bool ok = nf == 10 && (e.val.gram_iter == 0 || e.val.gram_iter == 1 || e.val.gram_iter == 2 ||
                                      e.val.gram_iter == 4) &&
-                        e.val.proj_form >= 0 && e.val.proj_form <= 2;
+                        e.val.proj_form >= 0 && e.val.proj_form <= 3;
         if (!ok) {
             fclose(f);
             return strict ? api_fail(DMD_E_INVAL, "%s:%d: not a tuning entry", path, lineno) : DMD_OK;
@@ -191,8 +191,13 @@ int tune_block_form(int64_t n, int32_t m, int32_t r, const dmd_opts_t& o, int gr
     } s2g{s2};
     for (int t = 0; t < m + 1; t += kb)
         if (int rc = dmd_stream_push_block(sh.h, X.p, ld, kb, s)) return rc;
-    const int forms[2] = {1, 2};
-    double times[2] = {0, 0};
+    // one product per window, window pairs (where 2r = 8 mod 16 allows them)
+    // and the banded product (where its stage fits)
+    int forms[3], nf = 0;
+    forms[nf++] = 1;
+    if (pairs_apply(m, r, kb)) forms[nf++] = 2;
+    if (band_applies(m, r, kb)) forms[nf++] = 3;
+    double times[3] = {0, 0, 0};
     Events ev;
     hipEvent_t join = nullptr;
     if (hipEventCreate(&ev.a) != hipSuccess || hipEventCreate(&ev.b) != hipSuccess ||
@@ -203,7 +208,7 @@ int tune_block_form(int64_t n, int32_t m, int32_t r, const dmd_opts_t& o, int gr
         ~J() { (void)hipEventDestroy(e); }
     } jg{join};
     constexpr int kWarm = 2, kReps = 4;
-    for (int c = 0; c < 2; ++c) {
+    for (int c = 0; c < nf; ++c) {
         stream_set_shapes(sh.h, gram_iter, forms[c]);
         auto step = [&]() -> int {
             if (int rc = dmd_stream_push_block(sh.h, X.p, ld, kb, s)) return rc;
@@ -223,8 +228,13 @@ int tune_block_form(int64_t n, int32_t m, int32_t r, const dmd_opts_t& o, int gr
         if (hipEventElapsedTime(&ms, ev.a, ev.b) != hipSuccess) return api_fail(DMD_E_DEVICE, "hipEventElapsedTime");
         times[c] = 1000.0 * ms / kReps;
     }
-    // the built-in rule (per window at r = 20) unless pairs are more than 2 % faster
-    const int bi = times[1] < 0.98 * times[0] ? 1 : 0;
+    // the built-in rule's form unless another is more than 2 % faster
+    const int rule = block_rule_form(m, r, kb);
+    int bi = 0;
+    for (int c = 0; c < nf; ++c)
+        if (forms[c] == rule) bi = c;
+    for (int c = 0; c < nf; ++c)
+        if (times[c] < 0.98 * times[bi]) bi = c;
     *best_form = forms[bi];
     *best_us = times[bi];
     if (hipStreamSynchronize(s2) != hipSuccess) return api_fail(DMD_E_DEVICE, "sync");
@@ -284,11 +294,10 @@ DMD_API int dmd_tune(int64_t n, int32_t m, int32_t r, const dmd_opts_t* opts, dm
     dmd::TuneVal v{};
     if (int rc = dmd::tune_gram(n, m, r, o, s, &v.gram_iter, &v.gram_us)) return rc;
     // the block projection form, where there is a choice: FP32 block streams
-    // whose 2r = 8 (mod 16) lets two windows share whole column tiles
-    const bool pairs_possible = o.max_block > 1 && o.dtype == DMD_F32 && o.precision != DMD_PREC_BF16X3 &&
-                                o.precision != DMD_PREC_FP64 && (2 * r) % 16 == 8 && 4 * r / 16 <= 5 &&
-                                (m + 4) / 4 >= 8 && ((m + 4) / 4) % 8 <= 1 && dmd::project_block_fits(m, o.max_block, r);
-    if (pairs_possible) {
+    // (FP32 data, FP32 products) with more than one form that applies
+    const bool fp32_block = o.max_block > 1 && o.dtype == DMD_F32 && o.precision != DMD_PREC_BF16X3 &&
+                            o.precision != DMD_PREC_FP64 && dmd::project_block_fits(m, o.max_block, r);
+    if (fp32_block && (dmd::pairs_apply(m, r, o.max_block) || dmd::band_applies(m, r, o.max_block))) {
         if (int rc = dmd::tune_block_form(n, m, r, o, v.gram_iter, s, &v.proj_form, &v.step_us)) return rc;
     }
     {

@@ -262,27 +262,53 @@ def test_block_modes_large_windows(m, r, kb):
             check_phi(phis[w].T, ref, perm, lam.size, 2e-4)
 
 
+@pytest.fixture
+def projection_form(request, tmp_path):
+    """Streams created in the test use block projection form `param` (0: the
+    built-in rule, else named by a tuning-table entry for the test's shape)."""
+    dmd = _dmd()
+    dmd.tune_clear()
+
+    def use(n, m, r, kb):
+        form = request.param
+        if form:
+            f = tmp_path / "form.txt"
+            f.write_text(f"0 0 {round(8 * np.log2(n))} {m} {r} {kb} 1 {form} 0 0\n")
+            dmd.tune_load(str(f))
+        return form
+    yield use
+    dmd.tune_clear()
+
+
+@pytest.mark.parametrize("projection_form", [0, 2, 3], indirect=True)
 @pytest.mark.parametrize("H,W,m,r", [(97, 134, 32, 12), (100, 200, 64, 12), (50, 100, 31, 4)])
-def test_block_fp32_window_pairs(H, W, m, r):
-    """FP32 ranks r = 4, 12 (2r = 8 mod 16) project two windows per product.  Odd
-    blocks end with a window of its own, and the block in which the window
-    fills pairs unsolved windows with solved ones: every window against the
-    oracle, unsolved windows and columns past r_eff left untouched."""
+def test_block_fp32_window_pairs(H, W, m, r, projection_form):
+    """FP32 ranks r = 4, 12 (2r = 8 mod 16): two windows per product (form 2),
+    or one banded product in which a 32-column tile spans up to five windows
+    (form 3, and the rule).  Odd blocks end with a window of its own, and the
+    block in which the window fills pairs unsolved windows with solved ones:
+    every window against the oracle, unsolved windows and columns past r_eff
+    left untouched."""
     dmd = _dmd()
     n = H * W
+    form = projection_form(n, m, r, 16)
     blocks = [16, 16, 7, 16, 1, 11, 16, 5]
     frames = gen.BlobVideo(height=H, width=W, blob_sigma=4.0).frames(0, sum(blocks))
     X = torch.from_numpy(frames.T.copy()).cuda()
     with dmd.Stream(n, m, r, max_block=16) as s:
+        assert s.info().proj_form == form
         run_blocks(s, X, frames, blocks, m, r, phi_tol=2e-4)
 
 
-def test_block_fp32_pairs_rank_deficient():
+@pytest.mark.parametrize("projection_form", [0, 2], indirect=True)
+def test_block_fp32_pairs_rank_deficient(projection_form):
     """Noiseless modal data has rank 10; with r = 12 every window uses
-    r_eff = 10 (both windows of a pair): modes 0..9 against the oracle of
-    the same rank, modes 10, 11 left untouched."""
+    r_eff = 10 (both windows of a pair, or every window of a banded tile):
+    modes 0..9 against the oracle of the same rank, modes 10, 11 left
+    untouched."""
     dmd = _dmd()
     n, m, r, kb = 6000, 32, 12, 7
+    projection_form(n, m, r, kb)
     g = gen.ModalStream(n=n, noise=0.0)
     T = m + 1 + 3 * kb
     frames = g.frames(0, T).astype(np.float32)
