@@ -30,7 +30,9 @@ Every window update runs the whole hot path through the C ABI:
   complex64 coefficients at 1 % (2,621 per frame, lowest wavenumbers, 5 %
   redrawn per frame), m = 128, r = 24; one step = one sparse push + solves +
   modes.  A second leg pushes 512 x 512 spatial frames through the device
-  Fourier ingest (same support size) and is reported under "fourier_ingest".
+  Fourier ingest (same support size) and is reported under "fourier_ingest";
+  a third advances --sparse-streams such streams by one batch tick per step
+  and is reported under "batched".
 
 Prints one JSON line (see the repository's benchmark contract).
 """
@@ -70,6 +72,8 @@ def parse():
     ap.add_argument("--latency-frames", type=int, default=400, help="single-frame pushes timed one by one")
     ap.add_argument("--latency-blocks", type=int, default=20, help="block mode: blocks timed one by one")
     ap.add_argument("--cpu-windows", type=int, default=4, help="windows in the oracle's timed sample")
+    ap.add_argument("--sparse-streams", type=int, default=16,
+                    help="sparse mode: streams in the batched leg (0: no batched leg)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-split", action="store_true",
                     help="block mode, FP32: skip the comparison run with split-BF16 projections")
@@ -790,9 +794,42 @@ def bench_sparse(args):
         s.close()
         return el, kern, int(lam.size)
 
+    def batched_leg(B):
+        # B streams of the same shape, stream b fed the frames from b on (distinct
+        # windows); one step = one tick that pushes a frame into every stream
+        # and writes every stream's modes
+        streams = [dmd.Stream(n, m, r, dtype="c64_csr", max_nnz=nnz) for _ in range(B)]
+        outs = [torch.zeros((r, n), dtype=torch.complex64, device="cuda").T for _ in range(B)]
+        with dmd.Batch(max_streams=B) as batch:
+            for st in streams:
+                batch.attach(st)
+
+            def tick(t):
+                batch.tick_frames(streams, [(idx[(t + b) % T], val[(t + b) % T]) for b in range(B)], modes=outs)
+
+            for t in range(m + 1 + Wu):
+                tick(t)
+            torch.cuda.synchronize()
+            dmd.profile_enable(True)
+            dmd.profile_reset()
+            t1 = time.perf_counter()
+            for t in range(m + 1 + Wu, T):
+                tick(t)
+            torch.cuda.synchronize()
+            el_b = time.perf_counter() - t1
+            dmd.profile_enable(False)
+            kern_b = kernel_table(dmd, ("batch_gram", "batch_solve", "batch_project"))
+            dmd.profile_reset()
+        r_effs = [int(st.eigs()[0].size) for st in streams]
+        for st in streams:
+            st.close()
+        return el_b, kern_b, r_effs
+
     names = ("csr_gram", "solve_sym", "solve_eig", "csr_project")
     el, kern, r_eff = leg("csr", names)
     el_f, kern_f, r_eff_f = leg("fourier", ("fourier",) + names)
+    B = args.sparse_streams
+    el_b, kern_b, r_effs_b = batched_leg(B) if B > 0 else (None, None, None)
     # the sparse Gram pass reads the window's coefficients once: (m+1) nnz (4 + 8) bytes
     roofline = roofline_of(kern, {"csr_gram": (m + 1) * nnz * 12}, {"csr_gram": "csr.hip"})
     out = result_line(K / el, K, Wu, el, "c64", {
@@ -809,6 +846,13 @@ def bench_sparse(args):
                                    "workload": "512 x 512 FP32 spatial frames (blob video) -> unitary 2-D DFT at "
                                                "the 2,621 lowest-|k| bins on the device -> the same sparse path",
                                    "kernels": kern_f}})
+    if B > 0:
+        out["batched"] = {
+            "value": round(B * K / el_b, 2), "unit": "window updates/s", "streams": B,
+            "ms_per_tick": round(1000.0 * el_b / K, 4), "r_eff": sorted(set(r_effs_b)),
+            "workload": f"{B} sparse streams of the same shape, one dmd_batch_tick_frames per step (a frame "
+                        "into every stream, grouped Hermitian solves, every stream's modes)",
+            "kernels": kern_b}
     return out, None
 
 

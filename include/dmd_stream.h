@@ -537,20 +537,47 @@ int dmd_batch_create(const dmd_batch_opts_t* opts, dmd_batch_t** out);
 int dmd_batch_destroy(dmd_batch_t* b);
 
 /* Admit a stream (DMD_E_NOMEM over budget, DMD_E_INVAL if already attached or
- * full, DMD_E_UNSUPPORTED unless dense FP32 with auto_solve on the batch's
- * device).  Detach returns its footprint to the budget. */
+ * full, DMD_E_UNSUPPORTED unless it solves every push (auto_solve) on the
+ * batch's device; a sparse stream must use the tridiagonal solver, i.e. no
+ * warm start).  Dense FP32 streams with FP32 or split-BF16 projections share
+ * grouped Gram and projection launches; FP64 streams (FP64 data or FP64
+ * projections) and sparse streams run their own Gram (or sparse ingest) and
+ * projection kernels inside the tick; every member's small solves are
+ * grouped.  Detach returns its footprint to the budget. */
 int dmd_batch_attach(dmd_batch_t* b, dmd_stream_t* h);
 int dmd_batch_detach(dmd_batch_t* b, dmd_stream_t* h);
 
-/* One tick on `stream`: push snapshots[i] (n_i FP32 values, device) into
- * streams[i] for i < count (attached, pairwise distinct), run every small
- * solve and, where modes != NULL and modes[i] != NULL, write that stream's
- * Phi into modes[i] (complex64, leading dimension ld_modes[i] >= n_i).
- * Equivalent to dmd_stream_push + dmd_stream_modes per stream; asynchronous.
- * Each member's later calls are ordered after the tick. */
+/* One tick on `stream`: push snapshots[i] (n_i values of the stream's dtype,
+ * FP32 or FP64, device) into streams[i] for i < count (attached, pairwise
+ * distinct, dense), run every small solve and, where modes != NULL and
+ * modes[i] != NULL, write that stream's Phi into modes[i] (complex64, or
+ * complex128 for FP64 projections; leading dimension ld_modes[i] >= n_i).
+ * Equivalent to dmd_stream_push + dmd_stream_modes per stream, with the same
+ * results bit for bit; asynchronous.  Each member's later calls are ordered
+ * after the tick.  Sparse members need dmd_batch_tick_frames (DMD_E_INVAL). */
 int dmd_batch_tick(dmd_batch_t* b, int32_t count, dmd_stream_t* const* streams,
                    const void* const* snapshots, void* const* modes,
                    const int64_t* ld_modes, void* stream);
+
+/* One member's frame of a tick: for a dense stream x (n values of its dtype,
+ * device; nnz, idx, val unused); for a sparse stream a snapshot as for
+ * dmd_stream_push_csr (nnz in [0, max_nnz], idx and val on the device, idx
+ * sorted, unique and in [0, n): a snapshot that breaks this is rejected by
+ * the device as in dmd_stream_push_csr). */
+typedef struct {
+    const void* x;
+    int32_t nnz;
+    const int32_t* idx;
+    const void* val;
+} dmd_frame_t;
+
+/* dmd_batch_tick for any mix of members, dense and sparse (Sec. 3.5), one
+ * frame each; the same ordering, outputs and errors.  A tick with FP64 or
+ * sparse members runs eagerly even when the batch replays ticks as graphs
+ * (their frames reach their kernels as launch arguments). */
+int dmd_batch_tick_frames(dmd_batch_t* b, int32_t count, dmd_stream_t* const* streams,
+                          const dmd_frame_t* frames, void* const* modes, const int64_t* ld_modes,
+                          void* stream);
 
 /* Attached streams, their total device footprint and the budget. */
 int dmd_batch_info(dmd_batch_t* b, int32_t* nstreams, int64_t* used_bytes,

@@ -58,6 +58,11 @@ class Info(ctypes.Structure):
     ]
 
 
+class Frame(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("nnz", ctypes.c_int32), ("idx", ctypes.c_void_p),
+                ("val", ctypes.c_void_p)]
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("gram_iter", ctypes.c_int32), ("proj_form", ctypes.c_int32), ("gram_us", ctypes.c_double),
                 ("step_us", ctypes.c_double), ("reserved", ctypes.c_int32 * 4)]
@@ -114,6 +119,8 @@ SIGNATURES = {
     "dmd_batch_detach": [_P, _P],
     "dmd_batch_tick": [_P, _I32, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                        ctypes.POINTER(_I64), _P],
+    "dmd_batch_tick_frames": [_P, _I32, ctypes.POINTER(_P), ctypes.POINTER(Frame), ctypes.POINTER(_P),
+                              ctypes.POINTER(_I64), _P],
     "dmd_batch_info": [_P, _I32P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)],
     "dmd_profile_enable": [ctypes.c_int],
     "dmd_profile_reset": [],
@@ -571,19 +578,47 @@ class Batch:
         check(load().dmd_batch_info(self._h, ctypes.byref(n), ctypes.byref(used), ctypes.byref(bud)))
         return n.value, used.value, bud.value
 
+    def _modes(self, streams, modes):
+        k = len(streams)
+        if modes is None:
+            return None, None
+        ms = (_P * k)(*[(o.data_ptr() if o is not None else None) for o in modes])
+        lds = (_I64 * k)(*[(o.stride(1) if o is not None else 0) for o in modes])
+        for s, o in zip(streams, modes):
+            if o is not None:
+                s._check_out(o, s.mode_dtype)
+        return ms, lds
+
     def tick(self, streams, snapshots, modes=None, stream=None):
+        """One tick of dense members: snapshots[i] is a contiguous CUDA tensor
+        of streams[i].n values of the stream's dtype."""
         k = len(streams)
         hs = (_P * k)(*[s._h for s in streams])
         for s, x in zip(streams, snapshots):
-            if not (x.is_cuda and x.dtype == torch.float32 and x.numel() == s.n and x.is_contiguous()):
-                raise ValueError("snapshots must be contiguous float32 CUDA tensors of n elements")
+            if not (x.is_cuda and x.dtype == s.elem and x.numel() == s.n and x.is_contiguous()):
+                raise ValueError("snapshots must be contiguous CUDA tensors of n values of the stream's dtype")
         xs = (_P * k)(*[x.data_ptr() for x in snapshots])
-        if modes is not None:
-            ms = (_P * k)(*[(o.data_ptr() if o is not None else None) for o in modes])
-            lds = (_I64 * k)(*[(o.stride(1) if o is not None else 0) for o in modes])
-            for s, o in zip(streams, modes):
-                if o is not None:
-                    s._check_out(o, s.mode_dtype)
-        else:
-            ms, lds = None, None
+        ms, lds = self._modes(streams, modes)
         return check(load().dmd_batch_tick(self._h, k, hs, xs, ms, lds, _stream_ptr(stream)))
+
+    def tick_frames(self, streams, frames, modes=None, stream=None):
+        """One tick of any members: frames[i] is a dense snapshot tensor, or for
+        a sparse stream an (idx, val) pair of CUDA tensors (int32, complex64)."""
+        k = len(streams)
+        hs = (_P * k)(*[s._h for s in streams])
+        fr = (Frame * k)()
+        for i, (s, f) in enumerate(zip(streams, frames)):
+            if s.elem == torch.complex64:
+                idx, val = f
+                if not (idx.is_cuda and val.is_cuda and idx.dtype == torch.int32 and val.dtype == torch.complex64
+                        and idx.numel() == val.numel() and idx.is_contiguous() and val.is_contiguous()):
+                    raise ValueError("a sparse frame is (idx int32, val complex64) contiguous CUDA tensors")
+                fr[i].nnz = idx.numel()
+                fr[i].idx = idx.data_ptr() if idx.numel() else None
+                fr[i].val = val.data_ptr() if val.numel() else None
+            else:
+                if not (f.is_cuda and f.dtype == s.elem and f.numel() == s.n and f.is_contiguous()):
+                    raise ValueError("a dense frame is a contiguous CUDA tensor of n values of the stream's dtype")
+                fr[i].x = f.data_ptr()
+        ms, lds = self._modes(streams, modes)
+        return check(load().dmd_batch_tick_frames(self._h, k, hs, fr, ms, lds, _stream_ptr(stream)))

@@ -167,6 +167,9 @@ hipError_t launch_jacobi_grouped(const SolveArgs* items_lds, int n_lds, const So
                                  hipStream_t s);
 hipError_t launch_trid_grouped(const SolveArgs* items_lds, int n_lds, const SolveArgs* items_glb, int n_glb,
                                hipStream_t s);
+// Grouped Hermitian (complex) tridiagonal solves: items_lds m <= 32, items_glb m > 32.
+hipError_t launch_trid_grouped_cplx(const SolveArgs* items_lds, int n_lds, const SolveArgs* items_glb, int n_glb,
+                                    hipStream_t s);
 hipError_t launch_eig_grouped(const SolveArgs* items, int n, hipStream_t s);
 hipError_t launch_solve_eig(const SolveArgs& a, hipStream_t s);
 

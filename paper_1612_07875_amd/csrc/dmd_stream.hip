@@ -1685,7 +1685,7 @@ namespace {
 // copied to the device before the grouped launches (two copies alternate so
 // that the host never overwrites a table a tick in flight still reads).
 struct TickLayout {
-    size_t gram, gblk, lds, glb, tlds, tglb, all, proj, pblk, bytes;
+    size_t gram, gblk, lds, glb, tlds, tglb, clds, cglb, all, proj, pblk, bytes;
     static TickLayout make(int cap) {
         TickLayout L;
         auto al = [](size_t x) { return (x + 255) / 256 * 256; };
@@ -1695,7 +1695,9 @@ struct TickLayout {
         L.glb = al(L.lds + sizeof(dmd::SolveArgs) * cap);
         L.tlds = al(L.glb + sizeof(dmd::SolveArgs) * cap);
         L.tglb = al(L.tlds + sizeof(dmd::SolveArgs) * cap);
-        L.all = al(L.tglb + sizeof(dmd::SolveArgs) * cap);
+        L.clds = al(L.tglb + sizeof(dmd::SolveArgs) * cap);
+        L.cglb = al(L.clds + sizeof(dmd::SolveArgs) * cap);
+        L.all = al(L.cglb + sizeof(dmd::SolveArgs) * cap);
         L.proj = al(L.all + sizeof(dmd::SolveArgs) * cap);
         L.pblk = al(L.proj + sizeof(dmd::ProjectArgs) * cap);
         L.bytes = al(L.pblk + sizeof(int) * (cap + 1));
@@ -1826,8 +1828,9 @@ DMD_API int dmd_batch_attach(dmd_batch_t* b, dmd_stream_t* h) {
     if (!b) return fail(DMD_E_INVAL, "null batch");
     if (int rc = check_handle(h)) return rc;
     if (h->device != b->device) return fail(DMD_E_UNSUPPORTED, "stream and batch are on different devices");
-    if (h->cplx || h->elem_bytes != 4 || h->coef_f64 || !h->opts.auto_solve)
-        return fail(DMD_E_UNSUPPORTED, "batches take dense FP32 streams with FP32 projections and auto_solve");
+    if (!h->opts.auto_solve) return fail(DMD_E_UNSUPPORTED, "batch members solve every push (auto_solve)");
+    if (h->cplx && !h->use_trid)
+        return fail(DMD_E_UNSUPPORTED, "sparse batch members use the tridiagonal solver (no warm start)");
     for (dmd_stream* x : b->members)
         if (x == h) return fail(DMD_E_INVAL, "stream already attached");
     if ((int)b->members.size() >= b->cap) return fail(DMD_E_INVAL, "batch is full (%d streams)", b->cap);
@@ -1859,13 +1862,27 @@ DMD_API int dmd_batch_info(dmd_batch_t* b, int32_t* nstreams, int64_t* used_byte
     return DMD_OK;
 }
 
-DMD_API int dmd_batch_tick(dmd_batch_t* b, int32_t count, dmd_stream_t* const* streams,
-                           const void* const* snapshots, void* const* modes, const int64_t* ld_modes,
-                           void* stream) {
-    if (!b) return fail(DMD_E_INVAL, "null batch");
+namespace {
+// One member's frame of a tick: dense x, or a sparse snapshot (nnz, idx, val).
+struct TickFrame {
+    const void* x;
+    int32_t nnz;
+    const int32_t* idx;
+    const void* val;
+};
+
+// A tick over any mix of members.  Dense FP32 members with FP32 projections
+// (class A) take the grouped Gram pass and the grouped projection; FP64
+// members (FP64 data or FP64 projections) and sparse members run their own
+// Gram (or sparse ingest) and projection kernels inside the tick, on the same
+// stream; the small solves of every member are grouped (real tridiagonal or
+// Jacobi, Hermitian tridiagonal, eig).  Each member's kernels are the ones its
+// own push would run, so its results equal its results alone, bit for bit.
+int batch_tick_impl(dmd_batch* b, int count, dmd_stream* const* streams, const TickFrame* frames,
+                    void* const* modes, const int64_t* ld_modes, void* stream) {
     if (count < 0 || count > b->cap) return fail(DMD_E_INVAL, "count must be in [0, %d]", b->cap);
     if (count == 0) return DMD_OK;
-    if (!streams || !snapshots) return fail(DMD_E_INVAL, "null streams or snapshots");
+    if (!streams || !frames) return fail(DMD_E_INVAL, "null streams or frames");
     for (int i = 0; i < count; ++i) {
         dmd_stream* h = streams[i];
         bool member = false;
@@ -1873,7 +1890,16 @@ DMD_API int dmd_batch_tick(dmd_batch_t* b, int32_t count, dmd_stream_t* const* s
         if (!member) return fail(DMD_E_INVAL, "streams[%d] is not attached to the batch", i);
         for (int j = 0; j < i; ++j)
             if (streams[j] == h) return fail(DMD_E_INVAL, "streams[%d] appears twice in one tick", i);
-        if (!snapshots[i] || (uintptr_t)snapshots[i] % 4) return fail(DMD_E_INVAL, "snapshots[%d] null or misaligned", i);
+        const TickFrame& f = frames[i];
+        if (h->cplx) {
+            if (f.nnz < 0 || f.nnz > h->max_nnz)
+                return fail(DMD_E_INVAL, "frames[%d]: nnz must be in [0, max_nnz=%d]", i, h->max_nnz);
+            if (f.nnz > 0 && (!f.idx || !f.val)) return fail(DMD_E_INVAL, "frames[%d]: null idx or val", i);
+            if ((uintptr_t)f.idx % 4 || (uintptr_t)f.val % 8)
+                return fail(DMD_E_INVAL, "frames[%d]: idx must be 4-byte and val 8-byte aligned", i);
+        } else if (!f.x || (uintptr_t)f.x % h->elem_bytes) {
+            return fail(DMD_E_INVAL, "snapshots[%d] null or not %d-byte aligned", i, h->elem_bytes);
+        }
         if (modes && modes[i]) {
             if (!ld_modes || ld_modes[i] < h->n) return fail(DMD_E_INVAL, "ld_modes[%d] < n", i);
         }
@@ -1890,51 +1916,100 @@ DMD_API int dmd_batch_tick(dmd_batch_t* b, int32_t count, dmd_stream_t* const* s
     auto* sg = reinterpret_cast<dmd::SolveArgs*>(H + b->L.glb);
     auto* tl = reinterpret_cast<dmd::SolveArgs*>(H + b->L.tlds);
     auto* tg = reinterpret_cast<dmd::SolveArgs*>(H + b->L.tglb);
+    auto* cl = reinterpret_cast<dmd::SolveArgs*>(H + b->L.clds);
+    auto* cg = reinterpret_cast<dmd::SolveArgs*>(H + b->L.cglb);
     auto* sa = reinterpret_cast<dmd::SolveArgs*>(H + b->L.all);
     auto* pa = reinterpret_cast<dmd::ProjectArgs*>(H + b->L.proj);
     int* pblk = reinterpret_cast<int*>(H + b->L.pblk);
-    int nl = 0, ng = 0, ntl = 0, ntg = 0, np = 0, gtot = 0, ptot = 0;
+    int na = 0, nl = 0, ng = 0, ntl = 0, ntg = 0, ncl = 0, ncg = 0, np = 0, gtot = 0, ptot = 0;
+    std::vector<int> own;  // members that run their own Gram and projection kernels
     for (int i = 0; i < count; ++i) {
         dmd_stream* h = streams[i];
-        dmd::GramItem& it = gi[i];
-        it = dmd::GramItem{};
-        it.x = snapshots[i];
-        it.ring = h->ring;
-        it.ld = h->ld;
-        it.n = h->n;
-        it.m = h->m;
-        it.slots = h->slots;
-        it.x_aligned = ((uintptr_t)snapshots[i] % 16) == 0;
-        it.iter = h->gram_iter;
-        it.nblk = dmd::gram_blocks(h->n, h->elem_bytes, h->gram_iter);
-        it.partials = h->partials;
-        it.G = h->G;
-        it.st = reinterpret_cast<DevState*>(h->res_dev);
-        gblk[i] = gtot;
-        gtot += it.nblk;
+        const bool grouped = !h->cplx && h->elem_bytes == 4 && !h->coef_f64;
+        if (grouped) {
+            dmd::GramItem& it = gi[na];
+            it = dmd::GramItem{};
+            it.x = frames[i].x;
+            it.ring = h->ring;
+            it.ld = h->ld;
+            it.n = h->n;
+            it.m = h->m;
+            it.slots = h->slots;
+            it.x_aligned = ((uintptr_t)frames[i].x % 16) == 0;
+            it.iter = h->gram_iter;
+            it.nblk = dmd::gram_blocks(h->n, h->elem_bytes, h->gram_iter);
+            it.partials = h->partials;
+            it.G = h->G;
+            it.st = reinterpret_cast<DevState*>(h->res_dev);
+            gblk[na] = gtot;
+            gtot += it.nblk;
+            ++na;
+            if (modes && modes[i]) {
+                fill_project_args(h, pa[np], modes[i], ld_modes[i], true);
+                pblk[np] = ptot;
+                ptot += dmd::project_item_blocks(h->n);
+                ++np;
+            }
+        } else {
+            own.push_back(i);
+        }
         dmd::SolveArgs a;
         fill_solve_args(h, a);
         sa[i] = a;
-        const bool small = h->m + (h->m & 1) <= 64;
-        if (h->use_trid) {
-            if (small) tl[ntl++] = a;
-            else tg[ntg++] = a;
+        if (h->cplx) {
+            if (h->m <= 32) cl[ncl++] = a;
+            else cg[ncg++] = a;
         } else {
-            if (small) sl[nl++] = a;
-            else sg[ng++] = a;
-        }
-        if (modes && modes[i]) {
-            fill_project_args(h, pa[np], modes[i], ld_modes[i], true);
-            pblk[np] = ptot;
-            ptot += dmd::project_item_blocks(h->n);
-            ++np;
+            const bool small = h->m + (h->m & 1) <= 64;
+            if (h->use_trid) {
+                if (small) tl[ntl++] = a;
+                else tg[ntg++] = a;
+            } else {
+                if (small) sl[nl++] = a;
+                else sg[ng++] = a;
+            }
         }
     }
-    gblk[count] = gtot;
+    gblk[na] = gtot;
     pblk[np] = ptot;
     // order after every member's earlier work and the batch's previous tick
     for (int i = 0; i < count; ++i) HIP_TRY(begin(streams[i], s));
     if (b->has_last && b->last_stream != s) HIP_TRY(hipStreamWaitEvent(s, b->ev_last, 0));
+    // the Gram pass (or sparse ingest) of a member with kernels of its own
+    auto own_gram = [&](hipStream_t q, int i) -> hipError_t {
+        dmd_stream* h = streams[i];
+        DevState* st = reinterpret_cast<DevState*>(h->res_dev);
+        if (h->cplx)
+            return dmd::launch_csr_push(frames[i].idx, static_cast<const float2*>(frames[i].val), frames[i].nnz, h->n,
+                                        h->ring_idx, h->ring_val, h->ring_nnz, h->max_nnz, h->m, h->scatter, h->flag,
+                                        h->G, h->partials, st, q);
+        int nblk = 0;
+        hipError_t e;
+        if (h->elem_bytes == 8)
+            e = dmd::launch_gram_columns<double>(static_cast<const double*>(frames[i].x), static_cast<double*>(h->ring),
+                                                 h->ld, h->n, h->m, h->slots, h->partials, h->nblk_cap, st,
+                                                 h->gram_iter, &nblk, q);
+        else
+            e = dmd::launch_gram_columns<float>(static_cast<const float*>(frames[i].x), static_cast<float*>(h->ring),
+                                                h->ld, h->n, h->m, h->slots, h->partials, h->nblk_cap, st,
+                                                h->gram_iter, &nblk, q);
+        if (e != hipSuccess) return e;
+        return dmd::launch_gram_finalize(h->G, h->partials, nblk, h->m, h->slots, st, q);
+    };
+    auto own_project = [&](hipStream_t q, int i) -> hipError_t {
+        dmd_stream* h = streams[i];
+        if (!modes || !modes[i]) return hipSuccess;
+        if (h->cplx)
+            return dmd::launch_csr_project(reinterpret_cast<const DevState*>(h->res_dev), h->ring_idx, h->ring_val,
+                                           h->ring_nnz, h->max_nnz, h->m, 1, static_cast<const float2*>(h->Bphi), h->r,
+                                           static_cast<float2*>(modes[i]), ld_modes[i], h->n,
+                                           dmd::CsrUnionScratch{h->upos, h->ulist, h->ucount, h->ucount + 1,
+                                                                h->ucap, h->ublock},
+                                           q);
+        dmd::ProjectArgs a;
+        fill_project_args(h, a, modes[i], ld_modes[i], true);
+        return dmd::launch_project(a, q);
+    };
     // the tick's work: descriptors to the device, then one grouped launch per phase
     auto enqueue = [&](hipStream_t q, bool time_phases) -> hipError_t {
         hipError_t e = hipMemcpyAsync(D, H, b->L.bytes, hipMemcpyHostToDevice, q);
@@ -1942,7 +2017,11 @@ DMD_API int dmd_batch_tick(dmd_batch_t* b, int32_t count, dmd_stream_t* const* s
         auto phase = [&](const char* name, auto&& fn) { return time_phases ? timed(name, q, fn) : fn(); };
         auto* dgi = reinterpret_cast<const dmd::GramItem*>(D + b->L.gram);
         auto* dgblk = reinterpret_cast<const int*>(D + b->L.gblk);
-        e = phase("batch_gram", [&] { return dmd::launch_gram_grouped(dgi, dgblk, count, gtot, q); });
+        e = phase("batch_gram", [&] {
+            hipError_t f = na > 0 ? dmd::launch_gram_grouped(dgi, dgblk, na, gtot, q) : hipSuccess;
+            for (size_t u = 0; u < own.size() && f == hipSuccess; ++u) f = own_gram(q, own[u]);
+            return f;
+        });
         if (e != hipSuccess) return e;
         e = phase("batch_solve", [&] {
             hipError_t f = dmd::launch_jacobi_grouped(reinterpret_cast<const dmd::SolveArgs*>(D + b->L.lds), nl,
@@ -1951,16 +2030,25 @@ DMD_API int dmd_batch_tick(dmd_batch_t* b, int32_t count, dmd_stream_t* const* s
                 f = dmd::launch_trid_grouped(reinterpret_cast<const dmd::SolveArgs*>(D + b->L.tlds), ntl,
                                              reinterpret_cast<const dmd::SolveArgs*>(D + b->L.tglb), ntg, q);
             if (f == hipSuccess)
+                f = dmd::launch_trid_grouped_cplx(reinterpret_cast<const dmd::SolveArgs*>(D + b->L.clds), ncl,
+                                                  reinterpret_cast<const dmd::SolveArgs*>(D + b->L.cglb), ncg, q);
+            if (f == hipSuccess)
                 f = dmd::launch_eig_grouped(reinterpret_cast<const dmd::SolveArgs*>(D + b->L.all), count, q);
             return f;
         });
-        if (e != hipSuccess || np == 0) return e;
+        if (e != hipSuccess || !modes) return e;
         return phase("batch_project", [&] {
-            return dmd::launch_project_grouped(reinterpret_cast<const dmd::ProjectArgs*>(D + b->L.proj),
-                                               reinterpret_cast<const int*>(D + b->L.pblk), np, ptot, q);
+            hipError_t f = np > 0 ? dmd::launch_project_grouped(reinterpret_cast<const dmd::ProjectArgs*>(D + b->L.proj),
+                                                                reinterpret_cast<const int*>(D + b->L.pblk), np, ptot, q)
+                                  : hipSuccess;
+            for (size_t u = 0; u < own.size() && f == hipSuccess; ++u) f = own_project(q, own[u]);
+            return f;
         });
     };
-    if (b->graphs > 0) {
+    // graph replays take every per-tick value from the descriptors; members
+    // with kernels of their own pass their frames as launch arguments, so
+    // such ticks run eagerly
+    if (b->graphs > 0 && own.empty()) {
         const TickShape shape{buf, count, nl, ng, ntl, ntg, gtot, np, ptot};
         TickGraph* tg = nullptr;
         for (TickGraph& g : b->tick_graphs)
@@ -2016,4 +2104,36 @@ DMD_API int dmd_batch_tick(dmd_batch_t* b, int32_t count, dmd_stream_t* const* s
     b->has_last = true;
     HIP_TRY(hipEventRecord(b->ev_last, s));
     return DMD_OK;
+}
+}  // namespace
+
+DMD_API int dmd_batch_tick(dmd_batch_t* b, int32_t count, dmd_stream_t* const* streams,
+                           const void* const* snapshots, void* const* modes, const int64_t* ld_modes,
+                           void* stream) {
+    if (!b) return fail(DMD_E_INVAL, "null batch");
+    if (count < 0 || count > b->cap) return fail(DMD_E_INVAL, "count must be in [0, %d]", b->cap);
+    if (count == 0) return DMD_OK;
+    if (!streams || !snapshots) return fail(DMD_E_INVAL, "null streams or snapshots");
+    std::vector<TickFrame> f((size_t)count);
+    for (int i = 0; i < count; ++i) {
+        if (int rc = check_handle(streams[i])) return rc;
+        if (streams[i]->cplx) return fail(DMD_E_INVAL, "streams[%d] is sparse: use dmd_batch_tick_frames", i);
+        f[i] = TickFrame{snapshots[i], 0, nullptr, nullptr};
+    }
+    return batch_tick_impl(b, count, streams, f.data(), modes, ld_modes, stream);
+}
+
+DMD_API int dmd_batch_tick_frames(dmd_batch_t* b, int32_t count, dmd_stream_t* const* streams,
+                                  const dmd_frame_t* frames, void* const* modes, const int64_t* ld_modes,
+                                  void* stream) {
+    if (!b) return fail(DMD_E_INVAL, "null batch");
+    if (count < 0 || count > b->cap) return fail(DMD_E_INVAL, "count must be in [0, %d]", b->cap);
+    if (count == 0) return DMD_OK;
+    if (!streams || !frames) return fail(DMD_E_INVAL, "null streams or frames");
+    std::vector<TickFrame> f((size_t)count);
+    for (int i = 0; i < count; ++i) {
+        if (int rc = check_handle(streams[i])) return rc;
+        f[i] = TickFrame{frames[i].x, frames[i].nnz, frames[i].idx, frames[i].val};
+    }
+    return batch_tick_impl(b, count, streams, f.data(), modes, ld_modes, stream);
 }

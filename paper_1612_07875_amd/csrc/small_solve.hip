@@ -1787,6 +1787,30 @@ hipError_t launch_trid_grouped(const SolveArgs* items_lds, int n_lds, const Solv
     return hipSuccess;
 }
 
+hipError_t launch_trid_grouped_cplx(const SolveArgs* items_lds, int n_lds, const SolveArgs* items_glb, int n_glb,
+                                    hipStream_t s) {
+    // Hermitian windows (sparse streams); items_lds: m <= 32, items_glb: m > 32
+    if (n_lds > 0) {
+        const size_t lds = sizeof(double) * 2 * 32 * kRMax + sizeof(cplx) * 32 * 33;
+        auto kern = k_solve_trid_grouped<cplx, 1024, true>;
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(n_lds), dim3(1024), lds, s, items_lds);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (n_glb > 0) {
+        const size_t lds = sizeof(double) * 2 * kMaxM * kRMax;
+        auto kern = k_solve_trid_grouped<cplx, 1024, false>;
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(n_glb), dim3(1024), lds, s, items_glb);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_eig_grouped(const SolveArgs* items, int n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_solve_eig_grouped, dim3(n), dim3(64), 0, s, items);

@@ -127,10 +127,14 @@ def test_batch_admission_by_hbm_budget():
 def test_batch_rejects_unsupported_members():
     dmd = _dmd()
     with dmd.Batch(max_streams=2) as batch:
+        # members solve on every tick; sparse members use the tridiagonal solver
+        for kw in ({"auto_solve": False}, {"dtype": "c64_csr", "max_nnz": 16, "eig_solver": "jacobi"}):
+            bad = dmd.Stream(1024, 8, 4, **kw)
+            with pytest.raises(dmd.DMDError) as ei:
+                batch.attach(bad)
+            assert ei.value.code == dmd.E_UNSUPPORTED, kw
+            bad.close()
         s64 = dmd.Stream(1000, 8, 4, dtype="f64")
-        with pytest.raises(dmd.DMDError) as ei:
-            batch.attach(s64)
-        assert ei.value.code == dmd.E_UNSUPPORTED
         s = dmd.Stream(1000, 8, 4)
         batch.attach(s)
         with pytest.raises(dmd.DMDError):
@@ -218,3 +222,111 @@ def test_graph_option_checks():
         with pytest.raises(dmd.DMDError) as ei:
             dmd.Batch(max_streams=4, graphs=bad)
         assert ei.value.code == dmd.E_INVAL
+
+
+# Heterogeneous members (dmd_batch_tick_frames): FP32 streams with FP32 or
+# split-BF16 projections share the grouped launches; FP64 streams (FP64 data,
+# or FP32 data with FP64 projections) and sparse complex streams (Sec. 3.5)
+# run their own Gram / ingest and projection kernels inside the tick; every
+# member's small solves are grouped, real and Hermitian windows of both sizes.
+HETERO = [  # (kind, n or (side, nnz), m, r, options)
+    ("video", 20000, 16, 8, {}),
+    ("flow", 33333, 32, 12, {"precision": "bf16x3"}),
+    ("video", 50001, 24, 10, {"dtype": "f64"}),
+    ("flow", 40000, 64, 16, {"precision": "fp64"}),
+    ("video", 9000, 80, 12, {}),                     # real window above 64: solve from global memory
+    ("sparse", (64, 80), 16, 6, {}),                 # Hermitian window in LDS
+    ("sparse", (48, 61), 40, 8, {}),                 # Hermitian window above 32
+]
+
+
+def _hetero_frames(i, kind, size, m, T):
+    """Frames (device) and their FP64 values (host) of member i."""
+    if kind == "sparse":
+        side, nnz = size
+        fs = gen.FourierSparse(side=side, nnz=nnz, redraw=0.05)
+        dev, host = [], []
+        for t in range(T):
+            idx, val = fs.frame(t)
+            dev.append((torch.from_numpy(idx).cuda(), torch.from_numpy(val).cuda()))
+            host.append(oracle.densify(idx, val, fs.n))
+        return fs.n, dev, np.stack(host, axis=1)
+    g = make_gen(200 + i, size, kind)
+    F = np.stack([g.frame(t) for t in range(T)], axis=1).astype(np.float32)
+    return size, F, F.astype(np.float64)
+
+
+def _open(dmd, kind, n, m, r, opts, nnz):
+    if kind == "sparse":
+        return dmd.Stream(n, m, r, dtype="c64_csr", max_nnz=nnz + 5)
+    return dmd.Stream(n, m, r, **opts)
+
+
+@pytest.mark.parametrize("graphs", [0, 2])
+def test_batch_mixed_members_equal_alone_and_oracle(graphs):
+    dmd = _dmd()
+    T_extra = 3
+    members = []
+    for i, (kind, size, m, r, opts) in enumerate(HETERO):
+        T = m + 1 + T_extra
+        n, F, host = _hetero_frames(i, kind, size, m, T)
+        if kind == "sparse":
+            frames = F
+        else:
+            elem = torch.float64 if opts.get("dtype") == "f64" else torch.float32
+            X = torch.from_numpy(F.T.copy()).to(elem).cuda()
+            frames = [X[t] for t in range(T)]
+        nnz = size[1] if kind == "sparse" else 0
+        members.append((kind, n, m, r, opts, nnz, frames, host))
+
+    def push_one(s, kind, f):
+        if kind == "sparse":
+            s.push_csr(*f)
+        else:
+            s.push(f)
+
+    alone = []
+    for kind, n, m, r, opts, nnz, frames, host in members:
+        with _open(dmd, kind, n, m, r, opts, nnz) as s:
+            for f in frames:
+                push_one(s, kind, f)
+            lam, sig, _ = s.eigs()
+            alone.append((s.gram(), lam, sig, s.modes().cpu().numpy()))
+
+    streams = [_open(dmd, kind, n, m, r, opts, nnz) for kind, n, m, r, opts, nnz, frames, host in members]
+    batch = dmd.Batch(max_streams=16, graphs=graphs)
+    for s in streams:
+        batch.attach(s)
+    # dmd_batch_tick takes dense members only
+    sp = [i for i, mb in enumerate(members) if mb[0] == "sparse"][0]
+    with pytest.raises(dmd.DMDError) as ei:
+        batch.tick([streams[sp]], [torch.zeros(streams[sp].n, dtype=torch.complex64, device="cuda")])
+    assert ei.value.code == dmd.E_INVAL
+    T = max(len(mb[6]) for mb in members)
+    outs = [torch.zeros((s.r, s.n), dtype=s.mode_dtype, device="cuda").T for s in streams]
+    for t in range(T):
+        act = [i for i, mb in enumerate(members) if t >= T - len(mb[6])]
+        batch.tick_frames([streams[i] for i in act], [members[i][6][t - (T - len(members[i][6]))] for i in act],
+                          modes=[outs[i] for i in act])
+    torch.cuda.synchronize()
+    for i, s in enumerate(streams):
+        kind, n, m, r, opts, nnz, frames, host = members[i]
+        lam, sig, _ = s.eigs()
+        G = s.gram()
+        phi = outs[i].cpu().numpy()
+        a = alone[i]
+        assert np.array_equal(G, a[0]), i
+        assert np.array_equal(lam, a[1]) and np.array_equal(sig, a[2]), i
+        k = lam.size
+        assert np.array_equal(phi[:, :k], a[3][:, :k]), i
+        W = host[:, -(m + 1):]
+        ref = oracle.exact_dmd(W[:, :m], W[:, 1:], r)
+        assert k == ref.r_eff, i
+        kap2 = (ref.sigma[0] / ref.sigma[:k]) ** 2
+        assert np.all(metrics.sigma_relerr(sig, ref.sigma[:k]) <= 1e-11 + 1e-13 * kap2), i
+        err, perm = metrics.eig_relerr(lam, ref.lam)
+        bound = eig_bound(ref)[perm]
+        assert np.all(err <= bound), (i, err, bound)
+    batch.close()
+    for s in streams:
+        s.close()
