@@ -121,6 +121,22 @@ __device__ __forceinline__ double wave_max(double x) {
     x = fmax(x, __shfl_xor(x, 16, 64));
     return fmax(x, __shfl_xor(x, 32, 64));
 }
+// Ordering of LDS accesses among the lanes of one wavefront: LDS executes a
+// wavefront's instructions in issue order, so a compiler-level fence at
+// wavefront scope is all that a one-wavefront workgroup needs between a
+// write and another lane's read (no wait for outstanding LDS work).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+// x of lane src (src the same in every lane), read from the register file.
+__device__ __forceinline__ double lane_f64(double x, int src) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    const int lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), src);
+    const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
 // Rotation (c, s) with c^2 + s^2 = 1 to working precision that annihilates
 // the off-diagonal of the real 2x2 [[a, g], [g, b]] (g > 0): t = tan(phi) is
 // the root of t^2 + 2 theta t - 1 = 0 of smaller modulus, theta = (b-a)/(2g).
@@ -596,7 +612,7 @@ constexpr int LDH = kRMax + 1;
 // storage, real values) accumulates the transformations.  The 2 x 2 blocks
 // left on the diagonal are then triangularized by one complex rotation each,
 // so that H becomes the complex upper triangular T of the complex Schur form.
-__device__ void real_schur(cplx* H, cplx* Z, int k, int lane, int max_iter, double hmax, int& total, bool& failed) {
+__device__ __forceinline__ void real_schur(cplx* H, cplx* Z, int k, int lane, int max_iter, double hmax, int& total, bool& failed) {
     auto h = [&](int i, int j) -> double& { return H[i + j * LDH].re; };
     int nn = k - 1, its = 0;
     while (nn >= 0) {
@@ -610,9 +626,9 @@ __device__ void real_schur(cplx* H, cplx* Z, int k, int lane, int max_iter, doub
         }
         const unsigned long long mask = __ballot(small);
         const int l = mask ? 63 - __clzll(mask) : 0;
-        __syncthreads();
+        wave_sync();
         if (l > 0 && lane == 0) h(l, l - 1) = 0.0;
-        __syncthreads();
+        wave_sync();
         if (l >= nn - 1) {  // a 1 x 1 or 2 x 2 block splits off
             nn = l - 1;
             its = 0;
@@ -638,72 +654,85 @@ __device__ void real_schur(cplx* H, cplx* Z, int k, int lane, int max_iter, doub
                 t = a11 * a22 - a12 * a21;
             }
         }
+        // (x, y, z): the first column of (H - mu1)(H - mu2) to start the
+        // sweep, then the bulge below the subdiagonal of column kk-1; the
+        // latter were just written by the lanes that updated column kk-1,
+        // and are read from their registers (the LDS copy only when that
+        // step applied no reflector)
+        double x, y, z;
+        {
+            const double h00 = h(l, l), h10 = h(l + 1, l);
+            x = h00 * h00 + h(l, l + 1) * h10 - s * h00 + t;
+            y = h10 * (h00 + h(l + 1, l + 1) - s);
+            z = h10 * h(l + 2, l + 1);
+        }
+        // One bulge step is straight-line code: every lane reads its column
+        // (rows kk .. kk+2) and its row of Z (columns kk .. kk+2) before the
+        // reflector is known, and lanes outside a range write to a sink
+        // entry past the matrix instead of branching, so that the updates
+        // of H's rows and of Z interleave.
+        const int lc = lane < LDH ? lane : LDH - 1;  // this lane's column / row, clamped
+        const int sink = LDH * LDH + lane;
         for (int kk = l; kk < nn; ++kk) {
-            double x, y, z;
-            if (kk == l) {
-                const double h00 = h(l, l), h10 = h(l + 1, l);
-                x = h00 * h00 + h(l, l + 1) * h10 - s * h00 + t;
-                y = h10 * (h00 + h(l + 1, l + 1) - s);
-                z = h10 * h(l + 2, l + 1);
-            } else {
-                x = h(kk, kk - 1);
-                y = h(kk + 1, kk - 1);
-                z = kk + 2 <= nn ? h(kk + 2, kk - 1) : 0.0;
-            }
             const bool three = kk + 2 <= nn;
+            const double r0 = h(kk, lc), r1 = h(kk + 1, lc), r2 = h(kk + 2, lc);
+            const double zc0 = Z[lc + kk * LDH].re, zc1 = Z[lc + (kk + 1) * LDH].re, zc2 = Z[lc + (kk + 2) * LDH].re;
             // (the bulge chase is a chain of dependent FP64 steps: the norm and
             // 2 / v^T v come from the hardware estimates plus Newton steps,
             // shorter chains than the correctly rounded square root and division)
             const double s2 = x * x + y * y + z * z;
             const double nrm = s2 > 0.0 ? s2 * rsqrt_acc(s2) : 0.0;
             // reflector P = I - tau v v^T, v = (x - alpha, y, z), P (x, y, z) = (alpha, 0, 0)
+            // (z = 0 exactly when the step has two rows)
             const double alpha = x > 0.0 ? -nrm : nrm;
             const double v0 = x - alpha;
             const double vtv = v0 * v0 + y * y + z * z;
             const double tau = vtv > 0.0 ? 2.0 * rcp_acc(vtv) : 0.0;
-            __syncthreads();
+            double nc0 = 0.0;  // this lane's new H[lane][kk]
             if (tau != 0.0) {
-                // rows kk .. kk+2 over columns jlo .. k-1 (lane = column)
+                // rows kk .. kk+2 over columns jlo .. k-1 (lane = column); the
+                // entries below the subdiagonal of column kk-1 become zero
                 const int jlo = kk > l ? kk - 1 : l;
-                const int j = lane;
-                if (j >= jlo && j < k) {
-                    const double r0 = h(kk, j), r1 = h(kk + 1, j), r2 = three ? h(kk + 2, j) : 0.0;
-                    const double f = tau * (v0 * r0 + y * r1 + z * r2);
-                    h(kk, j) = r0 - f * v0;
-                    h(kk + 1, j) = r1 - f * y;
-                    if (three) h(kk + 2, j) = r2 - f * z;
-                }
-            }
-            __syncthreads();
-            if (tau != 0.0) {
-                if (kk > l && lane == 0) {
-                    h(kk + 1, kk - 1) = 0.0;
-                    if (three) h(kk + 2, kk - 1) = 0.0;
-                }
-                // columns kk .. kk+2 over rows 0 .. min(kk+3, nn); Z over all rows (lane = row)
-                const int i = lane;
+                const bool rok = lane >= jlo && lane < k;
+                const double f = tau * (v0 * r0 + y * r1 + z * r2);
+                const bool below = kk > l && lane == kk - 1;
+                H[rok ? kk + lc * LDH : sink].re = r0 - f * v0;
+                H[rok ? kk + 1 + lc * LDH : sink].re = below ? 0.0 : r1 - f * y;
+                H[rok && three ? kk + 2 + lc * LDH : sink].re = below ? 0.0 : r2 - f * z;
+                // Z over all rows (lane = row)
+                const bool zok = lane < k;
+                const double fz = tau * (zc0 * v0 + zc1 * y + zc2 * z);
+                Z[zok ? lc + kk * LDH : sink].re = zc0 - fz * v0;
+                Z[zok ? lc + (kk + 1) * LDH : sink].re = zc1 - fz * y;
+                Z[zok && three ? lc + (kk + 2) * LDH : sink].re = zc2 - fz * z;
+                wave_sync();
+                // columns kk .. kk+2 over rows 0 .. min(kk+3, nn) (lane = row)
                 const int ihi = kk + 3 < nn ? kk + 3 : nn;
-                if (i <= ihi) {
-                    const double c0 = h(i, kk), c1 = h(i, kk + 1), c2 = three ? h(i, kk + 2) : 0.0;
-                    const double f = tau * (c0 * v0 + c1 * y + c2 * z);
-                    h(i, kk) = c0 - f * v0;
-                    h(i, kk + 1) = c1 - f * y;
-                    if (three) h(i, kk + 2) = c2 - f * z;
-                }
-                if (i < k) {
-                    double& z0 = Z[i + kk * LDH].re;
-                    double& z1 = Z[i + (kk + 1) * LDH].re;
-                    const double c0 = z0, c1 = z1, c2 = three ? Z[i + (kk + 2) * LDH].re : 0.0;
-                    const double f = tau * (c0 * v0 + c1 * y + c2 * z);
-                    z0 = c0 - f * v0;
-                    z1 = c1 - f * y;
-                    if (three) Z[i + (kk + 2) * LDH].re = c2 - f * z;
+                const bool cok = lane <= ihi;
+                const double c0 = h(lc, kk), c1 = h(lc, kk + 1), c2 = h(lc, kk + 2);
+                const double fc = tau * (c0 * v0 + c1 * y + c2 * z);
+                nc0 = c0 - fc * v0;
+                H[cok ? lc + kk * LDH : sink].re = nc0;
+                H[cok ? lc + (kk + 1) * LDH : sink].re = c1 - fc * y;
+                H[cok && three ? lc + (kk + 2) * LDH : sink].re = c2 - fc * z;
+            }
+            wave_sync();
+            if (kk + 1 < nn) {
+                // rows kk+1 .. kk+3 of column kk (rows 0 .. kk+3 were updated above)
+                const bool z3 = kk + 3 <= nn;
+                if (tau != 0.0) {
+                    x = lane_f64(nc0, kk + 1);
+                    y = lane_f64(nc0, kk + 2);
+                    z = z3 ? lane_f64(nc0, kk + 3) : 0.0;
+                } else {
+                    x = h(kk + 1, kk);
+                    y = h(kk + 2, kk);
+                    z = z3 ? h(kk + 3, kk) : 0.0;
                 }
             }
-            __syncthreads();
         }
     }
-    __syncthreads();
+    wave_sync();
     // triangularize each 2 x 2 diagonal block [[a, b], [c, d]], c != 0: with
     // u = (lambda_1 - d, c) / ||.||, lambda_1 an eigenvalue of the block, the
     // rotation G = [[u0, -conj(u1)], [u1, conj(u0)]] gives G^* B G = [[lambda_1, .], [0, lambda_2]]
@@ -719,7 +748,7 @@ __device__ void real_schur(cplx* H, cplx* Z, int k, int lane, int max_iter, doub
         const double nu = sqrt(abs2(u0) + abs2(u1));
         u0 = (1.0 / nu) * u0;
         u1 = (1.0 / nu) * u1;
-        __syncthreads();
+        wave_sync();
         {
             const int j = lane;  // rows i, i+1 over columns i .. k-1
             if (j >= i && j < k) {
@@ -728,7 +757,7 @@ __device__ void real_schur(cplx* H, cplx* Z, int k, int lane, int max_iter, doub
                 H[(i + 1) + j * LDH] = u0 * r1 - u1 * r0;
             }
         }
-        __syncthreads();
+        wave_sync();
         {
             const int r = lane;  // columns i, i+1 over rows 0 .. i+1; Z over all rows
             if (r <= i + 1) {
@@ -742,14 +771,14 @@ __device__ void real_schur(cplx* H, cplx* Z, int k, int lane, int max_iter, doub
                 Z[r + (i + 1) * LDH] = mul_conj(c1, u0) - mul_conj(c0, u1);
             }
         }
-        __syncthreads();
+        wave_sync();
         if (lane == 0) H[(i + 1) + i * LDH] = mkc(0.0);
-        __syncthreads();
+        wave_sync();
         ++i;  // the next row belongs to this block
     }
 }
 
-__device__ void solve_eig_body(const SolveArgs& a) {
+__device__ __forceinline__ void solve_eig_body(const SolveArgs& a) {
     const int lane = threadIdx.x;
     DevState* st = a.st;
     const int status0 = st->solve_status;
@@ -766,8 +795,8 @@ __device__ void solve_eig_body(const SolveArgs& a) {
         return;
     }
 
-    __shared__ cplx H[LDH * LDH];
-    __shared__ cplx Z[LDH * LDH];
+    __shared__ cplx H[LDH * LDH + 64];  // (64 sink entries past the matrix)
+    __shared__ cplx Z[LDH * LDH + 64];
     __shared__ cplx Y[LDH * LDH];
     __shared__ cplx hv[LDH];
     __shared__ double s_sig[kRMax];
@@ -782,9 +811,10 @@ __device__ void solve_eig_body(const SolveArgs& a) {
         }
         H[idx] = h;
         Z[idx] = mkc(i == j ? 1.0 : 0.0);
+        Y[idx] = mkc(0.0);
     }
     if (lane < k) s_sig[lane] = a.sigma[lane];
-    __syncthreads();
+    wave_sync();
 
     // ---- Householder reduction to upper Hessenberg form, Z accumulates
     for (int c = 0; c + 2 < k; ++c) {
@@ -796,13 +826,13 @@ __device__ void solve_eig_body(const SolveArgs& a) {
         const double ax0 = cabs(x0);
         const double alpha = sqrt(ax0 * ax0 + tail2);
         if (tail2 == 0.0) {
-            __syncthreads();
+            wave_sync();
             continue;
         }
         const cplx ph = ax0 > 0.0 ? cplx{x0.re / ax0, x0.im / ax0} : mkc(1.0);
         // v = x + ph*alpha e1 ; v^* v = 2 alpha (alpha + |x0|) ; P = I - tau v v^*
         if (lane < len) hv[lane] = (lane == 0) ? x0 + ph * alpha : H[(c + 1 + lane) + c * LDH];
-        __syncthreads();
+        wave_sync();
         const double tau = 1.0 / (alpha * (alpha + ax0));
         // left: rows c+1.., columns c..k-1 (lane = column)
         {
@@ -814,7 +844,7 @@ __device__ void solve_eig_body(const SolveArgs& a) {
                 for (int i = 0; i < len; ++i) H[(c + 1 + i) + j * LDH] = H[(c + 1 + i) + j * LDH] - hv[i] * w;
             }
         }
-        __syncthreads();
+        wave_sync();
         // right: all rows, columns c+1.. (lane = row); also Z
         {
             const int i = lane;
@@ -832,9 +862,9 @@ __device__ void solve_eig_body(const SolveArgs& a) {
                 }
             }
         }
-        __syncthreads();
+        wave_sync();
         if (lane < len) H[(c + 1 + lane) + c * LDH] = (lane == 0) ? -(ph * alpha) : mkc(0.0);
-        __syncthreads();
+        wave_sync();
     }
 
     // ---- Schur form T = Z^* A~ Z (full T and Z): real A~ by the implicit
@@ -863,9 +893,9 @@ __device__ void solve_eig_body(const SolveArgs& a) {
         }
         const unsigned long long mask = __ballot(small);
         const int l = mask ? 63 - __clzll(mask) : 0;
-        __syncthreads();
+        wave_sync();
         if (l > 0 && lane == 0) H[l + (l - 1) * LDH] = mkc(0.0);
-        __syncthreads();
+        wave_sync();
         if (l == hi) {
             --hi;
             iter = 0;
@@ -891,15 +921,17 @@ __device__ void solve_eig_body(const SolveArgs& a) {
             // (a+d)/2 +- disc == d + (a-d)/2 +- disc
             mu = (cabs(mu1 - td) <= cabs(mu2 - td)) ? mu1 : mu2;
         }
+        // (x, y): the shifted first column to start the sweep, then the
+        // bulge below the subdiagonal of column kk-1, read from the registers
+        // of the lanes that just updated that column
+        cplx x = H[l + l * LDH] - mu, y = H[(l + 1) + l * LDH];
+        // straight-line steps as in the real sweep: loads first, lanes
+        // outside a range write to a sink entry past the matrix
+        const int lc = lane < LDH ? lane : LDH - 1;
+        const int sink = LDH * LDH + lane;
         for (int kk = l; kk < hi; ++kk) {
-            cplx x, y;
-            if (kk == l) {
-                x = H[l + l * LDH] - mu;
-                y = H[(l + 1) + l * LDH];
-            } else {
-                x = H[kk + (kk - 1) * LDH];
-                y = H[(kk + 1) + (kk - 1) * LDH];
-            }
+            const cplx ru = H[kk + lc * LDH], rv = H[(kk + 1) + lc * LDH];
+            const cplx zu = Z[lc + kk * LDH], zv = Z[lc + (kk + 1) * LDH];
             // G = [[c, s], [-conj(s), c]] with G [x; y] = [rho; 0]:
             // c = |x| / r, s = (x / |x|) conj(y) / r, r^2 = |x|^2 + |y|^2
             double c;
@@ -920,39 +952,39 @@ __device__ void solve_eig_body(const SolveArgs& a) {
                 c = ax / rr;
                 s = (1.0 / rr) * mul_conj(cplx{x.re / ax, x.im / ax}, y);
             }
-            __syncthreads();
-            // rows kk, kk+1 over columns jlo .. k-1
+            // rows kk, kk+1 over columns jlo .. k-1 (lane = column); the entry
+            // below the subdiagonal of column kk-1 becomes zero.  Z over all
+            // rows (lane = row).
             {
                 const int jlo = kk > l ? kk - 1 : l;
-                const int j = lane;
-                if (j >= jlo && j < k) {
-                    const cplx u = H[kk + j * LDH], v = H[(kk + 1) + j * LDH];
-                    H[kk + j * LDH] = c * u + s * v;
-                    H[(kk + 1) + j * LDH] = c * v - conj_mul(s, u);
-                }
+                const bool rok = lane >= jlo && lane < k;
+                const bool below = kk > l && lane == kk - 1;
+                H[rok ? kk + lc * LDH : sink] = c * ru + s * rv;
+                H[rok ? (kk + 1) + lc * LDH : sink] = below ? mkc(0.0) : c * rv - conj_mul(s, ru);
+                const bool zok = lane < k;
+                Z[zok ? lc + kk * LDH : sink] = c * zu + mul_conj(zv, s);
+                Z[zok ? lc + (kk + 1) * LDH : sink] = c * zv - zu * s;
             }
-            __syncthreads();
-            if (kk > l && lane == 0) H[(kk + 1) + (kk - 1) * LDH] = mkc(0.0);
-            // columns kk, kk+1 over rows 0 .. min(kk+2, hi); Z over all rows
+            wave_sync();
+            // columns kk, kk+1 over rows 0 .. min(kk+2, hi) (lane = row)
+            cplx nc;  // this lane's new H[lane][kk]
             {
-                const int i = lane;
                 const int ihi = kk + 2 < hi ? kk + 2 : hi;
-                if (i <= ihi) {
-                    const cplx u = H[i + kk * LDH], v = H[i + (kk + 1) * LDH];
-                    H[i + kk * LDH] = c * u + mul_conj(v, s);
-                    H[i + (kk + 1) * LDH] = c * v - u * s;
-                }
-                if (i < k) {
-                    const cplx u = Z[i + kk * LDH], v = Z[i + (kk + 1) * LDH];
-                    Z[i + kk * LDH] = c * u + mul_conj(v, s);
-                    Z[i + (kk + 1) * LDH] = c * v - u * s;
-                }
+                const bool cok = lane <= ihi;
+                const cplx u = H[lc + kk * LDH], v = H[lc + (kk + 1) * LDH];
+                nc = c * u + mul_conj(v, s);
+                H[cok ? lc + kk * LDH : sink] = nc;
+                H[cok ? lc + (kk + 1) * LDH : sink] = c * v - u * s;
             }
-            __syncthreads();
+            wave_sync();
+            if (kk + 1 < hi) {  // rows kk+1, kk+2 of column kk (both updated above)
+                x = cplx{lane_f64(nc.re, kk + 1), lane_f64(nc.im, kk + 1)};
+                y = cplx{lane_f64(nc.re, kk + 2), lane_f64(nc.im, kk + 2)};
+            }
         }
     }
     }
-    __syncthreads();
+    wave_sync();
 
     // ---- eigenvectors of the triangular T: (T - t_qq) y = 0, y_q = 1 (lane q)
     {
@@ -970,11 +1002,11 @@ __device__ void solve_eig_body(const SolveArgs& a) {
             }
         }
     }
-    __syncthreads();
+    wave_sync();
     // W = Z Y (lane = row), written over T
     cplx lam_q = mkc(0.0);
     if (lane < k) lam_q = H[lane + lane * LDH];
-    __syncthreads();
+    wave_sync();
     {
         const int i = lane;
         if (i < k) {
@@ -985,13 +1017,13 @@ __device__ void solve_eig_body(const SolveArgs& a) {
             }
         }
     }
-    __syncthreads();
+    wave_sync();
     // normalise column q (lane q): unit norm, largest-modulus entry (lowest
     // index on ties) real positive; rank by |lambda| descending, arg ascending
     __shared__ cplx s_lam[kRMax];
     __shared__ int s_partner[kRMax];
     if (lane < k) s_lam[lane] = lam_q;
-    __syncthreads();
+    wave_sync();
     if (!a.cplx) {
         // A real A~ has a spectrum closed under conjugation.  The complex QR
         // returns each conjugate pair with independent rounding; pair them
@@ -1011,7 +1043,7 @@ __device__ void solve_eig_body(const SolveArgs& a) {
             }
         }
         if (lane < k) s_partner[lane] = partner;
-        __syncthreads();
+        wave_sync();
         // accept the pairing only if it is a bijection between the two halves
         int npos = 0, nneg = 0, ok = 1;
         for (int p = 0; p < k; ++p) {
@@ -1025,7 +1057,7 @@ __device__ void solve_eig_body(const SolveArgs& a) {
             }
         }
         ok = ok && (npos == nneg);
-        __syncthreads();
+        wave_sync();
         if (ok && lane < k) {
             const int pr = s_partner[lane];
             if (pr >= 0) {
@@ -1035,9 +1067,9 @@ __device__ void solve_eig_body(const SolveArgs& a) {
                 lam_q.im = 0.0;
             }
         }
-        __syncthreads();
+        wave_sync();
         if (lane < k) s_lam[lane] = lam_q;
-        __syncthreads();
+        wave_sync();
     }
     __shared__ double s_mod[kRMax], s_arg[kRMax];
     __shared__ cplx s_ls[kRMax];  // eigenvalues in sorted order
@@ -1045,7 +1077,7 @@ __device__ void solve_eig_body(const SolveArgs& a) {
         s_mod[lane] = cabs(lam_q);
         s_arg[lane] = atan2(lam_q.im, lam_q.re);
     }
-    __syncthreads();
+    wave_sync();
     if (lane < k) {
         const int q = lane;
         double nrm2 = 0.0, best = -1.0;
@@ -1076,7 +1108,7 @@ __device__ void solve_eig_body(const SolveArgs& a) {
             a.W[2 * (i + (int64_t)rank * k) + 1] = w.im;
         }
     }
-    __syncthreads();
+    wave_sync();
 
     // ---- mode amplitudes b = (W Lambda)^-1 alpha_1 (Sec. 3.3), alpha_1 = the
     // POD coefficients of the first snapshot = Sigma_r V_r^* e_1 (first row
@@ -1096,7 +1128,7 @@ __device__ void solve_eig_body(const SolveArgs& a) {
                                : mkc(a.V[(int64_t)lane * ldv]);
         s_rhs[lane] = s_sig[lane] * conj(v0);
     }
-    __syncthreads();
+    wave_sync();
     for (int c = 0; c < k; ++c) {
         double best = -1.0;
         int bi = c;
@@ -1124,20 +1156,20 @@ __device__ void solve_eig_body(const SolveArgs& a) {
                 s_rhs[bi] = t;
             }
         }
-        __syncthreads();
+        wave_sync();
         const cplx piv = H[c + c * LDH];
         if (lane > c && lane < k) {
             const cplx f = cdiv(H[lane + c * LDH], piv);
             for (int j = c + 1; j < k; ++j) H[lane + j * LDH] = H[lane + j * LDH] - f * H[c + j * LDH];
             s_rhs[lane] = s_rhs[lane] - f * s_rhs[c];
         }
-        __syncthreads();
+        wave_sync();
     }
     for (int c = k - 1; c >= 0; --c) {
         if (lane == 0) s_rhs[c] = cdiv(s_rhs[c], H[c + c * LDH]);
-        __syncthreads();
+        wave_sync();
         if (lane < c) s_rhs[lane] = s_rhs[lane] - H[lane + c * LDH] * s_rhs[c];
-        __syncthreads();
+        wave_sync();
     }
     if (lane < k) {
         a.amp[2 * lane] = s_rhs[lane].re;
@@ -1170,7 +1202,7 @@ __device__ void solve_eig_body(const SolveArgs& a) {
         }
         if (lane == 0) s_bg = ok ? bi : 0;
     }
-    __syncthreads();
+    wave_sync();
     if (lane == 0) {
         const int bi = s_bg;
         st->bg_index = bi;
@@ -1179,23 +1211,22 @@ __device__ void solve_eig_body(const SolveArgs& a) {
         const double pm = pow(cabs(lb), (double)m), th = (double)m * atan2(lb.im, lb.re);
         s_fbg = s_rhs[bi] * cplx{pm * cos(th), pm * sin(th)};
     }
-    __syncthreads();
+    wave_sync();
     const int bgq = s_bg;
     const cplx fbg = s_fbg;
 
     // ---- C = V_r Sigma^-1 W (m x k complex), row-major with row stride 2 r;
     // lane i keeps row i of V_r Sigma^-1 in registers, W (sorted) is in LDS
     for (int i = lane; i < m; i += 64) {
+        // (columns past k-1 read column k-1 and are zeroed: every load in flight at once)
         cplx vrow[kRMax];
 #pragma unroll
         for (int p = 0; p < kRMax; ++p) {
-            cplx v = mkc(0.0);
-            if (p < k) {
-                if (a.cplx) v = cplx{a.V[2 * (i + (int64_t)p * ldv)], a.V[2 * (i + (int64_t)p * ldv) + 1]};
-                else v = mkc(a.V[i + (int64_t)p * ldv]);
-                v = v * (1.0 / s_sig[p]);
-            }
-            vrow[p] = v;
+            const int pc = p < k ? p : k - 1;
+            cplx v;
+            if (a.cplx) v = cplx{a.V[2 * (i + (int64_t)pc * ldv)], a.V[2 * (i + (int64_t)pc * ldv) + 1]};
+            else v = mkc(a.V[i + (int64_t)pc * ldv]);
+            vrow[p] = p < k ? v * (1.0 / s_sig[pc]) : mkc(0.0);
         }
         // two columns q at a time: four independent accumulation chains (the
         // sums of each column keep their order)
@@ -1225,16 +1256,13 @@ __device__ void solve_eig_body(const SolveArgs& a) {
         for (int q = 0; q < k; q += 2) {
             const int q1 = q + 1 < k ? q + 1 : q;
             cplx a0 = mkc(0.0), a1 = mkc(0.0), b0 = mkc(0.0), b1 = mkc(0.0);
+            // (rows of Y past k-1 and vrow past k-1 are zero)
 #pragma unroll
             for (int p = 0; p < kRMax; p += 2) {
-                if (p < k) {
-                    a0 = a0 + vrow[p] * Y[p + q * LDH];
-                    b0 = b0 + vrow[p] * Y[p + q1 * LDH];
-                }
-                if (p + 1 < k) {
-                    a1 = a1 + vrow[p + 1] * Y[p + 1 + q * LDH];
-                    b1 = b1 + vrow[p + 1] * Y[p + 1 + q1 * LDH];
-                }
+                a0 = a0 + vrow[p] * Y[p + q * LDH];
+                b0 = b0 + vrow[p] * Y[p + q1 * LDH];
+                a1 = a1 + vrow[p + 1] * Y[p + 1 + q * LDH];
+                b1 = b1 + vrow[p + 1] * Y[p + 1 + q1 * LDH];
             }
             emit(q, a0 + a1);
             if (q + 1 < k) emit(q + 1, b0 + b1);
