@@ -3,12 +3,14 @@
 //
 // The k x k result is cut into 64 x 64 tiles; only tiles on or above the
 // diagonal are computed (G is symmetric) and mirrored.  The n rows are split
-// into `nsplit` ranges so that tiles x splits workgroups fill the chip; each
-// workgroup stages 64 (FP32 data) or 32 (FP64 data) rows of its two 64-column
-// panels in LDS at a time (16-byte coalesced loads) and accumulates its tile
-// with MFMAs; per-split tiles are summed in FP64 in a fixed order by a second
-// kernel, which also writes the Gram (physical slot indexing) and the window
-// state.
+// into `nsplit` ranges so that tiles x splits workgroups fill the chip (the
+// tiles of one split on one XCD, sharing its L2); each workgroup stages 64
+// (FP32 data) or 32 (FP64 data) rows of its two 64-column panels at a time
+// in one of two LDS buffers (16-byte coalesced loads into registers during
+// the previous stage's products) and accumulates its tile with MFMAs,
+// skipping 16-column blocks past the window's last column; per-split tiles
+// are summed in FP64 in a fixed order by a second kernel, which also writes
+// the Gram (physical slot indexing) and the window state.
 //
 // Precision of the products and of the in-tile accumulation:
 //   FP64    v_mfma_f64_16x16x4f64, data widened exactly to FP64;
@@ -63,20 +65,40 @@ __device__ __forceinline__ void tri_of(int t, int ntile, int& ti, int& tj) {
 template <typename TX, int MODE>
 __global__ __launch_bounds__(kThreads)
 void k_gram_tiles(GramFullArgs a) {
-    constexpr int R = sizeof(TX) == 8 ? 32 : 64;  // rows staged per step
-    constexpr int LDR = R + 1;                      // odd stride: column reads spread over banks
+    // Rows are staged 64 (FP32) or 32 (FP64) at a time, column-major with an
+    // odd stride, in two LDS buffers: the next full stage is loaded into
+    // registers while the current one is multiplied, then stored to the
+    // other buffer (one barrier per stage).
+    constexpr int PER = 16 / sizeof(TX);  // elements per 16-byte load
+    constexpr int R = 16 * PER;           // rows per stage
+    constexpr int LDR = R + 1;
+    constexpr int TPC = R / PER;          // loads per column and stage
     using T = typename std::conditional<MODE == MODE_F64, double, float>::type;
     using AccT = typename MAcc<MODE>::type;
-    __shared__ TX Ls[2 * kTile * LDR];
+    using V = typename std::conditional<PER == 4, float4, double2>::type;
+    __shared__ TX Lb[2][2 * kTile * LDR];
 
-    const int tile = blockIdx.x, split = blockIdx.y;
+    // Workgroup b goes to XCD b % 8 (dispatch order).  With nsplit a
+    // multiple of 8, the tiles of one row split share b % 8, so they run on
+    // one XCD and read their common column panels through its L2.
+    const int ntri = a.ntile * (a.ntile + 1) / 2;
+    int tile, split;
+    if (a.nsplit % 8 == 0) {
+        const int x = blockIdx.x & 7, slot = blockIdx.x >> 3;
+        split = slot / ntri * 8 + x;
+        tile = slot % ntri;
+    } else {
+        tile = blockIdx.x % ntri;
+        split = blockIdx.x / ntri;
+    }
     int ti, tj;
     tri_of(tile, a.ntile, ti, tj);
     const bool diag = ti == tj;
     const int oldest = a.oldest_override >= 0 ? a.oldest_override : a.st->oldest;
     const int kcols = a.oldest_override >= 0 ? a.kcols : min(a.kcols, a.st->count);
+    if (kcols <= 0) return;  // (no entry is written back)
     const TX* ring = reinterpret_cast<const TX*>(a.ring);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, lk = lane >> 4;
 
     AccT acc[4];
@@ -86,56 +108,53 @@ void k_gram_tiles(GramFullArgs a) {
     const int64_t r_begin = (int64_t)split * a.rows_per_split;
     const int64_t r_end = min(a.n, r_begin + a.rows_per_split);
     const int npanel = diag ? 1 : 2;
-    for (int64_t r0 = r_begin; r0 < r_end; r0 += R) {
-        // stage rows r0 .. r0+R-1 of the 64 (or 128) columns: column-major, stride LDR
-        constexpr int PER = 16 / sizeof(TX);           // elements per 16-byte load
-        constexpr int TPC = R / PER;                    // threads per column
-        for (int t = threadIdx.x; t < npanel * kTile * TPC; t += kThreads) {
-            const int colp = t / TPC, q = t % TPC;
-            const int c = (colp < kTile ? ti * kTile + colp : tj * kTile + colp - kTile);
-            const int64_t r = r0 + (int64_t)q * PER;
-            TX v[PER];
-            if (c < kcols) {
-                const TX* src = ring + (int64_t)slot_of(oldest, c, a.slots) * a.ld + r;
-                if (r + PER <= r_end) {
-                    if constexpr (PER == 4) {
-                        const float4 w = *reinterpret_cast<const float4*>(src);
-                        v[0] = w.x; v[1] = w.y; v[2] = w.z; v[3] = w.w;
-                    } else {
-                        const double2 w = *reinterpret_cast<const double2*>(src);
-                        v[0] = w.x; v[1] = w.y;
-                    }
-                } else {
+    // global column of staged column c (past the window: the last column;
+    // its products land only in entries that are not written back)
+    auto gcol = [&](int c) {
+        const int g = c < kTile ? ti * kTile + c : tj * kTile + c - kTile;
+        return g < kcols ? g : kcols - 1;
+    };
+    // loads per thread and stage: both panels' columns (a diagonal tile
+    // reads its one panel twice, so that no load sits under a branch)
+    constexpr int NLD = 2 * kTile * TPC / kThreads;
+    // the stage's loads of this thread: column t / TPC, rows q PER .. of the stage
+    const TX* src[NLD];
 #pragma unroll
-                    for (int e = 0; e < PER; ++e) v[e] = (r + e < r_end) ? src[e] : TX(0);
-                }
-            } else {
-#pragma unroll
-                for (int e = 0; e < PER; ++e) v[e] = TX(0);
-            }
-#pragma unroll
-            for (int e = 0; e < PER; ++e) Ls[colp * LDR + q * PER + e] = v[e];
+    for (int u = 0; u < NLD; ++u) {
+        const int t = threadIdx.x + u * kThreads, c = t / TPC, q = t % TPC;
+        src[u] = ring + (int64_t)slot_of(oldest, gcol(c < npanel * kTile ? c : c - kTile), a.slots) * a.ld + q * PER;
+    }
+    auto put = [&](TX* L, int u, const V& v) {
+        const int t = threadIdx.x + u * kThreads, c = t / TPC, q = t % TPC;
+        TX* d = L + c * LDR + q * PER;
+        if constexpr (PER == 4) {
+            d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+        } else {
+            d[0] = v.x; d[1] = v.y;
         }
-        __syncthreads();
-        const TX* Pi = Ls;                                   // panel of rows of the tile
-        const TX* Pj = diag ? Ls : Ls + kTile * LDR;         // panel of its columns
+    };
+    // products of one staged buffer, NC 16-column blocks of the panel
+    // (blocks past the window's last column are skipped)
+    const int cj0 = diag ? 0 : kTile;
+    auto products = [&](const TX* L, auto ncb) __attribute__((always_inline)) {
+        constexpr int NC = decltype(ncb)::value;
         if constexpr (MODE == MODE_BF16X3) {
 #pragma unroll
             for (int k0 = 0; k0 < R; k0 += 32) {
                 v8bf ahi, alo;
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    const float x = (float)Pi[(16 * wave + li) * LDR + k0 + 8 * lk + e];
+                    const float x = (float)L[(16 * wave + li) * LDR + k0 + 8 * lk + e];
                     const __bf16 h = (__bf16)x;
                     ahi[e] = h;
                     alo[e] = (__bf16)(x - (float)h);
                 }
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
+                for (int c = 0; c < NC; ++c) {
                     v8bf bhi, blo;
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
-                        const float x = (float)Pj[(16 * c + li) * LDR + k0 + 8 * lk + e];
+                        const float x = (float)L[(cj0 + 16 * c + li) * LDR + k0 + 8 * lk + e];
                         const __bf16 h = (__bf16)x;
                         bhi[e] = h;
                         blo[e] = (__bf16)(x - (float)h);
@@ -148,19 +167,70 @@ void k_gram_tiles(GramFullArgs a) {
         } else {
 #pragma unroll 4
             for (int k0 = 0; k0 < R; k0 += 4) {
-                const T av = (T)Pi[(16 * wave + li) * LDR + k0 + lk];
+                const T av = (T)L[(16 * wave + li) * LDR + k0 + lk];
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const T bv = (T)Pj[(16 * c + li) * LDR + k0 + lk];
+                for (int c = 0; c < NC; ++c) {
+                    const T bv = (T)L[(cj0 + 16 * c + li) * LDR + k0 + lk];
                     if constexpr (MODE == MODE_F64) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[c], 0, 0, 0);
                     else acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[c], 0, 0, 0);
                 }
             }
         }
+    };
+    // the wave's 16 rows of the tile and the panel's 16-column blocks that
+    // hold window columns
+    const bool rows_live = ti * kTile + 16 * wave < kcols;
+    const int cblk = rows_live ? max(0, min(4, (kcols - tj * kTile + 15) / 16)) : 0;
+    auto compute = [&](const TX* L) __attribute__((always_inline)) {
+        switch (cblk) {
+            case 4: products(L, std::integral_constant<int, 4>{}); break;
+            case 3: products(L, std::integral_constant<int, 3>{}); break;
+            case 2: products(L, std::integral_constant<int, 2>{}); break;
+            case 1: products(L, std::integral_constant<int, 1>{}); break;
+            default: break;
+        }
+    };
+    // full stages (r0 + R <= r_end) pipelined; the ragged last one after
+    const int nfull = (int)((r_end - r_begin) / R);
+    if (nfull > 0) {
+#pragma unroll
+        for (int u = 0; u < NLD; ++u) put(Lb[0], u, *reinterpret_cast<const V*>(src[u] + r_begin));
         __syncthreads();
     }
+    for (int st = 0; st < nfull; ++st) {
+        const int b = st & 1;
+        const int64_t rn = r_begin + (int64_t)(st + 1) * R;
+        V nx[NLD];
+        if (st + 1 < nfull) {
+#pragma unroll
+            for (int u = 0; u < NLD; ++u) nx[u] = *reinterpret_cast<const V*>(src[u] + rn);
+        }
+        compute(Lb[b]);
+        if (st + 1 < nfull) {
+#pragma unroll
+            for (int u = 0; u < NLD; ++u) put(Lb[b ^ 1], u, nx[u]);
+        }
+        __syncthreads();
+    }
+    {
+        const int64_t r0 = r_begin + (int64_t)nfull * R;
+        if (r0 < r_end) {
+            TX* L = Lb[nfull & 1];
+#pragma unroll
+            for (int u = 0; u < NLD; ++u) {
+                const int t = threadIdx.x + u * kThreads, q = t % TPC;
+                TX e[PER];
+#pragma unroll
+                for (int i2 = 0; i2 < PER; ++i2) e[i2] = r0 + q * PER + i2 < r_end ? src[u][r0 + i2] : TX(0);
+                if constexpr (PER == 4) put(L, u, V{e[0], e[1], e[2], e[3]});
+                else put(L, u, V{e[0], e[1]});
+            }
+            __syncthreads();
+            compute(L);
+        }
+    }
 
-    double* out = a.partial + ((int64_t)split * gridDim.x + tile) * (kTile * kTile);
+    double* out = a.partial + ((int64_t)split * ntri + tile) * (kTile * kTile);
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
@@ -222,9 +292,12 @@ int gram_full_tiles(int m) {
 }
 
 int gram_full_splits(int m) {
+    // about 512 workgroups; a multiple of 8 row splits where there are 8 or
+    // more (one XCD per split, see k_gram_tiles)
     const int ntri = gram_full_tiles(m);
     int s = (512 + ntri - 1) / ntri;
-    return s < 1 ? 1 : (s > 128 ? 128 : s);
+    s = s > 128 ? 128 : s;
+    return s >= 8 ? s / 8 * 8 : (s < 1 ? 1 : s);
 }
 
 hipError_t launch_gram_full(const void* ring, int64_t ld, int64_t n, int m, int slots, int elem_f64,
@@ -245,7 +318,7 @@ hipError_t launch_gram_full(const void* ring, int64_t ld, int64_t n, int m, int 
     a.rows_per_split = ((n + a.nsplit - 1) / a.nsplit + granule - 1) / granule * granule;
     a.partial = partial;
     a.st = st;
-    dim3 grid(ntri, a.nsplit);
+    dim3 grid(ntri * a.nsplit);
     // FP64 data always accumulates in FP64; FP32 data in the stream's precision
     int mode = MODE_F32;
     if (elem_f64 || precision == 3 /*FP64*/) mode = MODE_F64;
