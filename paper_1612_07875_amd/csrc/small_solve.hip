@@ -1256,13 +1256,19 @@ __device__ __forceinline__ void solve_eig_body(const SolveArgs& a) {
         for (int q = 0; q < k; q += 2) {
             const int q1 = q + 1 < k ? q + 1 : q;
             cplx a0 = mkc(0.0), a1 = mkc(0.0), b0 = mkc(0.0), b1 = mkc(0.0);
-            // (rows of Y past k-1 and vrow past k-1 are zero)
+            // (the reads of Y stay under p < k: unconditional, the compiler
+            // hoists them all and the grouped kernel needs more registers
+            // than a retiring projection workgroup frees)
 #pragma unroll
             for (int p = 0; p < kRMax; p += 2) {
-                a0 = a0 + vrow[p] * Y[p + q * LDH];
-                b0 = b0 + vrow[p] * Y[p + q1 * LDH];
-                a1 = a1 + vrow[p + 1] * Y[p + 1 + q * LDH];
-                b1 = b1 + vrow[p + 1] * Y[p + 1 + q1 * LDH];
+                if (p < k) {
+                    a0 = a0 + vrow[p] * Y[p + q * LDH];
+                    b0 = b0 + vrow[p] * Y[p + q1 * LDH];
+                }
+                if (p + 1 < k) {
+                    a1 = a1 + vrow[p + 1] * Y[p + 1 + q * LDH];
+                    b1 = b1 + vrow[p + 1] * Y[p + 1 + q1 * LDH];
+                }
             }
             emit(q, a0 + a1);
             if (q + 1 < k) emit(q + 1, b0 + b1);
