@@ -31,6 +31,35 @@ namespace {
 constexpr int kRMax = 32;         // largest truncation rank handled by k_solve_eig
 constexpr double kEps = DBL_EPSILON;
 
+// acc + sum of fa(k) * fb(k) over k = k0, k0 + step, ... < L, added in that
+// order.  The operands of U consecutive terms are read before their
+// products, so that their memory latencies overlap: a loop that reads,
+// waits and multiplies one term at a time pays a full round trip per term,
+// which the workspace forms of the solves (matrix and coefficients in
+// global memory) cannot afford.  The sum is the plain loop's, bit for bit.
+// U = 1 is the plain loop (the LDS forms: their register count decides
+// whether a solve fits beside a running projection).
+template <int U, typename S, typename FA, typename FB>
+__device__ __forceinline__ S ordered_dot(S acc, int k0, int step, int L, FA fa, FB fb) {
+    int k = k0;
+    if constexpr (U > 1) {
+        for (; k + (U - 1) * step < L; k += U * step) {
+            S x[U], y[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                x[u] = fa(k + u * step);
+                y[u] = fb(k + u * step);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc = acc + mulr(x[u], y[u]);
+        }
+    }
+    for (; k < L; k += step) acc = acc + mulr(fa(k), fb(k));
+    return acc;
+}
+// terms read ahead by the workspace forms: 8 real or 4 complex values
+template <typename S, bool LDS> constexpr int kAhead = LDS ? 1 : (sizeof(S) == sizeof(double) ? 8 : 4);
+
 template <typename S> __device__ __forceinline__ S gram_at(const double* G, int a, int b, int slots);
 template <> __device__ __forceinline__ double gram_at<double>(const double* G, int a, int b, int slots) {
     return G[a + (int64_t)b * slots];
@@ -223,7 +252,7 @@ template <> __device__ __forceinline__ cplx load_s<cplx>(const double* p, int64_
 // s_sig[i]: sigma of eigenvector i (i < m); Vc: eigenvectors by column
 // (leading dimension ld), the first nvec of them valid (nvec >= r_eff);
 // spare1, spare2: M x ld scratch.
-template <typename S, int NT>
+template <typename S, int NT, int AHEAD = 1>
 __device__ void sym_tail(const SolveArgs& a, int ld, S* Vc, S* spare1, S* spare2, double* s_sig, int* s_perm,
                          int nvec, int sweeps, bool converged, int warm) {
     using SC = Scal<S>;
@@ -301,9 +330,9 @@ __device__ void sym_tail(const SolveArgs& a, int ld, S* Vc, S* spare1, S* spare2
     for (int idx = tid; idx < m * k_eff; idx += NT) {
         const int i = idx % m, b = idx / m;
         const int si = slot_of(oldest, i, slots);
-        S acc = SC::zero();
-        for (int j = 0; j < m; ++j)
-            acc = acc + mulr(gram_at<S>(a.G, si, slot_of(oldest, j + 1, slots), slots), Vr[j + (size_t)b * ld]);
+        const S acc = ordered_dot<AHEAD>(SC::zero(), 0, 1, m,
+                                     [&](int j) { return gram_at<S>(a.G, si, slot_of(oldest, j + 1, slots), slots); },
+                                     [&](int j) { return Vr[j + (size_t)b * ld]; });
         T[i + (size_t)b * ld] = acc;
     }
     __syncthreads();
@@ -311,8 +340,8 @@ __device__ void sym_tail(const SolveArgs& a, int ld, S* Vc, S* spare1, S* spare2
     // A~[p][q] = (V_r^* T)[p][q] / (sigma_p sigma_q)
     for (int idx = tid; idx < k_eff * k_eff; idx += NT) {
         const int p = idx % k_eff, q = idx / k_eff;
-        S acc = SC::zero();
-        for (int i = 0; i < m; ++i) acc = acc + mulr(SC::cj(Vr[i + (size_t)p * ld]), T[i + (size_t)q * ld]);
+        const S acc = ordered_dot<AHEAD>(SC::zero(), 0, 1, m, [&](int i) { return SC::cj(Vr[i + (size_t)p * ld]); },
+                                     [&](int i) { return T[i + (size_t)q * ld]; });
         const double sp = s_sig[s_perm[p]], sq = s_sig[s_perm[q]];
         store_s<S>(a.At, p + (int64_t)q * k_eff, acc * (1.0 / (sp * sq)));
     }
@@ -577,7 +606,7 @@ __device__ void solve_sym_body(const SolveArgs& a, int M) {
         spare1 = bufA;
         spare2 = bufQ;
     }
-    sym_tail<S, NT>(a, ld, Vc, spare1, spare2, s_sig, s_perm, m, sweep + (converged ? 1 : 0), converged, warm);
+    sym_tail<S, NT, kAhead<S, LDS>>(a, ld, Vc, spare1, spare2, s_sig, s_perm, m, sweep + (converged ? 1 : 0), converged, warm);
 }
 
 template <typename S, int NT, bool LDS, int PMAX>
@@ -1463,9 +1492,9 @@ __device__ void solve_trid_body(const SolveArgs& a) {
             while (G > 1 && G * L > NT) G >>= 1;
             const int gi = tid / G, gl = tid % G;
             for (int i = gi; i < L; i += NT / G) {
-                S acc = SC::zero();
                 const S* ci = A22 + (size_t)i * ld;
-                for (int k = gl; k < L; k += G) acc = acc + mulr(SC::cj(ci[k]), v[k]);
+                S acc = ordered_dot<kAhead<S, LDS>>(SC::zero(), gl, G, L, [&](int k) { return SC::cj(ci[k]); },
+                                       [&](int k) { return v[k]; });
                 acc = group_sum(acc, G);
                 if (gl == 0) s_p[i] = mulr(tau, acc);
             }
@@ -1486,14 +1515,29 @@ __device__ void solve_trid_body(const SolveArgs& a) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             if (j + 2 < n) householder_col<S>(A, ld, n, j + 1, vnext, s_tau, s_e, s_d);
         } else {
-            const int L1 = L - 1;
-            for (int idx = tid - 64; idx < L1 * L1; idx += NT - 64) {
+            // every element is read before the chunk's writes (no two
+            // iterations touch the same element), so that the reads of a
+            // chunk overlap instead of waiting behind the previous write
+            const int L1 = L - 1, NW = NT - 64;
+            auto upd = [&](int idx, S a) {
                 const int k = 1 + idx % L1, i = 1 + idx / L1;
                 const S vk = v[k], vi = v[i];
                 const S wk = s_p[k] + mulr(c, vk), wi = s_p[i] + mulr(c, vi);
-                S& ak = A22[k + (size_t)i * ld];
-                ak = ak - (mulr(vk, SC::cj(wi)) + mulr(wk, SC::cj(vi)));
+                return a - (mulr(vk, SC::cj(wi)) + mulr(wk, SC::cj(vi)));
+            };
+            auto at = [&](int idx) -> S& { return A22[(1 + idx % L1) + (size_t)(1 + idx / L1) * ld]; };
+            constexpr int U = LDS ? 1 : 4;
+            int idx = tid - 64;
+            if constexpr (U > 1) {
+                for (; idx + (U - 1) * NW < L1 * L1; idx += U * NW) {
+                    S x[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) x[u] = at(idx + u * NW);
+#pragma unroll
+                    for (int u = 0; u < U; ++u) at(idx + u * NW) = upd(idx + u * NW, x[u]);
+                }
             }
+            for (; idx < L1 * L1; idx += NW) at(idx) = upd(idx, at(idx));
         }
         __syncthreads();
     }
@@ -1732,7 +1776,7 @@ __device__ void solve_trid_body(const SolveArgs& a) {
     // eigenvector index k of the tail = selection rank k (columns of Z)
     for (int i = tid; i < n; i += NT) s_perm[i] = i;
     __syncthreads();
-    sym_tail<S, NT>(a, ld, Z, spare1, spare2, s_sig, s_perm, nv, 0, true, 0);
+    sym_tail<S, NT, kAhead<S, LDS>>(a, ld, Z, spare1, spare2, s_sig, s_perm, nv, 0, true, 0);
 }
 
 template <typename S, int NT, bool LDS>
