@@ -40,6 +40,16 @@ template <typename TX> struct Stage;
 template <> struct Stage<float>  { static constexpr int R = 64, PER = 4; using V = float4; };
 template <> struct Stage<double> { static constexpr int R = 32, PER = 2; using V = double2; };
 
+// Entry (i, j) of the block (union column i, new column j) is read by some
+// window the k pushes pass through iff the two columns fit in one window of
+// m + 1 columns (i >= cb + j - m), and, for a pair of new columns, it is the
+// upper entry (i - cb <= j), from which the pair is written.  Entries outside
+// are neither summed nor written: no window ever reads them (a slot that
+// leaves the window has all its Gram entries rewritten when it is reused).
+__device__ __forceinline__ bool block_needed(int i, int j, int cb, int m) {
+    return i >= cb + j - m && (i < cb || i - cb <= j);
+}
+
 template <typename TX>
 __global__ __launch_bounds__(kThreads, 4)
 void k_block_tiles(BlockArgs a) {
@@ -136,8 +146,33 @@ void k_block_tiles(BlockArgs a) {
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lq = lane >> 4;
-    const bool active = 16 * wave < ni;
-    const int nsub = nj16 / 16;
+    const int nsub = nj16 / 16, n16 = ni16 / 16;
+    // Work units: the 16 x 16 tiles (union tile iu of this workgroup's
+    // columns, new subtile c) that hold an entry some window reads.  Unit u
+    // goes to wave u % 8, i.e. to SIMD u % 4, so the four SIMDs' matrix cores
+    // get equal shares; a wave holds at most four (n16 <= 8, nsub <= 4).
+    // Every wave derives the same list (lane l < 16 tests row l of a tile).
+    int my_iu[4] = {0, 0, 0, 0}, my_c[4] = {0, 0, 0, 0}, nmine = 0;
+    {
+        int u = 0;
+        for (int c = 0; c < nsub; ++c)
+            for (int iu = 0; iu < n16; ++iu) {
+                const int ja = 16 * c, jb = min(ja + 15, nj - 1), i = i0 + 16 * iu + lane;
+                bool ok = false;
+                if (lane < 16 && i < U) {
+                    const int jlo = i < cb ? ja : max(ja, i - cb);
+                    const int jhi = min(jb, i - cb + a.m);
+                    ok = jlo <= jhi;
+                }
+                if (__ballot(ok) == 0) continue;
+                if ((u & 7) == wave && nmine < 4) {
+                    my_iu[nmine] = iu;
+                    my_c[nmine] = c;
+                    ++nmine;
+                }
+                ++u;
+            }
+    }
     v4d acc[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = v4d{0, 0, 0, 0};
@@ -148,21 +183,16 @@ void k_block_tiles(BlockArgs a) {
         store(r0);
         __syncthreads();
         if (r0 + R < r_end) load(r0 + R);    // in flight during this step's MFMAs
-        if (active) {
-            const TX* pa = Ls + (16 * wave + li) * LDR + 4 * lq;
 #pragma unroll 1
-            for (int k0 = 0; k0 < R; k0 += 16) {
-                TX av[4];
+        for (int k0 = 0; k0 < R; k0 += 16) {
 #pragma unroll
-                for (int s = 0; s < 4; ++s) av[s] = pa[k0 + s];
+            for (int t = 0; t < 4; ++t) {
+                if (t < nmine) {
+                    const TX* pa = Ls + (16 * my_iu[t] + li) * LDR + 4 * lq + k0;
+                    const TX* pb = Ls + (ni16 + 16 * my_c[t] + li) * LDR + 4 * lq + k0;
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    if (c < nsub) {
-                        const TX* pb = Ls + (ni16 + 16 * c + li) * LDR + 4 * lq + k0;
-#pragma unroll
-                        for (int s = 0; s < 4; ++s)
-                            acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)av[s], (double)pb[s], acc[c], 0, 0, 0);
-                    }
+                    for (int s = 0; s < 4; ++s)
+                        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)pa[s], (double)pb[s], acc[t], 0, 0, 0);
                 }
             }
         }
@@ -170,16 +200,14 @@ void k_block_tiles(BlockArgs a) {
 
     // partial[split][i * kmax + j] for union column i, new column j
     double* out = a.partial + (int64_t)split * (a.slots * a.kmax);
-    if (active) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            if (c >= nsub) break;
+    for (int t = 0; t < 4; ++t) {
+        if (t >= nmine) break;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int i = 16 * wave + lq + 4 * v;
-                const int j = 16 * c + li;
-                if (i < ni && j < nj) out[(int64_t)(i0 + i) * a.kmax + j] = acc[c][v];
-            }
+        for (int v = 0; v < 4; ++v) {
+            const int i = 16 * my_iu[t] + lq + 4 * v;
+            const int j = 16 * my_c[t] + li;
+            if (i < ni && j < nj) out[(int64_t)(i0 + i) * a.kmax + j] = acc[t][v];
         }
     }
 }
@@ -188,11 +216,11 @@ void k_block_tiles(BlockArgs a) {
 // c + 32, ...; chunks in index order), write the block, flag non-finite sums.
 __global__ __launch_bounds__(kRedElems * kRedChunks)
 void k_block_reduce(BlockArgs a) {
-    const int U = a.st->count + a.k;
+    const int cb = a.st->count, U = cb + a.k;
     const int el = threadIdx.x % kRedElems, ch = threadIdx.x / kRedElems;
     const int e = blockIdx.x * kRedElems + el;
     const int i = e / a.kmax, j = e % a.kmax;
-    const bool valid = i < U && j < a.k;
+    const bool valid = i < U && j < a.k && block_needed(i, j, cb, a.m);
     const int64_t estride = (int64_t)a.slots * a.kmax;
     double s = 0.0;
     if (valid)
@@ -247,7 +275,7 @@ void k_block_commit(BlockArgs a) {
     }
     for (int e = threadIdx.x; e < U * k; e += blockDim.x) {
         const int i = e / k, j = e % k;
-        if (i >= cb && i - cb > j) continue;  // a pair of new columns is written from its upper entry
+        if (!block_needed(i, j, cb, m)) continue;  // never read (a pair of new columns: from its upper entry)
         const double v = a.gblock[i * a.kmax + j];
         const int si = slot_of(ob, i, slots), sj = slot_of(ob, cb + j, slots);
         a.G[si + (int64_t)sj * slots] = v;
