@@ -243,31 +243,38 @@ def serve_bench(args):
     torch.cuda.synchronize()
     print(f"[serve] generated frame pools for {len(mix)} streams in {time.perf_counter() - t_gen:.1f} s",
           file=sys.stderr, flush=True)
-    ex_gpu = GPUExecutor(frames)
-    srv = Server(ex_gpu)
-    for s in mix:
-        srv.open(s.stream, StreamSpec(s.n, s.m, s.r))
-    # fill every window (backlogged burst), untimed
-    fill = sorted((0.0, s.stream) for s in mix for _ in range(s.m + 1))
-    srv.run(fill)
-    srv.records.clear()
-    srv.batch_sizes.clear()
-    srv.ticks = 0
-    print("[serve] windows filled", file=sys.stderr, flush=True)
-    # Poisson arrivals at the target rate
     times, sids = poisson_arrivals(len(mix), args.serve_rate, args.serve_seconds)
     arrivals = [(float(t), mix[int(k)].stream) for t, k in zip(times, sids)]
-    st = srv.run(arrivals)
-    print(f"[serve] poisson run: {st.frames} frames in {st.elapsed:.1f} s", file=sys.stderr, flush=True)
-    # saturation: every stream backlogged
-    srv.records.clear()
-    srv.batch_sizes.clear()
-    srv.ticks = 0
-    sat_frames = 8
-    burst = sorted((0.0, s.stream) for s in mix for _ in range(sat_frames))
-    sat = srv.run(burst)
-    ex_gpu.shutdown()
-    torch.cuda.synchronize()
+
+    def serving(lane_split, max_inflight=1):
+        ex_gpu = GPUExecutor(frames, lane_split=lane_split)
+        srv = Server(ex_gpu, max_inflight=max_inflight)
+        for s in mix:
+            srv.open(s.stream, StreamSpec(s.n, s.m, s.r))
+        # fill every window (backlogged burst), untimed
+        srv.run(sorted((0.0, s.stream) for s in mix for _ in range(s.m + 1)))
+        srv.records.clear()
+        srv.batch_sizes.clear()
+        srv.ticks = 0
+        # Poisson arrivals at the target rate
+        st = srv.run(arrivals)
+        print(f"[serve] lanes split at m = {lane_split}, ticks in flight per lane {max_inflight}: poisson run, "
+              f"{st.frames} frames in {st.elapsed:.1f} s, p50 {st.p50_ms:.2f} ms, p99 {st.p99_ms:.2f} ms, "
+              f"mean batch {st.mean_batch:.2f}", file=sys.stderr, flush=True)
+        # saturation: every stream backlogged
+        srv.records.clear()
+        srv.batch_sizes.clear()
+        srv.ticks = 0
+        sat = srv.run(sorted((0.0, s.stream) for s in mix for _ in range(8)))
+        ex_gpu.shutdown()
+        torch.cuda.synchronize()
+        return st, sat
+
+    print("[serve] frames resident", file=sys.stderr, flush=True)
+    st, sat = serving((32, 64), 1)
+    st3, sat3 = serving((32, 64), None)
+    st2, sat2 = serving(64, None)
+    st1, sat1 = serving(None, None)
     modes_cmp = None if args.no_split else modes_saturation(mix, frames, GPUExecutor, Server, StreamSpec)
     footprint = sum((s.m + 2) * s.n * 4 for s in mix)
     out = {
@@ -281,12 +288,32 @@ def serve_bench(args):
                                f"m in {{16,32,64,128}}, r = min(m/2, 32), blob video / travelling waves; "
                                f"Poisson arrivals {args.serve_rate:.0f} frames/s for {args.serve_seconds:.0f} s; "
                                f"each update = Gram column + FP64 solves (no modes; modes_saturation "
-                               f"adds them)",
+                               f"adds them); three lanes (m <= 32, m = 64, m = 128), each with its own "
+                               f"batch and HIP stream, one tick in flight per lane",
                    "streams": len(mix), "ring_bytes": footprint},
         "latency_ms": {"p50": round(st.p50_ms, 3), "p99": round(st.p99_ms, 3), "max": round(st.max_ms, 3)},
         "mean_batch": round(st.mean_batch, 2), "ticks": st.ticks,
         "saturation": {"updates_per_s": round(sat.updates_per_s, 1), "frames": sat.frames,
                        "mean_batch": round(sat.mean_batch, 2), "p99_ms": round(sat.p99_ms, 2)},
+        "three_lanes_unlimited": {"note": "the same arrivals and lanes, with no limit on the ticks in flight",
+                                  "updates_per_s": round(st3.updates_per_s, 2),
+                                  "latency_ms": {"p50": round(st3.p50_ms, 3), "p99": round(st3.p99_ms, 3),
+                                                 "max": round(st3.max_ms, 3)},
+                                  "mean_batch": round(st3.mean_batch, 2),
+                                  "saturation_updates_per_s": round(sat3.updates_per_s, 1)},
+        "two_lanes": {"note": "the same arrivals in two lanes (m <= 64, m = 128), no limit on the ticks in flight",
+                      "updates_per_s": round(st2.updates_per_s, 2),
+                      "latency_ms": {"p50": round(st2.p50_ms, 3), "p99": round(st2.p99_ms, 3),
+                                     "max": round(st2.max_ms, 3)},
+                      "mean_batch": round(st2.mean_batch, 2),
+                      "saturation_updates_per_s": round(sat2.updates_per_s, 1)},
+        "one_lane": {"note": "the same arrivals with every stream in one batch on one HIP stream, no limit "
+                             "on the ticks in flight",
+                     "updates_per_s": round(st1.updates_per_s, 2),
+                     "latency_ms": {"p50": round(st1.p50_ms, 3), "p99": round(st1.p99_ms, 3),
+                                    "max": round(st1.max_ms, 3)},
+                     "mean_batch": round(st1.mean_batch, 2),
+                     "saturation_updates_per_s": round(sat1.updates_per_s, 1)},
     }
     if modes_cmp is not None:
         out["modes_saturation"] = modes_cmp

@@ -25,7 +25,10 @@ def _dmd():
     return dmd
 
 
-def test_served_equals_alone_with_admission_queue():
+# lane_split (8, 12): streams with m <= 8, 8 < m <= 12 and m > 12 tick in three
+# lanes (each a batch and a HIP stream of its own) that run side by side
+@pytest.mark.parametrize("lane_split", [None, (8, 12)])
+def test_served_equals_alone_with_admission_queue(lane_split):
     dmd = _dmd()
     from paper_1612_07875_amd.serve import GPUExecutor, Server, StreamSpec, stream_footprint
     from test_gpu_batch import eig_bound
@@ -42,7 +45,8 @@ def test_served_equals_alone_with_admission_queue():
         foot.append(stream_footprint(StreamSpec(n, m, r), True, dmd.footprint))
         assert foot[-1] == dmd.footprint(n, m, r) + 8 * n * r
     budget = sum(foot[:4]) + 1024
-    ex = GPUExecutor(frames, hbm_budget=budget, modes=True)
+    ex = GPUExecutor(frames, hbm_budget=budget, modes=True, lane_split=lane_split)
+    assert len({ex._lane_of(StreamSpec(n, m, r)) for n, m, r in SPECS}) == (3 if lane_split else 1)
     srv = Server(ex)
     admitted = [srv.open(sid, StreamSpec(n, m, r)) for sid, (n, m, r) in enumerate(SPECS)]
     assert admitted == [True, True, True, True, False, False]
