@@ -821,18 +821,28 @@ def bench_sparse(args):
         s.close()
         return el, kern, int(lam.size)
 
-    def batched_leg(B):
+    def batched_leg(B, L=1):
         # B streams of the same shape, stream b fed the frames from b on (distinct
-        # windows); one step = one tick that pushes a frame into every stream
-        # and writes every stream's modes
+        # windows), in L lanes (batches of B / L streams, each ticking on a HIP
+        # stream of its own); one step = one tick per lane, which pushes a frame
+        # into every stream of the lane and writes every stream's modes
         streams = [dmd.Stream(n, m, r, dtype="c64_csr", max_nnz=nnz) for _ in range(B)]
         outs = [torch.zeros((r, n), dtype=torch.complex64, device="cuda").T for _ in range(B)]
-        with dmd.Batch(max_streams=B) as batch:
-            for st in streams:
-                batch.attach(st)
+        lanes = [list(range(q, B, L)) for q in range(L)]
+        queues = [torch.cuda.Stream() for _ in range(L)]
+        for q in queues:
+            q.wait_stream(torch.cuda.current_stream())
+        batches = [dmd.Batch(max_streams=B) for _ in range(L)]
+        try:
+            for lane, batch in zip(lanes, batches):
+                for b in lane:
+                    batch.attach(streams[b])
 
             def tick(t):
-                batch.tick_frames(streams, [(idx[(t + b) % T], val[(t + b) % T]) for b in range(B)], modes=outs)
+                for lane, batch, q in zip(lanes, batches, queues):
+                    batch.tick_frames([streams[b] for b in lane],
+                                      [(idx[(t + b) % T], val[(t + b) % T]) for b in lane],
+                                      modes=[outs[b] for b in lane], stream=q)
 
             for t in range(m + 1 + Wu):
                 tick(t)
@@ -847,6 +857,9 @@ def bench_sparse(args):
             dmd.profile_enable(False)
             kern_b = kernel_table(dmd, ("batch_gram", "batch_solve", "batch_project"))
             dmd.profile_reset()
+        finally:
+            for batch in batches:
+                batch.close()
         r_effs = [int(st.eigs()[0].size) for st in streams]
         for st in streams:
             st.close()
@@ -857,6 +870,8 @@ def bench_sparse(args):
     el_f, kern_f, r_eff_f = leg("fourier", ("fourier",) + names)
     B = args.sparse_streams
     el_b, kern_b, r_effs_b = batched_leg(B) if B > 0 else (None, None, None)
+    BL, LL = 3 * B, 3
+    el_l, kern_l, r_effs_l = batched_leg(BL, LL) if B > 0 else (None, None, None)
     # the sparse Gram pass reads the window's coefficients once: (m+1) nnz (4 + 8) bytes
     roofline = roofline_of(kern, {"csr_gram": (m + 1) * nnz * 12}, {"csr_gram": "csr.hip"})
     out = result_line(K / el, K, Wu, el, "c64", {
@@ -880,6 +895,11 @@ def bench_sparse(args):
             "workload": f"{B} sparse streams of the same shape, one dmd_batch_tick_frames per step (a frame "
                         "into every stream, grouped Hermitian solves, every stream's modes)",
             "kernels": kern_b}
+        out["batched_lanes"] = {
+            "value": round(BL * K / el_l, 2), "unit": "window updates/s", "streams": BL, "lanes": LL,
+            "ms_per_step": round(1000.0 * el_l / K, 4), "r_eff": sorted(set(r_effs_l)),
+            "workload": f"{BL} sparse streams in {LL} lanes of {BL // LL} (a batch on a HIP stream of its own "
+                        "each); one step = one tick per lane"}
     return out, None
 
 
