@@ -156,11 +156,21 @@ struct SolveArgs {
     char* res_block;       // device results block (state, sigma, lambda)
     char* res_host;        // device address of its pinned host mirror
     int res_bytes;         // size of the results block
+    // single-window eig solve only (may be null): after the solve, copy the
+    // state to snap_st and snap_n16 x 16 bytes of Bphi to snap_B (the
+    // snapshot a later projection of this solve reads)
+    DevState* snap_st;
+    void* snap_B;
+    int snap_n16;
 };
 hipError_t launch_solve_sym(const SolveArgs& a, hipStream_t s);
 // Same outputs by Householder tridiagonalization, multisection and twisted
 // factorizations (no warm start).
 hipError_t launch_solve_trid(const SolveArgs& a, hipStream_t s);
+// The finalize of a dense push's Gram pass (launch_gram_finalize) and the
+// real tridiagonal solve of the new window as one launch.
+hipError_t launch_finalize_solve_trid(double* G, const double* partials, int nblk, const SolveArgs& a,
+                                      hipStream_t s);
 // Grouped real symmetric solves (one workgroup per item; lds: m <= 64) by
 // Jacobi or by the tridiagonal method, and the grouped eig of A~.
 hipError_t launch_jacobi_grouped(const SolveArgs* items_lds, int n_lds, const SolveArgs* items_glb, int n_glb,
@@ -220,10 +230,6 @@ struct ProjectArgs {
     int buildup;           // partial windows (window_cols): X_sub has window_cols columns
 };
 hipError_t launch_project(const ProjectArgs& a, hipStream_t s);
-// Copies a solve's state and its mode coefficients (bytes, a multiple of 16)
-// into a snapshot that later projections read.
-hipError_t launch_snapshot(const DevState* st, DevState* st_out, const void* B, void* B_out, size_t bytes,
-                           hipStream_t s);
 // Grouped FP32 projections of many streams in one launch.
 hipError_t launch_project_grouped(const ProjectArgs* items, const int* blk_start, int nitems, int total_blocks,
                                   hipStream_t s);

@@ -447,21 +447,30 @@ void fill_project_args(const dmd_stream* h, dmd::ProjectArgs& a, void* out, int6
     a.buildup = h->opts.buildup;
 }
 
-int enqueue_solve(dmd_stream* h, hipStream_t s) {
+// The solves of the current window.  sym_done: the symmetric solve already
+// ran, fused with the push's Gram finalize (dmd_stream_push).  The eig solve
+// also leaves the snapshot of the solve (state and mode coefficients, parity
+// snap_seq & 1) that dmd_stream_modes projects from.
+int enqueue_solve(dmd_stream* h, hipStream_t s, bool sym_done = false) {
     h->last_block_k = 0;
     h->last_packed = -1;
     h->snap_par = -1;
     dmd::SolveArgs a;
     fill_solve_args(h, a);
-    HIP_TRY(timed("solve_sym", s, [&] {
-        return h->use_trid ? dmd::launch_solve_trid(a, s) : dmd::launch_solve_sym(a, s);
-    }));
-    HIP_TRY(timed("solve_eig", s, [&] { return dmd::launch_solve_eig(a, s); }));
+    if (!sym_done)
+        HIP_TRY(timed("solve_sym", s, [&] {
+            return h->use_trid ? dmd::launch_solve_trid(a, s) : dmd::launch_solve_sym(a, s);
+        }));
+    int par = -1;
     if (h->snap_st) {
         // every caller has waited for the modes of the solve before last (this parity)
-        const int par = (int)(h->snap_seq & 1);
-        HIP_TRY(dmd::launch_snapshot(reinterpret_cast<const DevState*>(h->res_dev), h->snap_st + par, h->Bphi,
-                                     h->snap_B + par * h->snap_B_bytes, h->snap_B_bytes, s));
+        par = (int)(h->snap_seq & 1);
+        a.snap_st = h->snap_st + par;
+        a.snap_B = h->snap_B + par * h->snap_B_bytes;
+        a.snap_n16 = (int)(h->snap_B_bytes / 16);
+    }
+    HIP_TRY(timed("solve_eig", s, [&] { return dmd::launch_solve_eig(a, s); }));
+    if (par >= 0) {
         h->snap_par = par;
         ++h->snap_seq;
     }
@@ -835,15 +844,22 @@ DMD_API int dmd_stream_push(dmd_stream_t* h, const void* x, void* stream) {
                                                h->n, h->m, h->slots, h->partials, h->nblk_cap, st, h->gram_iter,
                                                &nblk, s);
     });
-    if (e == hipSuccess)
+    // with the tridiagonal solver the finalize and the solve are one launch
+    const bool fuse = h->opts.auto_solve && h->use_trid;
+    if (e == hipSuccess && !fuse)
         e = timed("gram_finalize", s,
                   [&] { return dmd::launch_gram_finalize(h->G, h->partials, nblk, h->m, h->slots, st, s); });
+    if (e == hipSuccess && fuse) {
+        dmd::SolveArgs a;
+        fill_solve_args(h, a);
+        e = timed("solve_sym", s, [&] { return dmd::launch_finalize_solve_trid(h->G, h->partials, nblk, a, s); });
+    }
     if (e != hipSuccess) return hip_fail(e, "gram push launch");
     h->last_block_k = 0;
     h->last_packed = -1;
     h->snap_par = -1;
     if (h->opts.auto_solve)
-        if (int rc = enqueue_solve(h, s)) return rc;
+        if (int rc = enqueue_solve(h, s, fuse)) return rc;
     HIP_TRY(end(h, s));
     return DMD_OK;
 }

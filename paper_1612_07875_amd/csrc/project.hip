@@ -1485,25 +1485,6 @@ hipError_t launch_project_grouped(const ProjectArgs* items, const int* blk_start
     return hipGetLastError();
 }
 
-namespace {
-__global__ __launch_bounds__(256)
-void k_snapshot(const DevState* __restrict__ st, DevState* __restrict__ st_out, const uint4* __restrict__ B,
-                uint4* __restrict__ B_out, int n16) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += gridDim.x * blockDim.x) B_out[i] = B[i];
-    if (blockIdx.x == 0 && threadIdx.x == 0) *st_out = *st;
-}
-}  // namespace
-
-hipError_t launch_snapshot(const DevState* st, DevState* st_out, const void* B, void* B_out, size_t bytes,
-                           hipStream_t s) {
-    if (bytes % 16) return hipErrorInvalidValue;
-    const int n16 = (int)(bytes / 16);
-    const int blocks = n16 / 256 + 1 < 64 ? n16 / 256 + 1 : 64;
-    hipLaunchKernelGGL(k_snapshot, dim3(blocks), dim3(256), 0, s, st, st_out, static_cast<const uint4*>(B),
-                       static_cast<uint4*>(B_out), n16);
-    return hipGetLastError();
-}
-
 hipError_t launch_project(const ProjectArgs& a, hipStream_t s) {
     const int kc_max = a.cplx_out ? 2 * a.kmax : a.kmax;
     if (kc_max > 64) return hipErrorInvalidValue;

@@ -24,6 +24,7 @@
 
 #include "cplx.h"
 #include "dmd_internal.h"
+#include "gram_finalize.h"
 
 namespace dmd {
 namespace {
@@ -1314,6 +1315,15 @@ __device__ __forceinline__ void solve_eig_body(const SolveArgs& a) {
 __global__ __launch_bounds__(64)
 void k_solve_eig(SolveArgs a) {
     solve_eig_body(a);
+    if (a.snap_st) {
+        // the snapshot of this solve (state and mode coefficients) for the
+        // projections that may run beside the next push
+        __syncthreads();
+        const uint4* B = static_cast<const uint4*>(a.Bphi);
+        uint4* out = static_cast<uint4*>(a.snap_B);
+        for (int i = threadIdx.x; i < a.snap_n16; i += blockDim.x) out[i] = B[i];
+        if (threadIdx.x == 0) *a.snap_st = *a.st;
+    }
 }
 
 __global__ __launch_bounds__(64)
@@ -1785,6 +1795,19 @@ void k_solve_trid(SolveArgs a) {
     solve_trid_body<S, NT, LDS>(a);
 }
 
+// A dense push's Gram finalize (1024 threads, as its own kernel) followed by
+// the tridiagonal solve of the window it completes, in one launch: one
+// kernel boundary fewer on the single-push step.  A rejected snapshot leaves
+// the state as it was, and the solve then finds nothing new (skipped), as
+// after the two separate launches.
+template <bool LDS>
+__global__ __launch_bounds__(1024)
+void k_finalize_solve_trid(double* G, const double* partials, int nblk, SolveArgs a) {
+    gram_finalize_body(G, partials, nblk, a.m, a.slots, a.st);
+    __syncthreads();
+    solve_trid_body<double, 1024, LDS>(a);
+}
+
 template <typename S, int NT, bool LDS>
 __global__ __launch_bounds__(NT)
 void k_solve_trid_grouped(const SolveArgs* __restrict__ items) {
@@ -1829,6 +1852,22 @@ hipError_t launch_solve_trid(const SolveArgs& a, hipStream_t s) {
     if (a.r > kRMax || a.m > kMaxM) return hipErrorInvalidValue;
     if (a.cplx) return a.m <= 32 ? launch_trid_one<cplx, true>(a, s) : launch_trid_one<cplx, false>(a, s);
     return a.m <= 64 ? launch_trid_one<double, true>(a, s) : launch_trid_one<double, false>(a, s);
+}
+
+hipError_t launch_finalize_solve_trid(double* G, const double* partials, int nblk, const SolveArgs& a,
+                                      hipStream_t s) {
+    if (a.r > kRMax || a.m > kMaxM || a.cplx) return hipErrorInvalidValue;
+    const int n = a.m, nv = a.r < n ? a.r : n;
+    const bool lds_form = a.m <= 64;
+    size_t lds = sizeof(double) * 2 * (size_t)n * nv;
+    if (lds_form) lds += sizeof(double) * (size_t)n * (n + 1);
+    const void* kern = lds_form ? reinterpret_cast<const void*>(k_finalize_solve_trid<true>)
+                                : reinterpret_cast<const void*>(k_finalize_solve_trid<false>);
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (lds_form) hipLaunchKernelGGL(k_finalize_solve_trid<true>, dim3(1), dim3(1024), lds, s, G, partials, nblk, a);
+    else hipLaunchKernelGGL(k_finalize_solve_trid<false>, dim3(1), dim3(1024), lds, s, G, partials, nblk, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_solve_eig(const SolveArgs& a, hipStream_t s) {
