@@ -1283,6 +1283,198 @@ void k_project_band_s(BlockProjectArgs a, int64_t slab0) {
     }
 }
 
+// The banded product on v_mfma_f32_16x16x4f32 (the form run wherever one of
+// its fixed-step instances applies).  Same 32-column tiles, windows and
+// stores as above, but each step covers 4 staged columns with 16 products
+// (8 row tiles of 16 x 2 column tiles of 16) instead of 2 columns with 4
+// products of 32 x 32: the 16 x 16 products keep the matrix cores busier
+// (a probe of the products alone sustains 155-157 TFLOP/s against 129 for
+// 32 x 32 products rotating over four accumulators).  Lane l holds
+// A[l % 16][l / 16] (row, staged column), B[l / 16][l % 16] (staged column,
+// output column) and D[4 (l / 16) + v][l % 16]; one swap with the neighbouring
+// lane gives each lane two whole complex rows, and one store instruction
+// writes 16 rows of 8 complex columns (128-byte runs).
+constexpr int kBand16LDR = kBandRows + 16;  // 576-byte stride: the 4 columns a step reads on distinct banks
+// packed values per lane and tile: steps x 2 column tiles, in 16-byte groups
+__host__ __device__ inline int band16_nq(int S4) { return (2 * S4 + 3) / 4; }
+// a tile from window w_lo reads columns w_lo .. w_lo + 4 S4 - 1 and one step ahead
+__host__ __device__ inline int band16_stage_cols(int m, int k, int S4) {
+    const int need = k + 4 * S4 + 3;
+    return need > m + k - 1 ? need : m + k - 1;
+}
+__host__ __device__ inline int band16_max_steps(int m, int r, int k) {
+    int smax = 0;
+    const int r2 = 2 * r;
+    for (int t = 0; t < band_tiles(r, k); ++t) {
+        const int wl = 32 * t / r2, wh = min((32 * t + 31) / r2, k - 1);
+        const int st = (m + wh - wl + 3) / 4;
+        smax = st > smax ? st : smax;
+    }
+    return smax;
+}
+
+// Packs tile t = blockIdx.x: lane l's values, in the order 2 s + ct, are
+// B[w_lo + 4 s + l / 16][32 t + 16 ct + l % 16] (zero outside the window's
+// rows and rank).  Also fills the block descriptor (ring position, ranks).
+template <int S4>
+__global__ __launch_bounds__(64)
+void k_pack_band16(BlockProjectArgs a) {
+    constexpr int NQ = (2 * S4 + 3) / 4;
+    const int lane = threadIdx.x, t = blockIdx.x;
+    const int k = a.k, m = a.m, r2 = 2 * a.r;
+    if (t == 0) {
+        for (int w = lane; w < k; w += 64) {
+            int kc = 0;
+            window_coef(a, w, kc);
+            a.desc->kc[w] = kc;
+        }
+        if (lane == 0) {
+            a.desc->valid = a.st->count >= a.m + 1 && !a.st->block_rejected;
+            a.desc->base = a.st->oldest + 2 - k + a.slots;
+        }
+    }
+    const int wlo = 32 * t / r2;
+    const int lr = lane & 15, lk = lane >> 4;
+    float y[4 * NQ];
+#pragma unroll
+    for (int j = 0; j < 4 * NQ; ++j) y[j] = 0.0f;
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+        const int g = 32 * t + 16 * ct + lr;
+        const int w = g / r2, c = g % r2;
+        int kc = 0;
+        const float* B = w < k ? window_coef(a, w, kc) : nullptr;
+#pragma unroll
+        for (int st = 0; st < S4; ++st) {
+            const int i = wlo + 4 * st + lk - w;  // row of C_w
+            y[2 * st + ct] = (w < k && c < kc && i >= 0 && i < m) ? B[(int64_t)i * r2 + c] : 0.0f;
+        }
+    }
+    uint4* out = a.cfrag + (size_t)t * NQ * 64 + lane;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+        out[(size_t)q * 64] = uint4{__builtin_bit_cast(unsigned, y[4 * q]), __builtin_bit_cast(unsigned, y[4 * q + 1]),
+                                    __builtin_bit_cast(unsigned, y[4 * q + 2]), __builtin_bit_cast(unsigned, y[4 * q + 3])};
+}
+
+// FULL as in k_project_band_s; S4 steps of 4 staged columns per tile (a
+// shorter tile meets zero coefficients), every tile computed, stores that
+// always issue.
+template <int S4, bool FULL>
+__global__ __launch_bounds__(kThreads, 2)
+void k_project_band16_s(BlockProjectArgs a, int64_t slab0) {
+    constexpr int NQ = (2 * S4 + 3) / 4;
+    extern __shared__ float dynp[];
+    const BlockDesc* desc = a.desc;
+    if (!desc->valid) return;
+    const int m = a.m, k = a.k, r2 = 2 * a.r;
+    const int ncols = m + k - 1, nstage = band16_stage_cols(m, k, S4);
+    const int ntile = band_tiles(a.r, k);
+    float* U = dynp;
+    const int64_t row0 = (slab0 + blockIdx.x) * kBandRows;
+    const int base = desc->base;
+    const float* ring = static_cast<const float*>(a.ring);
+    __shared__ int s_kc[64];
+    if (threadIdx.x < 64) s_kc[threadIdx.x] = threadIdx.x < k ? desc->kc[threadIdx.x] : 0;
+    stage_columns<kBandRows>(ring, a.ld, a.slots, base, ncols, nstage, row0,
+                             [&](int c, int r4, float4 x) { *reinterpret_cast<float4*>(&U[c * kBand16LDR + r4]) = x; });
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const bool odd = lr & 1;
+    const uint4* cf = a.cfrag + lane;
+    auto load_a = [&](int c, float (&av)[8]) {
+        const float* u = U + (c + lk) * kBand16LDR + lr;
+#pragma unroll
+        for (int rt = 0; rt < 8; ++rt) av[rt] = u[16 * rt];
+    };
+    auto load_b = [&](int t, uint4 (&b)[NQ]) {
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) b[i] = cf[(size_t)(t * NQ + i) * 64];
+    };
+    auto bval = [](const uint4 (&b)[NQ], int j) {
+        const uint4& u = b[j / 4];
+        const unsigned bits = (j & 3) == 0 ? u.x : (j & 3) == 1 ? u.y : (j & 3) == 2 ? u.z : u.w;
+        return __builtin_bit_cast(float, bits);
+    };
+    auto tile = [&](int t, const uint4 (&b)[NQ]) {
+        const int g0 = 32 * t;
+        const int wlo = __builtin_amdgcn_readfirstlane(g0 / r2);
+        v4f acc[2][8];
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int rt = 0; rt < 8; ++rt) acc[ct][rt] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+        int c = wlo;
+        float av[8];
+        load_a(c, av);
+#pragma unroll
+        for (int st = 0; st < S4; ++st) {
+            float an[8];
+            load_a(c + 4, an);  // the next step's A fragments ahead of the products
+            __builtin_amdgcn_sched_barrier(0);
+            const float b0 = bval(b, 2 * st), b1 = bval(b, 2 * st + 1);
+#pragma unroll
+            for (int rt = 0; rt < 8; ++rt)
+                acc[0][rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rt], b0, acc[0][rt], 0, 0, 0);
+#pragma unroll
+            for (int rt = 0; rt < 8; ++rt)
+                acc[1][rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rt], b1, acc[1][rt], 0, 0, 0);
+#pragma unroll
+            for (int rt = 0; rt < 8; ++rt) av[rt] = an[rt];
+            c += 4;
+        }
+        v4f* sink = reinterpret_cast<v4f*>(a.desc->sink) + lane;
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+            // this lane pair's complex column: real column g, imaginary g + 1
+            const int g = g0 + 16 * ct + (lr & ~1);
+            const int w = g / r2, cc = g % r2;
+            const int ws = w < k ? w : 0;
+            const bool ok = w < k && cc < s_kc[ws];
+            float2* o = a.out + (int64_t)ws * a.ldw + (int64_t)(cc >> 1) * a.ldo;
+#pragma unroll
+            for (int rt = 0; rt < 8; ++rt) {
+                const v4f d = acc[ct][rt];
+                const float x = odd ? d[0] : d[2], y = odd ? d[1] : d[3];
+                const float xs = swap_pair(x), ys = swap_pair(y);
+                const float4 val = odd ? float4{xs, d[2], ys, d[3]} : float4{d[0], xs, d[1], ys};
+                const int64_t row = row0 + 16 * rt + 4 * lk + (odd ? 2 : 0);
+                float2* q = o + row;
+                if constexpr (FULL) {
+                    v4f* dst = ok ? reinterpret_cast<v4f*>(q) : sink;
+                    __builtin_nontemporal_store(v4f{val.x, val.y, val.z, val.w}, dst);
+                } else if (ok && row < a.n) {
+                    q[0] = float2{val.x, val.y};
+                    if (row + 1 < a.n) q[1] = float2{val.z, val.w};
+                }
+            }
+        }
+    };
+    constexpr int T4 = kThreads / 64;
+    uint4 bA[NQ], bB[NQ];
+    auto ahead = [&](int t) { return t + T4 < ntile ? t + T4 : ntile - 1; };
+    int t = wave;
+    if (t >= ntile) return;
+    load_b(t, bA);
+    load_b(ahead(t), bB);
+    __builtin_amdgcn_sched_barrier(0);
+    tile(t, bA);
+    t += T4;
+    while (t < ntile) {
+        load_b(ahead(t), bA);
+        __builtin_amdgcn_sched_barrier(0);
+        tile(t, bB);
+        t += T4;
+        if (t >= ntile) break;
+        load_b(ahead(t), bB);
+        __builtin_amdgcn_sched_barrier(0);
+        tile(t, bA);
+        t += T4;
+    }
+}
+
 size_t block_lds(int m, int k) { return sizeof(float) * (size_t)(k - 1 + 32 * ((m + 31) / 32)) * kBlkLDR; }
 
 template <int NT>
@@ -1301,14 +1493,30 @@ hipError_t launch_block_nt(const BlockProjectArgs& a, hipStream_t s) {
 
 }  // namespace
 
+// Fixed-step instances of the 16 x 16 banded kernel (4 staged columns a
+// step), and the instance for these sizes: the longest tile's steps rounded
+// up by at most one, its stage within the LDS budget; 0 if none applies.
+constexpr int kBand16Steps[] = {5, 9, 13, 17};
+constexpr int kBand16NSteps = sizeof(kBand16Steps) / sizeof(kBand16Steps[0]);
+int band16_fixed_steps(int m, int r, int k) {
+    const int smax = band16_max_steps(m, r, k);
+    for (int S4 : kBand16Steps)
+        if (smax <= S4 && S4 - smax <= 1 &&
+            sizeof(float) * (size_t)band16_stage_cols(m, k, S4) * kBand16LDR <= kBlockLdsMax)
+            return S4;
+    return 0;
+}
+
 size_t project_block_frag_bytes(int m, int r, int kmax) {
     const PairShape ps = pair_shape(m);
     const size_t per_window = (size_t)kmax * ((m + 31) / 32) * 4 * 64 * 32;
     const size_t pairs =
         (size_t)((kmax + 1) / 2) * (8 * ps.nfull + ps.tail) * kPairMaxTilesTuned * 64 * sizeof(float);
     const size_t band = (size_t)band_tiles(r, kmax) * band_chunks(m, r) * 64 * 32;
+    const size_t band16 = (size_t)band_tiles(r, kmax) * band16_nq(kBand16Steps[kBand16NSteps - 1]) * 64 * 16;
     size_t b = per_window > pairs ? per_window : pairs;
-    return b > band ? b : band;
+    b = b > band ? b : band;
+    return b > band16 ? b : band16;
 }
 
 bool project_block_fits(int m, int k, int r) {
@@ -1358,8 +1566,51 @@ int block_rule_form(int m, int r, int k) {
     return use_band(a) ? 3 : use_pairs(a) ? 2 : 1;
 }
 
+hipError_t launch_band16(const BlockProjectArgs& a, hipStream_t s, bool pack, int S4) {
+    const int ntile = band_tiles(a.r, a.k);
+    const void* pk = nullptr;
+    const void* full = nullptr;
+    const void* part = nullptr;
+#define DMD_BAND16_S(N)                                                                          \
+    if (S4 == N) {                                                                               \
+        pk = reinterpret_cast<const void*>(k_pack_band16<N>);                                    \
+        full = reinterpret_cast<const void*>(k_project_band16_s<N, true>);                       \
+        part = reinterpret_cast<const void*>(k_project_band16_s<N, false>);                      \
+    }
+    DMD_BAND16_S(5)
+    DMD_BAND16_S(9)
+    DMD_BAND16_S(13)
+    DMD_BAND16_S(17)
+#undef DMD_BAND16_S
+    if (!pk) return hipErrorInvalidValue;
+    if (pack) {
+        void* args[] = {const_cast<BlockProjectArgs*>(&a)};
+        return hipLaunchKernel(pk, dim3((unsigned)ntile), dim3(64), args, 0, s);
+    }
+    const size_t lds = sizeof(float) * (size_t)band16_stage_cols(a.m, a.k, S4) * kBand16LDR;
+    const int64_t nslab = (a.n + kBandRows - 1) / kBandRows;
+    // whole slabs with 16-byte stores in one launch, the rest in another
+    const int64_t nfull = a.out16 ? a.n / kBandRows : 0;
+    int64_t slab0 = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        const void* kern = pass == 0 ? full : part;
+        const int64_t cnt = pass == 0 ? nfull : nslab - nfull;
+        if (cnt <= 0) continue;
+        hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        void* args[] = {const_cast<BlockProjectArgs*>(&a), &slab0};
+        e = hipLaunchKernel(kern, dim3((unsigned)cnt), dim3(kThreads), args, lds, s);
+        if (e != hipSuccess) return e;
+        slab0 += cnt;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_band(const BlockProjectArgs& a, hipStream_t s, bool pack) {
     if (!a.cfrag || !a.desc) return hipErrorInvalidValue;
+    // the 16 x 16 form wherever one of its instances applies (the pack and
+    // the projection of a block take the same decision from the same sizes)
+    if (const int S4 = band16_fixed_steps(a.m, a.r, a.k)) return launch_band16(a, s, pack, S4);
     const int ntile = band_tiles(a.r, a.k);
     if (pack) {
         hipLaunchKernelGGL(k_pack_band, dim3((unsigned)ntile, (unsigned)band_chunks(a.m, a.r)), dim3(64), 0, s, a);
