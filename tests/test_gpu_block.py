@@ -339,3 +339,18 @@ def test_block_fp32_pairs_rank_deficient(projection_form):
                 assert np.all(phis[w][10:] == sentinel)
                 checked += 1
         assert checked == 3 * kb
+
+
+@pytest.mark.parametrize("H,W,m,r,kb", [(61, 83, 16, 8, 12), (90, 70, 48, 16, 16), (40, 50, 16, 4, 9)])
+def test_block_fp32_banded_16x16_instances(H, W, m, r, kb):
+    """The FP32 block projection's 16 x 16 x 4 banded kernel at the step
+    counts the full-HD test does not take (4-column steps per tile: 5 at
+    m = 16, 13 at m = 48; r = 4 puts up to five windows in a 32-column tile):
+    every window of every block against the oracle, ragged row count."""
+    dmd = _dmd()
+    n = H * W
+    blocks = [kb, kb, 5, kb, 1, kb]
+    frames = gen.BlobVideo(height=H, width=W, blob_sigma=4.0).frames(0, sum(blocks))
+    X = torch.from_numpy(frames.T.copy()).cuda()
+    with dmd.Stream(n, m, r, max_block=kb) as s:
+        run_blocks(s, X, frames, blocks, m, r, phi_tol=2e-4)
