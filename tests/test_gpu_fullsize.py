@@ -146,6 +146,46 @@ def test_batch_slab_forms_ragged(monkeypatch, iter_):
         s.close()
 
 
+
+def test_batch_at_serving_mix_extremes():
+    """A batch tick at the ends of the serving mix's size range (n = 2,097,152
+    and 65,536, with a ragged 1,048,579 between) in the slab forms the default
+    launch shapes pick at those sizes: every member equals the same stream
+    alone bit for bit, its Gram the oracle's, and the largest member's last
+    window the oracle's exact DMD."""
+    dmd = _dmd()
+    specs = [(2_097_152, 16, 8), (65_536, 32, 16), (1_048_579, 16, 8)]
+    gens = [gen.MixStream(stream=400 + i, n=n, m=0, r=0, kind="video") for i, (n, m, r) in enumerate(specs)]
+    T = max(m for _, m, _ in specs) + 3
+    frames = [np.stack([g.frame(t) for t in range(T)], axis=1) for g in gens]
+    dev = [torch.from_numpy(F.T.copy()).cuda() for F in frames]
+    alone = []
+    for (n, m, r), X in zip(specs, dev):
+        with dmd.Stream(n, m, r) as s:
+            for t in range(T):
+                s.push(X[t])
+            lam, sig, _ = s.eigs()
+            alone.append((s.gram(), lam, sig))
+    streams = [dmd.Stream(n, m, r) for (n, m, r) in specs]
+    with dmd.Batch(max_streams=4) as batch:
+        for s in streams:
+            batch.attach(s)
+        for t in range(T):
+            batch.tick(streams, [X[t] for X in dev])
+        torch.cuda.synchronize()
+        for i, s in enumerate(streams):
+            n, m, r = specs[i]
+            lam, sig, _ = s.eigs()
+            assert np.array_equal(s.gram(), alone[i][0]), i
+            assert np.array_equal(lam, alone[i][1]) and np.array_equal(sig, alone[i][2]), i
+            check_gram(s, frames[i][:, T - m - 1:])
+        n, m, r = specs[0]
+        check_window(streams[0], frames[0][:, T - m - 1:], m, r, phi_tol=2e-4)
+        for s in streams:
+            batch.detach(s)
+    for s in streams:
+        s.close()
+
 # ---------------------------------------------------------------- 1920 x 1080 video
 
 def test_full_hd_video_single_pushes():
